@@ -1,0 +1,227 @@
+/*
+ * og.h — C ABI of the MI355X short-range TreePM tree force.
+ *
+ * The library builds an octree over particles in a (periodic) box and
+ * evaluates, per target particle, the short-range part of the TreePM
+ * gravitational force with a Barnes-Hut walk.  The operations follow the
+ * paper's "Gravity Solver" section:
+ *   - tree construction ("Tree construction": root cube covering the domain,
+ *     recursive 8-way subdivision, particles in space-filling-curve order,
+ *     bottom-up pass for node mass and centre of mass, two-pointer
+ *     first-child/sibling traversal order);
+ *   - tree walk ("Tree walk": one walk per target from the root, Barnes-Hut
+ *     opening criterion plus a boundary check, accepted nodes act as a point
+ *     mass at their centre of mass, the sibling pointer skips the subtree);
+ *   - force evaluation ("Force evaluation" and "Particle Mesh": the tree
+ *     carries the short-range term of the split 1/r = erfc(r/2A)/r +
+ *     erf(r/2A)/r, A = r_s).
+ * Where the paper leaves a choice open this library uses: Plummer softening
+ * (r^2+eps^2)^(-3/2); 63-bit Morton keys; a cutoff r < r_cut with the
+ * periodic minimum image; a node is skipped when on some axis its cube lies
+ * farther than r_cut from the target; open iff side^2 > theta^2 |COM-x|^2 or
+ * the target lies inside the node cube enlarged 1.2x; leaves hold up to
+ * leaf_max particles.  Per target, acceleration
+ *   a_i = sum_j G m_j d_ij (r^2+eps^2)^(-3/2) [erfc(u) + 2u/sqrt(pi) e^(-u^2)]
+ *   phi_i = -sum_j G m_j erfc(u) / sqrt(r^2+eps^2),   u = r/(2 r_s),
+ * summed over the particles and accepted nodes of the walk.
+ *
+ * Conventions for every call:
+ *   - return value: OG_OK (0) or a negative OG_E* code; output handles are
+ *     written only on success; nothing aborts or throws across the ABI;
+ *     og_last_error() returns a thread-local detail string.
+ *   - every array argument is a DEVICE pointer (HIP device memory) unless
+ *     stated as host; a host pointer where a device one is required gives
+ *     OG_EINVAL.
+ *   - work is enqueued on the stream given in og_params.stream (a
+ *     hipStream_t; NULL = the default stream).  Inputs must stay valid and
+ *     unchanged until that stream has passed the call; outputs are valid
+ *     once it has.  The tree copies what it needs and keeps no caller
+ *     pointer beyond the call.
+ *   - a built tree is read-only: og_tree_force calls on it may run
+ *     concurrently on different streams; og_tree_free must not overlap any
+ *     other use of the tree.
+ */
+#ifndef OG_H
+#define OG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    OG_OK = 0,
+    OG_EINVAL = -1,       /* invalid argument */
+    OG_ERANGE = -2,       /* a position outside [0,box) (periodic) or not finite */
+    OG_ENOMEM = -3,       /* device allocation failed or workspace too small */
+    OG_EDEVICE = -4,      /* a HIP runtime error */
+    OG_EBUSY = -5,        /* server: over budget and queue full */
+    OG_EUNSUPPORTED = -6, /* valid request this build does not handle */
+    OG_ENOTFOUND = -7     /* server: unknown ticket */
+};
+
+/* Arithmetic of the walk.  FP64: every step in double precision.  MIXED:
+ * positions are turned into node-relative offsets in FP64 (at build time
+ * for particles and node centres of mass, per target at walk start); the
+ * opening tests and the interactions then run in FP32 on those offsets and
+ * every contribution is accumulated per target in FP64. */
+enum { OG_PREC_FP64 = 0, OG_PREC_MIXED = 1 };
+
+typedef struct og_params {
+    uint32_t struct_size;   /* = sizeof(og_params) (ABI check) */
+    double G;               /* gravitational constant (default 1) */
+    double eps;             /* Plummer softening length, >= 0 */
+    double r_s;             /* split scale A_smth; <= 0: plain Newtonian force,
+                               no cutoff (then periodic must be 0) */
+    double r_cut;           /* cutoff radius; 0 => 4.5 r_s; periodic: < box/2 */
+    double theta;           /* opening angle, >= 0 (0 opens every node) */
+    int32_t periodic;       /* 1: positions in [0,box)^3 with minimum image;
+                               0: open boundaries, root = bounding cube */
+    int32_t leaf_max;       /* max particles per leaf (default 8), 1..4096;
+                               the result depends on it */
+    int32_t precision;      /* OG_PREC_FP64 or OG_PREC_MIXED (default MIXED) */
+    int32_t group_max;      /* targets per wavefront group, 1..64, 0 = 64;
+                               the result does not depend on it */
+    void *stream;           /* hipStream_t, NULL = default stream */
+    void *workspace;        /* optional caller device buffer for the tree */
+    size_t workspace_bytes; /* its size; must be >= og_tree_workspace_bound */
+} og_params;
+
+/* Defaults: G 1, eps 0, r_s 0, r_cut 0, theta 0.5, periodic 1, leaf_max 8,
+ * MIXED, group_max 0, no stream, no workspace. */
+void og_params_default(og_params *p);
+
+/* Device bytes one tree over N particles needs (upper bound, independent of
+ * the particle distribution); 0 for invalid arguments.  Used for HBM
+ * admission before the build. */
+size_t og_tree_workspace_bound(int64_t N, const og_params *p);
+
+typedef struct og_tree og_tree;
+
+/* Build the octree (keys, sort, topology, moments) of N particles.
+ *   pos:  device, [N][3] FP64, row-major, caller order
+ *   mass: device, [N] FP64, > 0
+ *   box:  periodic box side (> 0); with periodic = 0 it is not used
+ * Enqueued on params->stream; returns without waiting for the device.  A
+ * periodic coordinate outside [0,box) (or a non-finite one) is found on the
+ * device: the tree is then marked and og_tree_status reports OG_ERANGE;
+ * the keys of such particles are clamped so that every kernel stays in
+ * bounds.  Errors: OG_EINVAL (N < 1 or > 2^27-1, box <= 0, eps < 0,
+ * theta < 0, leaf_max outside 1..4096, group_max outside 0..64, periodic
+ * with r_s <= 0 or r_cut >= box/2, null pointers, host pointers),
+ * OG_ENOMEM, OG_EDEVICE. */
+int og_tree_build(const double *pos, const double *mass, int64_t N, double box,
+                  const og_params *params, og_tree **out);
+
+/* Targets of a force evaluation: caller-order particle indices (device,
+ * int64, each in [0,N); repeats allowed) or idx = NULL for all N particles
+ * in caller order. */
+typedef struct og_targets {
+    const int64_t *idx;
+    int64_t M;
+} og_targets;
+
+/* Short-range force on the targets, with the tree's parameters.
+ *   targets: NULL or {NULL, N} = all particles;
+ *   acc: device [M][3] FP64, pot: device [M] FP64 or NULL, in target order.
+ * Enqueued on the tree's stream. */
+int og_tree_force(const og_tree *tree, const og_targets *targets, double *acc, double *pot);
+
+typedef struct og_force_opts {
+    uint32_t struct_size;   /* = sizeof(og_force_opts) */
+    int32_t precision;      /* -1: the tree's; else OG_PREC_* */
+    void *stream;           /* NULL: the tree's stream */
+    int64_t *n_inter;       /* device [M] or NULL: per-target count of
+                               contributions that passed the cutoff */
+} og_force_opts;
+
+/* As og_tree_force, with a precision, stream and interaction counts. */
+int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_force_opts *opts,
+                     double *acc, double *pot);
+
+/* Synchronise the tree's stream and report the device-side status of the
+ * build: OG_OK or OG_ERANGE. */
+int og_tree_status(const og_tree *tree);
+
+/* Synchronise and report node count, deepest level and device bytes held. */
+int og_tree_stats(const og_tree *tree, int64_t *n_nodes, int32_t *depth, size_t *bytes);
+
+/* Copy the tree to HOST buffers (synchronises); any pointer may be NULL.
+ *   keys[N]   Morton keys in sorted order      perm[N]  sorted -> caller index
+ *   first, count, skip, parent [n_nodes]      level [n_nodes]
+ *   node_m_com [n_nodes][4] = (mass, com_x, com_y, com_z)
+ * Node arrays must hold og_tree_stats' n_nodes entries. */
+int og_tree_export(const og_tree *tree, uint64_t *keys, uint32_t *perm, uint32_t *first,
+                   uint32_t *count, uint8_t *level, uint32_t *skip, uint32_t *parent,
+                   double *node_m_com);
+
+/* Free the tree and its device memory (not a caller workspace).  Waits for
+ * the tree's stream first. */
+int og_tree_free(og_tree *tree);
+
+/* ---------------------------------------------------------------- batch --
+ * Many independent boxes, each with its own particles and parameters, built
+ * and walked by the same kernels in one set of launches (a box index is part
+ * of every sort key and every walk group).  Each box's result equals the
+ * result of building and walking that box alone. */
+typedef struct og_box {
+    const double *pos;   /* device [N][3] */
+    const double *mass;  /* device [N] */
+    int64_t N;
+    double box;
+    og_params params;    /* per box; stream/workspace fields ignored;
+                            precision and group_max taken from box 0 */
+    double *acc;         /* device [N][3] output, caller order */
+    double *pot;         /* device [N] output or NULL */
+} og_box;
+
+typedef struct og_batch og_batch;
+
+/* Build all B boxes' trees on `stream` (hipStream_t or NULL). */
+int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out);
+/* Walk every box's particles and write each box's acc/pot. */
+int og_batch_force(og_batch *b);
+/* Capture og_batch_build's kernels + og_batch_force for the same boxes into
+ * a HIP graph owned by the batch, and replay it: positions and masses are
+ * re-read from the same device pointers on every replay. */
+int og_batch_graph_replay(og_batch *b);
+int og_batch_status(const og_batch *b);
+int og_batch_free(og_batch *b);
+
+/* -------------------------------------------------------------- serving --
+ * Continuous batching: requests (one box each) are admitted when their
+ * tree's device footprint fits the HBM budget and a slot is free, built on
+ * their own stream as soon as admitted, and walked while other requests
+ * build or walk; a request that arrives while others are on the device is
+ * admitted as soon as memory and a slot free up.  Trees stay resident until
+ * the caller releases the ticket. */
+typedef struct og_server og_server;
+
+int og_server_create(size_t hbm_budget_bytes, int32_t max_slots, og_server **out);
+/* Submit a request; its pos/mass/acc/pot are device buffers owned by the
+ * caller and must stay valid until the ticket is released.  OG_EBUSY when
+ * the request can never fit the budget or the pending queue is full. */
+int og_server_submit(og_server *s, const og_box *req, uint64_t *ticket);
+/* Progress the server (admit, launch, retire) without blocking. */
+int og_server_progress(og_server *s);
+/* done = 1 once acc/pot are written; times in seconds on the server's
+ * monotonic clock (arrival = submit call, done = completion observed). */
+int og_server_poll(og_server *s, uint64_t ticket, int32_t *done, double *t_arrive, double *t_done);
+/* Block until the ticket is done (progressing the server meanwhile). */
+int og_server_wait(og_server *s, uint64_t ticket);
+/* Free the request's resident tree and slot. */
+int og_server_release(og_server *s, uint64_t ticket);
+/* Bytes currently reserved by admitted requests, and counts. */
+int og_server_stats(const og_server *s, size_t *reserved, int32_t *in_flight, int32_t *pending);
+int og_server_destroy(og_server *s);
+
+const char *og_strerror(int code);
+const char *og_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OG_H */

@@ -1,0 +1,848 @@
+// Tree construction kernels for CDNA4 (gfx950, wave64): root frame, Morton
+// keys, LSD radix sort, gather into sorted SoA/AoS, pre-order topology,
+// bottom-up moments and walk groups.
+//
+// Paper, "Tree construction": the root covers the domain; particles are
+// placed in space-filling-curve order; the cube hierarchy is the recursive
+// 8-way subdivision; a bottom-up pass gives node mass and centre of mass;
+// traversal uses a first-child ("nextnode") and a sibling pointer.  Here the
+// hierarchy is built without insertion: from the sorted keys every particle
+// knows at which levels it starts a node, so node ranks come from one scan.
+//
+// Compiled with -ffp-contract=off: keys and node geometry are rounded
+// exactly as written, which makes them bit-identical to any other IEEE
+// evaluation of the same expressions.
+#include "og_kernels.h"
+
+namespace og {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ inline uint32_t lane_id() { return threadIdx.x & 63; }
+
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ inline uint32_t block_exscan(uint32_t v, uint32_t *tmp4, uint32_t *total) {
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t t = __shfl_up(x, off, 64);
+    if (lane >= (uint32_t)off) x += t;
+  }
+  if (lane == 63) tmp4[w] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    uint32_t t = tmp4[i];
+    if (i < (int)w) base += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// ---------------------------------------------------------------- scan --
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *in, const uint32_t *n_dev,
+                                                          uint32_t *partial) {
+  __shared__ uint32_t tmp[kWaves];
+  const uint32_t n = *n_dev;
+  const uint32_t base = blockIdx.x * kScanTile;
+  if (base >= n) return;
+  uint32_t s = 0;
+  for (uint32_t i = threadIdx.x; i < kScanTile; i += kThreads) {
+    uint32_t e = base + i;
+    if (e < n) s += in[e];
+  }
+  uint32_t tot;
+  block_exscan(s, tmp, &tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_partials(uint32_t *partial, const uint32_t *n_dev) {
+  __shared__ uint32_t tmp[kWaves];
+  const uint32_t n = *n_dev;
+  const uint32_t nb = (n + kScanTile - 1) / kScanTile;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nb; base += kThreads) {
+    uint32_t e = base + threadIdx.x;
+    uint32_t v = e < nb ? partial[e] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_exscan(v, tmp, &tot);
+    if (e < nb) partial[e] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) partial[nb] = carry;  // grand total
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *in, uint32_t *out,
+                                                        const uint32_t *n_dev, const uint32_t *partial) {
+  __shared__ uint32_t buf[kScanTile];
+  __shared__ uint32_t tmp[kWaves];
+  const uint32_t n = *n_dev;
+  const uint32_t base = blockIdx.x * kScanTile;
+  const uint32_t nb = (n + kScanTile - 1) / kScanTile;
+  if (base > n) return;
+  if (base == n) {  // n is a multiple of the tile: this block only writes the total
+    if (threadIdx.x == 0) out[n] = partial[nb];
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < kScanTile; i += kThreads) {
+    uint32_t e = base + i;
+    buf[i] = e < n ? in[e] : 0u;
+  }
+  __syncthreads();
+  constexpr uint32_t per = kScanTile / kThreads;  // 16 consecutive values per thread
+  uint32_t loc[per];
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < per; ++k) {
+    loc[k] = buf[threadIdx.x * per + k];
+    s += loc[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_exscan(s, tmp, &tot) + partial[blockIdx.x];
+#pragma unroll
+  for (uint32_t k = 0; k < per; ++k) {
+    buf[threadIdx.x * per + k] = ex;
+    ex += loc[k];
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kScanTile; i += kThreads) {
+    uint32_t e = base + i;
+    if (e < n) out[e] = buf[i];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = partial[nb];
+}
+
+// --------------------------------------------------------------- frame --
+// Order-preserving map of doubles to unsigned 64-bit integers.
+__device__ inline uint64_t d2ord(double v) {
+  uint64_t u = (uint64_t)__double_as_longlong(v);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ inline double ord2d(uint64_t u) {
+  u = (u >> 63) ? (u & ~(1ull << 63)) : ~u;
+  return __longlong_as_double((long long)u);
+}
+
+__global__ __launch_bounds__(kThreads) void k_frame_init(BoxDev *boxes, int B, uint64_t *minmax) {
+  int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < 6 * B) minmax[i] = (i % 6) < 3 ? ~0ull : 0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_frame_reduce(const BoxDev *boxes, int B, uint32_t n,
+                                                           uint64_t *minmax, uint32_t *status) {
+  uint32_t g = blockIdx.x * kThreads + threadIdx.x;
+  if (g >= n) return;
+  int b = box_of(boxes, B, g);
+  const BoxDev &bx = boxes[b];
+  if (bx.periodic) return;
+  uint32_t i = g - bx.p_off;
+  const double *x = bx.pos + 3ull * i;
+  bool ok = true;
+  uint64_t o[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double v = x[k];
+    ok = ok && isfinite(v);
+    o[k] = d2ord(v);
+  }
+  if (!ok) {
+    atomicOr(status, kStatusRange);
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    atomicMin((unsigned long long *)&minmax[6 * b + k], (unsigned long long)o[k]);
+    atomicMax((unsigned long long *)&minmax[6 * b + 3 + k], (unsigned long long)o[k]);
+  }
+}
+
+__global__ void k_frame_finalize(BoxDev *boxes, int B, const uint64_t *minmax) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  BoxDev &bx = boxes[b];
+  if (bx.periodic) return;
+  double L = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double lo = ord2d(minmax[6 * b + k]);
+    double hi = ord2d(minmax[6 * b + 3 + k]);
+    if (minmax[6 * b + k] == ~0ull) { lo = 0.0; hi = 0.0; }  // no finite point
+    double e = hi - lo;
+    if (e > L) L = e;
+    bx.lo[k] = lo;
+  }
+  if (!(L > 0.0)) L = 1.0;
+  bx.L = L;
+  bx.scale = 2097152.0 / L;
+  bx.Lf = (float)L;
+  bx.h22f = (float)(L * 0x1p-22);
+}
+
+// ---------------------------------------------------------------- keys --
+__device__ inline uint32_t cell_of(double x, double lo, double scale, bool &bad) {
+  double v = (x - lo) * scale;
+  if (!(v >= 0.0)) {  // below the root cube or NaN
+    bad = true;
+    return 0u;
+  }
+  if (v >= 2097151.0) return 2097151u;
+  return (uint32_t)v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_keys(const BoxDev *boxes, int B, uint32_t n,
+                                                   uint64_t *keys, uint32_t *vals, uint32_t *status) {
+  uint32_t g = blockIdx.x * kThreads + threadIdx.x;
+  if (g >= n) return;
+  const BoxDev &bx = boxes[box_of(boxes, B, g)];
+  uint32_t i = g - bx.p_off;
+  const double *x = bx.pos + 3ull * i;
+  bool bad = false;
+  uint32_t c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double v = x[k];
+    if (bx.periodic && !(v < bx.box)) bad = true;  // v >= box or NaN
+    c[k] = cell_of(v, bx.lo[k], bx.scale, bad);
+  }
+  if (bad) atomicOr(status, kStatusRange);
+  keys[g] = morton3(c[0], c[1], c[2]);
+  vals[g] = g;
+}
+
+// ---------------------------------------------------------------- sort --
+constexpr int kSortItems = kSortTile / kThreads;  // 16 per thread
+
+__device__ inline uint32_t sort_digit(uint64_t key, uint32_t val, int pass, const BoxDev *boxes,
+                                      int B) {
+  if (pass < 8) return (uint32_t)(key >> (8 * pass)) & 255u;
+  return ((uint32_t)box_of(boxes, B, val) >> (8 * (pass - 8))) & 255u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_hist(const uint64_t *keys, const uint32_t *vals,
+                                                        uint32_t n, int pass, const BoxDev *boxes,
+                                                        int B, uint32_t *hist, uint32_t ntiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int r = 0; r < kSortItems; ++r) {
+    uint32_t e = base + r * kThreads + threadIdx.x;
+    if (e < n) atomicAdd(&h[sort_digit(keys[e], vals[e], pass, boxes, B)], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's per-tile counts.
+__global__ __launch_bounds__(kThreads) void k_sort_rowscan(uint32_t *hist, uint32_t ntiles,
+                                                           uint32_t *digit_tot) {
+  __shared__ uint32_t tmp[kWaves];
+  uint32_t *row = hist + (size_t)blockIdx.x * ntiles;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < ntiles; base += kThreads) {
+    uint32_t e = base + threadIdx.x;
+    uint32_t v = e < ntiles ? row[e] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_exscan(v, tmp, &tot);
+    if (e < ntiles) row[e] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
+}
+
+// Stable scatter of one tile.  Wave w owns tile elements
+// [w*1024, (w+1)*1024) in 16 rounds of 64; ranks among equal digits come
+// from ballot-matched peer masks, per-wave running counts, a scan over
+// waves and a scan over digits.  The tile is reordered in LDS first so that
+// the global writes of each digit run are contiguous.
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
+                                                           uint64_t *keys_out, uint32_t *vals_out,
+                                                           uint32_t n, int pass, const BoxDev *boxes,
+                                                           int B, const uint32_t *hist,
+                                                           const uint32_t *digit_tot, uint32_t ntiles) {
+  __shared__ uint64_t skeys[kSortTile];
+  __shared__ uint32_t svals[kSortTile];
+  __shared__ uint32_t wcnt[kWaves][256];
+  __shared__ uint32_t gbase[256];    // global base of each digit for this tile
+  __shared__ uint32_t tbase[256];    // base of each digit inside the tile
+  __shared__ uint32_t tmp[kWaves];
+
+  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const uint32_t base = blockIdx.x * kSortTile;
+  const uint32_t tile_n = min(kSortTile, n - base);
+
+  // digit bases over the whole array: exclusive scan of the digit totals
+  {
+    uint32_t tot;
+    uint32_t ex = block_exscan(digit_tot[tid], tmp, &tot);
+    gbase[tid] = ex + hist[tid * ntiles + blockIdx.x];
+  }
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) wcnt[k][tid] = 0;
+  __syncthreads();
+
+  uint64_t key[kSortItems];
+  uint32_t val[kSortItems];
+  uint32_t dig[kSortItems];
+  uint32_t off[kSortItems];
+  const uint32_t wbase = w * (kSortItems * 64);
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    uint32_t le = wbase + r * 64 + lane;
+    bool valid = le < tile_n;
+    key[r] = valid ? keys_in[base + le] : 0ull;
+    val[r] = valid ? vals_in[base + le] : 0u;
+    dig[r] = valid ? sort_digit(key[r], val[r], pass, boxes, B) : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    uint32_t le = wbase + r * 64 + lane;
+    bool valid = le < tile_n;
+    uint64_t peers = __ballot(valid);
+    const uint32_t d = dig[r];
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      uint64_t bb = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? bb : ~bb;
+    }
+    uint32_t leader = __ffsll((unsigned long long)peers) - 1;
+    uint32_t rank = __popcll(peers & ((1ull << lane) - 1ull));
+    uint32_t old = 0;
+    if (valid && lane == leader) {
+      old = wcnt[w][d];
+      wcnt[w][d] = old + (uint32_t)__popcll(peers);
+    }
+    old = __shfl(old, valid ? leader : lane, 64);
+    off[r] = old + rank;
+  }
+  __syncthreads();
+  // per digit: exclusive scan over waves, then over digits
+  {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      uint32_t t = wcnt[k][tid];
+      wcnt[k][tid] = acc;
+      acc += t;
+    }
+    uint32_t tot;
+    tbase[tid] = block_exscan(acc, tmp, &tot);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    uint32_t le = wbase + r * 64 + lane;
+    if (le < tile_n) {
+      uint32_t lp = tbase[dig[r]] + wcnt[w][dig[r]] + off[r];
+      skeys[lp] = key[r];
+      svals[lp] = val[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int r = 0; r < kSortItems; ++r) {
+    uint32_t e = r * kThreads + tid;
+    if (e < tile_n) {
+      uint64_t k = skeys[e];
+      uint32_t v = svals[e];
+      uint32_t d = sort_digit(k, v, pass, boxes, B);
+      uint32_t gp = gbase[d] + (e - tbase[d]);
+      keys_out[gp] = k;
+      vals_out[gp] = v;
+    }
+  }
+}
+
+// -------------------------------------------------------------- gather --
+__global__ __launch_bounds__(kThreads) void k_gather(const BoxDev *boxes, int B, uint32_t n,
+                                                     const uint32_t *vals, uint32_t *perm,
+                                                     uint32_t *inv, double4 *part64) {
+  uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  uint32_t g = vals[p];
+  const BoxDev &bx = boxes[box_of(boxes, B, g)];
+  uint32_t i = g - bx.p_off;
+  const double *x = bx.pos + 3ull * i;
+  part64[p] = make_double4(x[0], x[1], x[2], bx.mass[i]);
+  perm[p] = g;
+  inv[g] = p;
+}
+
+// ------------------------------------------------------------ topology --
+// lcp(p): levels shared by sorted keys p-1 and p inside one box; -1 at a
+// box's first particle and past its last one.
+__device__ inline int lcp_at(const uint64_t *skeys, uint32_t q, uint32_t b0, uint32_t b1) {
+  if (q <= b0 || q >= b1) return -1;
+  return shared_levels(skeys[q - 1], skeys[q]);
+}
+
+// depth(p): the level of the leaf holding p = the smallest level whose node
+// around p holds <= leaf_max particles (21 at most).  The node at level L
+// around p holds 1 + #{neighbours q within leaf_max places with
+// lcp-range-min >= L}, so depth = 1 + the leaf_max-th largest of the
+// running minima of lcp to the right and to the left (merged, both
+// sequences are non-increasing).  nstart(p) = nodes whose first particle
+// is p = levels lcp(p)+1 .. depth(p).
+__global__ __launch_bounds__(kThreads) void k_lcp_depth(const BoxDev *boxes, int B, uint32_t n,
+                                                        const uint64_t *skeys, int8_t *lcp,
+                                                        uint8_t *depth, uint32_t *nstart) {
+  uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  const BoxDev &bx = boxes[box_of(boxes, B, p)];
+  const uint32_t b0 = bx.p_off, b1 = bx.p_off + bx.n;
+  const int lm = bx.leaf_max;
+  const int own = lcp_at(skeys, p, b0, b1);
+  int ri = 1, li = 1;
+  int rv = lcp_at(skeys, p + 1, b0, b1);
+  int lv = own;
+  int v = -1;
+  for (int k = 0; k < lm; ++k) {
+    if (rv >= lv) {
+      v = rv;
+      ++ri;
+      rv = ri <= lm ? min(rv, lcp_at(skeys, p + ri, b0, b1)) : -2;
+    } else {
+      v = lv;
+      ++li;
+      lv = (li <= lm && p + 1 >= (uint32_t)li) ? min(lv, lcp_at(skeys, p + 1 - li, b0, b1)) : -2;
+    }
+  }
+  int d = min(kLevels, v + 1);
+  lcp[p] = (int8_t)own;
+  depth[p] = (uint8_t)d;
+  nstart[p] = (uint32_t)max(0, d - own);
+}
+
+// Per box: node range [S[p_off], S[p_off+n]).
+__global__ void k_box_nodes(BoxDev *boxes, int B, const uint32_t *S, uint32_t n, uint32_t node_cap,
+                            uint32_t *scalars) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) {
+    boxes[b].root = min(S[boxes[b].p_off], node_cap);
+    boxes[b].node_end = min(S[boxes[b].p_off + boxes[b].n], node_cap);
+  }
+  if (b == 0) {
+    uint32_t tot = S[n];
+    scalars[3] = min(tot, node_cap);
+    if (tot > node_cap) atomicOr(&scalars[0], kStatusNodes);
+  }
+}
+
+// End (exclusive) of the level-L node that starts at p: first q in (p, b1]
+// whose key leaves the node's prefix; exponential then binary search.
+__device__ inline uint32_t node_end(const uint64_t *skeys, uint32_t p, int L, uint32_t b1) {
+  if (L == 0) return b1;
+  const int sh = 63 - 3 * L;
+  const uint64_t pre = skeys[p] >> sh;
+  uint32_t lo = p, step = 1;  // lo: last index known inside the node
+  while (true) {
+    uint32_t q = lo + step;
+    if (q >= b1 || (skeys[q] >> sh) != pre) break;
+    lo = q;
+    step <<= 1;
+  }
+  uint32_t hi = min(lo + step, b1);  // first index known outside (or b1)
+  while (hi - lo > 1) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    if ((skeys[mid] >> sh) == pre) lo = mid; else hi = mid;
+  }
+  return hi;
+}
+
+__global__ __launch_bounds__(kThreads) void k_emit(const BoxDev *boxes, int B, uint32_t n,
+                                                   const uint64_t *skeys, const int8_t *lcp,
+                                                   const uint8_t *depth, const uint32_t *S,
+                                                   uint32_t node_cap, Topo *topo, uint32_t *first,
+                                                   uint32_t *skip) {
+  uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  const int l0 = lcp[p], d = depth[p];
+  if (d <= l0) return;
+  const BoxDev &bx = boxes[box_of(boxes, B, p)];
+  const uint32_t b1 = bx.p_off + bx.n;
+  const uint64_t key = skeys[p];
+  const uint32_t cx = compact3(key >> 2), cy = compact3(key >> 1), cz = compact3(key);
+  uint32_t rank = S[p];
+  for (int L = l0 + 1; L <= d; ++L, ++rank) {
+    if (rank >= node_cap) return;
+    const uint32_t e = node_end(skeys, p, L, b1);
+    const int drop = kLevels - L;
+    const uint64_t corner = (uint64_t)((cx >> drop) << drop) | ((uint64_t)((cy >> drop) << drop) << 21) |
+                            ((uint64_t)((cz >> drop) << drop) << 42);
+    const bool leaf = (L == d);
+    const uint32_t sk = S[e];
+    Topo t;
+    t.corner = corner | (leaf ? kLeafBit : 0ull);
+    t.a = leaf ? p : sk;
+    t.b = ((e - p) & kCountMask) | ((uint32_t)L << kCountBits);
+    topo[rank] = t;
+    first[rank] = p;
+    skip[rank] = sk;
+  }
+}
+
+// Parent links and child counts; clears the arrival counters.
+__global__ __launch_bounds__(kThreads) void k_links(const Topo *topo, const uint32_t *skip,
+                                                    const uint32_t *scalars, uint32_t node_cap,
+                                                    uint32_t *parent, uint32_t *nchild,
+                                                    uint32_t *arrive) {
+  const uint32_t tot = min(scalars[3], node_cap);
+  for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
+    arrive[r] = 0;
+    const Topo t = topo[r];
+    uint32_t nc = 0;
+    if (!(t.corner & kLeafBit)) {
+      const uint32_t end = min(t.a, tot);
+      for (uint32_t c = r + 1; c < end;) {
+        parent[c] = r;
+        ++nc;
+        const uint32_t nx = skip[c];
+        if (nx <= c) break;  // never taken for a well-formed tree
+        c = nx;
+      }
+    }
+    nchild[r] = nc;
+  }
+}
+
+// Roots of all boxes have no parent.
+__global__ void k_roots(const BoxDev *boxes, int B, uint32_t *parent) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) parent[boxes[b].root] = 0xffffffffu;
+}
+
+// Cube centre of a node in FP64: lo + (corner + 2^(20-level)) L 2^-21.
+__device__ inline void node_centre(const BoxDev &bx, uint64_t corner, int level, double c[3]) {
+  const double h = bx.L * 0x1p-21;
+  const double half = ldexp(1.0, 20 - level);
+  c[0] = bx.lo[0] + ((double)(uint32_t)(corner & 0x1fffffull) + half) * h;
+  c[1] = bx.lo[1] + ((double)(uint32_t)((corner >> 21) & 0x1fffffull) + half) * h;
+  c[2] = bx.lo[2] + ((double)(uint32_t)((corner >> 42) & 0x1fffffull) + half) * h;
+}
+
+// Bottom-up moments.  Each leaf sums its particles (relative to the cube
+// centre) and writes the particles' FP32 offsets from that centre; then it
+// climbs: the last child to arrive at a parent (acq_rel counter at agent
+// scope) sums the parent's children in child order.  Every node is summed
+// exactly once, in a fixed order, so the result is deterministic.
+__global__ __launch_bounds__(kThreads) void k_moments(const BoxDev *boxes, int B, const Topo *topo,
+                                                      const uint32_t *skip, const uint32_t *parent,
+                                                      const uint32_t *nchild, uint32_t *arrive,
+                                                      const double4 *part64, float4 *part32,
+                                                      Mom64 *mom64, Mom32 *mom32,
+                                                      const uint32_t *scalars, uint32_t node_cap) {
+  const uint32_t tot = min(scalars[3], node_cap);
+  for (uint32_t r0 = blockIdx.x * kThreads + threadIdx.x; r0 < tot; r0 += gridDim.x * kThreads) {
+    const Topo t = topo[r0];
+    if (!(t.corner & kLeafBit)) continue;
+    const uint32_t f = t.a, cnt = t.b & kCountMask;
+    const BoxDev &bx = boxes[box_of(boxes, B, f)];
+    double c[3];
+    node_centre(bx, t.corner, (int)(t.b >> kCountBits), c);
+    double M = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (uint32_t j = f; j < f + cnt; ++j) {
+      const double4 q = part64[j];
+      const double dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
+      M += q.w;
+      s0 += q.w * dx;
+      s1 += q.w * dy;
+      s2 += q.w * dz;
+      part32[j] = make_float4((float)dx, (float)dy, (float)dz, (float)q.w);
+    }
+    double com[3] = {c[0] + s0 / M, c[1] + s1 / M, c[2] + s2 / M};
+    mom64[r0] = Mom64{com[0], com[1], com[2], M};
+    mom32[r0] = Mom32{(float)(com[0] - c[0]), (float)(com[1] - c[1]), (float)(com[2] - c[2]), (float)M};
+    uint32_t r = r0;
+    while (true) {
+      const uint32_t par = parent[r];
+      if (par == 0xffffffffu) break;
+      const uint32_t old =
+          __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + 1 != nchild[par]) break;
+      const Topo tp = topo[par];
+      double cp[3];
+      node_centre(bx, tp.corner, (int)(tp.b >> kCountBits), cp);
+      double Mp = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+      const uint32_t pend = min(tp.a, tot);
+      for (uint32_t ch = par + 1; ch < pend;) {
+        const Mom64 m = mom64[ch];
+        Mp += m.m;
+        q0 += m.m * (m.cx - cp[0]);
+        q1 += m.m * (m.cy - cp[1]);
+        q2 += m.m * (m.cz - cp[2]);
+        const uint32_t nx = skip[ch];
+        if (nx <= ch) break;  // never taken for a well-formed tree
+        ch = nx;
+      }
+      const double cm[3] = {cp[0] + q0 / Mp, cp[1] + q1 / Mp, cp[2] + q2 / Mp};
+      mom64[par] = Mom64{cm[0], cm[1], cm[2], Mp};
+      mom32[par] = Mom32{(float)(cm[0] - cp[0]), (float)(cm[1] - cp[1]), (float)(cm[2] - cp[2]),
+                         (float)Mp};
+      r = par;
+    }
+  }
+}
+
+// -------------------------------------------------------------- groups --
+// Walk groups when every particle is a target: the maximal nodes holding
+// <= group_max particles (and chunks of leaves that hold more).
+__global__ __launch_bounds__(kThreads) void k_group_count(const BoxDev *boxes, int B, const Topo *topo,
+                                                          const uint32_t *parent, const uint32_t *scalars,
+                                                          uint32_t node_cap, uint32_t G, uint32_t *ng) {
+  const uint32_t tot = min(scalars[3], node_cap);
+  for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
+    const Topo t = topo[r];
+    const uint32_t cnt = t.b & kCountMask;
+    const uint32_t par = parent[r];
+    uint32_t k = 0;
+    if (cnt <= G) {
+      if (par == 0xffffffffu || (topo[par].b & kCountMask) > G) k = 1;
+    } else if (t.corner & kLeafBit) {
+      k = (cnt + G - 1) / G;
+    }
+    ng[r] = k;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_emit(const BoxDev *boxes, int B, const Topo *topo,
+                                                         const uint32_t *first, const uint32_t *ng,
+                                                         const uint32_t *goff, const uint32_t *scalars,
+                                                         uint32_t node_cap, uint32_t G, Group *groups,
+                                                         uint32_t *n_groups) {
+  const uint32_t tot = min(scalars[3], node_cap);
+  const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
+  if (gid == 0) *n_groups = goff[tot];
+  for (uint32_t r = gid; r < tot; r += gridDim.x * kThreads) {
+    const uint32_t k = ng[r];
+    if (k == 0) continue;
+    const uint32_t cnt = topo[r].b & kCountMask, f = first[r];
+    const uint32_t b = (uint32_t)box_of(boxes, B, f);
+    const uint32_t o = goff[r];
+    for (uint32_t c = 0; c < k; ++c) {
+      Group gr;
+      gr.node = r;
+      gr.tstart = f + c * G;
+      gr.tcount = min(G, cnt - c * G);
+      gr.box = b;
+      groups[o + c] = gr;
+    }
+  }
+}
+
+// --------------------------------------------------- targets (subsets) --
+__global__ __launch_bounds__(kThreads) void k_targets_map(const BoxDev *boxes, const int64_t *idx,
+                                                          uint32_t M, const uint32_t *inv,
+                                                          uint64_t *tkey, uint32_t *tval,
+                                                          uint32_t *status) {
+  uint32_t t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= M) return;
+  int64_t i = idx[t];
+  const uint32_t n = boxes[0].n;
+  if (i < 0 || i >= (int64_t)n) {
+    atomicOr(status, kStatusRange);
+    i = 0;
+  }
+  tkey[t] = inv[(uint32_t)i];
+  tval[t] = t;
+}
+
+__device__ inline uint32_t lower_bound_u64(const uint64_t *a, uint32_t n, uint64_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_count_sub(const Topo *topo, const uint32_t *first,
+                                                              const uint32_t *parent, const uint32_t *scalars,
+                                                              uint32_t node_cap, uint32_t G,
+                                                              const uint64_t *tkey, uint32_t M,
+                                                              uint32_t *ng) {
+  const uint32_t tot = min(scalars[3], node_cap);
+  for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
+    const Topo t = topo[r];
+    const uint32_t f = first[r], cnt = t.b & kCountMask;
+    const uint32_t sel = lower_bound_u64(tkey, M, (uint64_t)f + cnt) - lower_bound_u64(tkey, M, f);
+    uint32_t k = 0;
+    if (sel > 0) {
+      const uint32_t par = parent[r];
+      if (sel <= G) {
+        if (par == 0xffffffffu) {
+          k = 1;
+        } else {
+          const uint32_t pf = first[par], pc = topo[par].b & kCountMask;
+          const uint32_t psel = lower_bound_u64(tkey, M, (uint64_t)pf + pc) - lower_bound_u64(tkey, M, pf);
+          if (psel > G) k = 1;
+        }
+      } else if (t.corner & kLeafBit) {
+        k = (sel + G - 1) / G;
+      }
+    }
+    ng[r] = k;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_emit_sub(const Topo *topo, const uint32_t *first,
+                                                             const uint32_t *ng, const uint32_t *goff,
+                                                             const uint32_t *scalars_tree,
+                                                             uint32_t node_cap, uint32_t G,
+                                                             const uint64_t *tkey, uint32_t M,
+                                                             Group *groups, uint32_t *n_groups) {
+  const uint32_t tot = min(scalars_tree[3], node_cap);
+  const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
+  if (gid == 0) *n_groups = goff[tot];
+  for (uint32_t r = gid; r < tot; r += gridDim.x * kThreads) {
+    const uint32_t k = ng[r];
+    if (k == 0) continue;
+    const uint32_t f = first[r], cnt = topo[r].b & kCountMask;
+    const uint32_t t0 = lower_bound_u64(tkey, M, f);
+    const uint32_t sel = lower_bound_u64(tkey, M, (uint64_t)f + cnt) - t0;
+    const uint32_t o = goff[r];
+    for (uint32_t c = 0; c < k; ++c) {
+      Group gr;
+      gr.node = r;
+      gr.tstart = t0 + c * G;
+      gr.tcount = min(G, sel - c * G);
+      gr.box = 0;
+      groups[o + c] = gr;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_max_level(const Topo *topo, const uint32_t *scalars,
+                                                        uint32_t node_cap, uint32_t *out) {
+  __shared__ uint32_t m;
+  if (threadIdx.x == 0) m = 0;
+  __syncthreads();
+  const uint32_t tot = min(scalars[3], node_cap);
+  uint32_t v = 0;
+  for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads)
+    v = max(v, topo[r].b >> kCountBits);
+  atomicMax(&m, v);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, m);
+}
+
+__global__ void k_reset(uint32_t *w) { *w = 0; }
+__global__ void k_set(uint32_t *w, uint32_t v) { *w = v; }
+
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+int g_cu = 0;
+
+}  // namespace
+
+int device_cu_count() {
+  if (g_cu == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+      cu = 256;
+    g_cu = cu;
+  }
+  return g_cu;
+}
+
+void launch_reset(uint32_t *word, hipStream_t s) { k_reset<<<1, 1, 0, s>>>(word); }
+
+void launch_max_level(const BuildArrays &A, uint32_t *out, hipStream_t s) {
+  k_reset<<<1, 1, 0, s>>>(out);
+  const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kThreads), 1024));
+  k_max_level<<<g, kThreads, 0, s>>>(A.topo, A.scalars, A.node_cap, out);
+}
+
+void scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t cap,
+              uint32_t *partial, hipStream_t s) {
+  const uint32_t nb = cdiv((uint64_t)cap + 1, kScanTile);
+  k_scan_reduce<<<nb, kThreads, 0, s>>>(in, n_dev, partial);
+  k_scan_partials<<<1, kThreads, 0, s>>>(partial, n_dev);
+  k_scan_down<<<nb, kThreads, 0, s>>>(in, out, n_dev, partial);
+}
+
+size_t radix_hist_words(uint32_t n) { return (size_t)256 * cdiv(n > 0 ? n : 1, kSortTile); }
+
+bool radix_sort(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *vals_b, uint32_t n,
+                int pass_lo, int pass_hi, int box_passes, const BoxDev *boxes, int B,
+                uint32_t *hist, uint32_t *digit_tot, hipStream_t s) {
+  const uint32_t ntiles = cdiv(n, kSortTile);
+  uint64_t *ki = keys_a, *ko = keys_b;
+  uint32_t *vi = vals_a, *vo = vals_b;
+  bool in_b = false;
+  for (int pass = pass_lo; pass < pass_hi + box_passes; ++pass) {
+    const int pp = pass < pass_hi ? pass : 8 + (pass - pass_hi);
+    k_sort_hist<<<ntiles, kThreads, 0, s>>>(ki, vi, n, pp, boxes, B, hist, ntiles);
+    k_sort_rowscan<<<256, kThreads, 0, s>>>(hist, ntiles, digit_tot);
+    k_sort_scatter<<<ntiles, kThreads, 0, s>>>(ki, vi, ko, vo, n, pp, boxes, B, hist, digit_tot, ntiles);
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+    in_b = !in_b;
+  }
+  return in_b;
+}
+
+void launch_build(BuildArrays &A, hipStream_t s) {
+  const uint32_t n = A.n;
+  const uint32_t nb = cdiv(n, kThreads);
+  k_reset<<<1, 1, 0, s>>>(&A.scalars[0]);
+  k_set<<<1, 1, 0, s>>>(&A.scalars[4], n);
+  if (A.any_open) {
+    k_frame_init<<<cdiv(6 * (uint64_t)A.B, kThreads), kThreads, 0, s>>>(A.boxes, A.B, A.minmax);
+    k_frame_reduce<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.minmax, &A.scalars[0]);
+    k_frame_finalize<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.minmax);
+  }
+  // Start in the buffer pair that makes the sorted result land in *_a.
+  const int box_passes = A.B <= 1 ? 0 : (A.B <= 256 ? 1 : 2);
+  const bool odd = ((8 + box_passes) & 1) != 0;
+  uint64_t *k0 = odd ? A.keys_b : A.keys_a, *k1 = odd ? A.keys_a : A.keys_b;
+  uint32_t *v0 = odd ? A.vals_b : A.vals_a, *v1 = odd ? A.vals_a : A.vals_b;
+  k_keys<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, k0, v0, &A.scalars[0]);
+  radix_sort(k0, v0, k1, v1, n, 0, 8, box_passes, A.boxes, A.B, A.hist, A.digit_tot, s);
+  const uint64_t *skeys = A.keys_a;
+  k_gather<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.vals_a, A.perm, A.inv, A.part64);
+  k_lcp_depth<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.nstart);
+  scan_u32(A.nstart, A.S, &A.scalars[4], n, A.scan_partial, s);
+  k_box_nodes<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.S, n, A.node_cap, A.scalars);
+  k_emit<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.S, A.node_cap, A.topo,
+                                 A.first, A.skip);
+  const uint32_t gnodes = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kThreads), 8192));
+  k_links<<<gnodes, kThreads, 0, s>>>(A.topo, A.skip, A.scalars, A.node_cap, A.parent, A.nchild, A.arrive);
+  k_roots<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.parent);
+  k_moments<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.skip, A.parent, A.nchild, A.arrive,
+                                        A.part64, A.part32, A.mom64, A.mom32, A.scalars, A.node_cap);
+  k_group_count<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.parent, A.scalars, A.node_cap,
+                                            A.group_max, A.ng);
+  scan_u32(A.ng, A.goff, &A.scalars[3], A.node_cap, A.scan_partial, s);
+  k_group_emit<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.first, A.ng, A.goff, A.scalars,
+                                           A.node_cap, A.group_max, A.groups, &A.scalars[1]);
+}
+
+void launch_targets(const BuildArrays &A, TargetArrays &T, hipStream_t s) {
+  const uint32_t M = T.M;
+  k_reset<<<1, 1, 0, s>>>(&T.scalars[0]);
+  k_targets_map<<<cdiv(M, kThreads), kThreads, 0, s>>>(A.boxes, T.idx, M, A.inv, T.tkey_a, T.tval_a,
+                                                      &T.scalars[0]);
+  int passes = 1;
+  while (passes < 4 && (A.n >> (8 * passes)) != 0) ++passes;
+  bool in_b = radix_sort(T.tkey_a, T.tval_a, T.tkey_b, T.tval_b, M, 0, passes, 0, A.boxes, 1, T.hist,
+                         T.digit_tot, s);
+  T.tkey = in_b ? T.tkey_b : T.tkey_a;
+  T.tval = in_b ? T.tval_b : T.tval_a;
+  const uint32_t gnodes = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kThreads), 8192));
+  k_group_count_sub<<<gnodes, kThreads, 0, s>>>(A.topo, A.first, A.parent, A.scalars, A.node_cap,
+                                                A.group_max, T.tkey, M, T.ng);
+  scan_u32(T.ng, T.goff, &A.scalars[3], A.node_cap, T.scan_partial, s);
+  k_group_emit_sub<<<gnodes, kThreads, 0, s>>>(A.topo, A.first, T.ng, T.goff, A.scalars, A.node_cap,
+                                               A.group_max, T.tkey, M, T.groups, &T.scalars[1]);
+}
+
+}  // namespace og

@@ -1,0 +1,608 @@
+// C ABI of the tree force library: argument checks, device memory layout,
+// tree/batch objects and stream-ordered launches.  No torch types; every
+// array is a raw device pointer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/og.h"
+#include "og_forest.h"
+
+using namespace og;
+
+// ------------------------------------------------------------ errors --
+namespace og {
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  (void)hipGetLastError();
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(OG_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(OG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// ---------------------------------------------------------- layout --
+namespace {
+struct Carver {
+  size_t off = 0;
+  char *base = nullptr;
+  template <class T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += sizeof(T) * (count ? count : 1);
+    return p;
+  }
+};
+
+void carve(Carver &c, BuildArrays &A, uint32_t n, uint32_t node_cap, int B) {
+  A.boxes = c.take<BoxDev>(B);
+  A.minmax = c.take<uint64_t>(6ull * B);
+  A.keys_a = c.take<uint64_t>(n);
+  A.keys_b = c.take<uint64_t>(n);
+  A.vals_a = c.take<uint32_t>(n);
+  A.vals_b = c.take<uint32_t>(n);
+  A.hist = c.take<uint32_t>(radix_hist_words(n));
+  A.digit_tot = c.take<uint32_t>(256);
+  A.perm = c.take<uint32_t>(n);
+  A.inv = c.take<uint32_t>(n);
+  A.part64 = c.take<double4>(n);
+  A.part32 = c.take<float4>(n);
+  A.lcp = c.take<int8_t>(n);
+  A.depth = c.take<uint8_t>(n);
+  A.nstart = c.take<uint32_t>(n);
+  A.S = c.take<uint32_t>(n + 1ull);
+  A.scan_partial = c.take<uint32_t>(std::max<size_t>(n, node_cap) / kScanTile + 4);
+  A.topo = c.take<Topo>(node_cap);
+  A.mom64 = c.take<Mom64>(node_cap);
+  A.mom32 = c.take<Mom32>(node_cap);
+  A.first = c.take<uint32_t>(node_cap);
+  A.skip = c.take<uint32_t>(node_cap);
+  A.parent = c.take<uint32_t>(node_cap);
+  A.nchild = c.take<uint32_t>(node_cap);
+  A.arrive = c.take<uint32_t>(node_cap);
+  A.ng = c.take<uint32_t>(node_cap);
+  A.goff = c.take<uint32_t>(node_cap + 1ull);
+  A.groups = c.take<Group>(n);
+  A.scalars = c.take<uint32_t>(16);
+}
+}  // namespace
+
+uint64_t node_bound(uint64_t n, int leaf_max) { return n + 21ull * (n / (uint64_t)(leaf_max + 1)) + 1ull; }
+
+size_t forest_bytes(uint32_t n, uint32_t node_cap, int B) {
+  Carver c;
+  BuildArrays A{};
+  carve(c, A, n, node_cap, B);
+  return c.off + 256;
+}
+
+// --------------------------------------------------------- params --
+int check_params(const og_params *p, int64_t N, double box, bool need_stream_fields) {
+  (void)need_stream_fields;
+  if (!p) return fail(OG_EINVAL, "params is NULL");
+  if (p->struct_size != sizeof(og_params))
+    return fail(OG_EINVAL, "og_params.struct_size = %u, expected %zu", p->struct_size, sizeof(og_params));
+  if (N < 1 || N > (int64_t)kCountMask) return fail(OG_EINVAL, "N = %lld outside [1, 2^27-1]", (long long)N);
+  if (!(box > 0.0) || !std::isfinite(box)) return fail(OG_EINVAL, "box must be > 0");
+  if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return fail(OG_EINVAL, "eps must be >= 0");
+  if (!(p->theta >= 0.0) || !std::isfinite(p->theta)) return fail(OG_EINVAL, "theta must be >= 0");
+  if (!std::isfinite(p->G)) return fail(OG_EINVAL, "G must be finite");
+  if (p->leaf_max < 1 || p->leaf_max > 4096) return fail(OG_EINVAL, "leaf_max outside 1..4096");
+  if (p->group_max < 0 || p->group_max > 64) return fail(OG_EINVAL, "group_max outside 0..64");
+  if (p->precision != OG_PREC_FP64 && p->precision != OG_PREC_MIXED)
+    return fail(OG_EINVAL, "unknown precision %d", p->precision);
+  if (!std::isfinite(p->r_s) || !std::isfinite(p->r_cut) || p->r_cut < 0.0)
+    return fail(OG_EINVAL, "r_s / r_cut invalid");
+  const double rcut = p->r_cut > 0.0 ? p->r_cut : 4.5 * p->r_s;
+  if (p->periodic) {
+    if (!(p->r_s > 0.0)) return fail(OG_EINVAL, "periodic boxes need r_s > 0 (short-range force)");
+    if (!(rcut < 0.5 * box)) return fail(OG_EINVAL, "r_cut must be < box/2 in a periodic box");
+  } else if (p->r_s > 0.0 && !(rcut > 0.0)) {
+    return fail(OG_EINVAL, "r_cut must be > 0");
+  }
+  return OG_OK;
+}
+
+void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, double box, const og_params &p,
+              uint32_t p_off) {
+  std::memset(&b, 0, sizeof(b));
+  b.pos = pos;
+  b.mass = mass;
+  b.box = box;
+  b.periodic = p.periodic ? 1 : 0;
+  b.cutoff = p.r_s > 0.0 ? 1 : 0;
+  b.leaf_max = p.leaf_max;
+  b.p_off = p_off;
+  b.n = (uint32_t)N;
+  b.G = p.G;
+  b.eps2 = p.eps * p.eps;
+  b.r_s = p.r_s;
+  b.rcut = p.r_cut > 0.0 ? p.r_cut : 4.5 * p.r_s;
+  b.rc2 = b.rcut * b.rcut;
+  b.theta2 = p.theta * p.theta;
+  b.Gf = (float)p.G;
+  b.eps2f = (float)b.eps2;
+  b.inv2rsf = b.cutoff ? (float)(1.0 / (2.0 * p.r_s)) : 0.0f;
+  b.rcutf = (float)b.rcut;
+  b.rc2f = (float)b.rc2;
+  b.theta2f = (float)b.theta2;
+  if (b.periodic) {
+    b.lo[0] = b.lo[1] = b.lo[2] = 0.0;
+    b.L = box;
+  } else {  // set on the device from the bounding cube
+    b.L = 1.0;
+  }
+  b.scale = 2097152.0 / b.L;
+  b.Lf = (float)b.L;
+  b.h22f = (float)(b.L * 0x1p-22);
+}
+
+// --------------------------------------------------------- forest --
+int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream_t s, int prec, int gmax,
+                 void *workspace, size_t ws_bytes) {
+  B = (int)boxes.size();
+  uint64_t ntot = 0;
+  for (auto &b : boxes) ntot += b.n;
+  if (ntot > kCountMask) return fail(OG_EINVAL, "total particle count %llu exceeds 2^27-1", (unsigned long long)ntot);
+  if (node_cap_ > 0xfffffff0ull) return fail(OG_EINVAL, "node bound too large");
+  N = (uint32_t)ntot;
+  node_cap = (uint32_t)node_cap_;
+  stream = s;
+  precision = prec;
+  group_max = gmax > 0 ? (uint32_t)gmax : 64u;
+  hboxes = boxes;
+  bytes = forest_bytes(N, node_cap, B);
+  if (workspace) {
+    if (!is_device_ptr(workspace)) return fail(OG_EINVAL, "workspace is not device memory");
+    if (ws_bytes < bytes) return fail(OG_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, bytes);
+    mem = workspace;
+    own = false;
+  } else {
+    hipError_t e = hipMalloc(&mem, bytes);
+    if (e != hipSuccess) {
+      mem = nullptr;
+      return hip_fail(e, "hipMalloc(tree)");
+    }
+    own = true;
+  }
+  Carver c;
+  c.base = static_cast<char *>(mem);
+  carve(c, A, N, node_cap, B);
+  A.B = B;
+  A.n = N;
+  A.node_cap = node_cap;
+  A.group_max = group_max;
+  A.any_open = 0;
+  for (auto &b : hboxes) A.any_open |= b.periodic ? 0 : 1;
+  hipError_t e = hipMemcpyAsync(A.boxes, hboxes.data(), sizeof(BoxDev) * B, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(boxes)");
+  return OG_OK;
+}
+
+int Forest::build() {
+  launch_build(A, stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "build launch");
+  return OG_OK;
+}
+
+int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint) {
+  WalkArgs W{};
+  W.boxes = A.boxes;
+  W.topo = A.topo;
+  W.mom32 = A.mom32;
+  W.mom64 = A.mom64;
+  W.part32 = A.part32;
+  W.part64 = A.part64;
+  W.perm = A.perm;
+  W.groups = A.groups;
+  W.n_groups = &A.scalars[1];
+  W.counter = &A.scalars[2];
+  W.acc = acc;
+  W.pot = pot;
+  W.pot_override = pot_override;
+  W.nint = nint;
+  launch_walk(W, prec, N, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "walk launch");
+  return OG_OK;
+}
+
+int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
+                        int64_t *nint) {
+  Carver c;
+  TargetArrays T{};
+  auto plan = [&](Carver &cv) {
+    T.tkey_a = cv.take<uint64_t>(M);
+    T.tkey_b = cv.take<uint64_t>(M);
+    T.tval_a = cv.take<uint32_t>(M);
+    T.tval_b = cv.take<uint32_t>(M);
+    T.hist = cv.take<uint32_t>(radix_hist_words(M));
+    T.digit_tot = cv.take<uint32_t>(256);
+    T.ng = cv.take<uint32_t>(node_cap);
+    T.goff = cv.take<uint32_t>(node_cap + 1ull);
+    T.scan_partial = cv.take<uint32_t>(node_cap / kScanTile + 4);
+    T.groups = cv.take<Group>(M);
+    T.scalars = cv.take<uint32_t>(16);
+  };
+  plan(c);
+  void *tmp = nullptr;
+  hipError_t e = hipMallocAsync(&tmp, c.off + 256, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(targets)");
+  Carver c2;
+  c2.base = static_cast<char *>(tmp);
+  plan(c2);
+  T.idx = idx;
+  T.M = M;
+  launch_targets(A, T, s);
+  WalkArgs W{};
+  W.boxes = A.boxes;
+  W.topo = A.topo;
+  W.mom32 = A.mom32;
+  W.mom64 = A.mom64;
+  W.part32 = A.part32;
+  W.part64 = A.part64;
+  W.perm = A.perm;
+  W.groups = T.groups;
+  W.n_groups = &T.scalars[1];
+  W.counter = &T.scalars[2];
+  W.tkey = T.tkey;
+  W.tval = T.tval;
+  W.acc = acc;
+  W.pot = pot;
+  W.pot_override = 1;
+  W.nint = nint;
+  launch_walk(W, prec, M, s);
+  e = hipGetLastError();
+  hipError_t e2 = hipFreeAsync(tmp, s);
+  if (e != hipSuccess) return hip_fail(e, "walk launch (targets)");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync(targets)");
+  return OG_OK;
+}
+
+int Forest::read_status(hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  uint32_t st = 0;
+  e = hipMemcpy(&st, &A.scalars[0], sizeof(st), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status)");
+  if (st & kStatusRange) return fail(OG_ERANGE, "a position lies outside [0, box) or is not finite");
+  if (st & kStatusNodes) return fail(OG_EDEVICE, "node bound exceeded");
+  return OG_OK;
+}
+
+void Forest::release() {
+  if (gexec) {
+    hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+  if (own_stream) {
+    hipStreamDestroy(own_stream);
+    own_stream = nullptr;
+  }
+  if (mem && own) hipFree(mem);
+  mem = nullptr;
+}
+
+}  // namespace og
+
+// ================================================================= ABI ==
+struct og_tree {
+  Forest F;
+};
+struct og_batch {
+  Forest F;
+  std::vector<og_box> boxes;
+};
+
+extern "C" {
+
+void og_params_default(og_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(og_params);
+  p->G = 1.0;
+  p->theta = 0.5;
+  p->periodic = 1;
+  p->leaf_max = 8;
+  p->precision = OG_PREC_MIXED;
+}
+
+size_t og_tree_workspace_bound(int64_t N, const og_params *p) {
+  if (!p || p->struct_size != sizeof(og_params) || N < 1 || N > (int64_t)kCountMask || p->leaf_max < 1 ||
+      p->leaf_max > 4096)
+    return 0;
+  return forest_bytes((uint32_t)N, (uint32_t)node_bound((uint64_t)N, p->leaf_max), 1);
+}
+
+int og_tree_build(const double *pos, const double *mass, int64_t N, double box, const og_params *params,
+                  og_tree **out) {
+  if (!out) return fail(OG_EINVAL, "out is NULL");
+  int rc = check_params(params, N, box, true);
+  if (rc) return rc;
+  if (!is_device_ptr(pos) || !is_device_ptr(mass)) return fail(OG_EINVAL, "pos/mass must be device pointers");
+  og_tree *t = new (std::nothrow) og_tree();
+  if (!t) return fail(OG_ENOMEM, "host allocation");
+  std::vector<BoxDev> boxes(1);
+  fill_box(boxes[0], pos, mass, N, box, *params, 0);
+  rc = t->F.init(boxes, node_bound((uint64_t)N, params->leaf_max), (hipStream_t)params->stream,
+                 params->precision, params->group_max, params->workspace, params->workspace_bytes);
+  if (rc == OG_OK) rc = t->F.build();
+  if (rc != OG_OK) {
+    t->F.release();
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return OG_OK;
+}
+
+int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_force_opts *opts, double *acc,
+                     double *pot) {
+  if (!tree) return fail(OG_EINVAL, "tree is NULL");
+  og_tree *t = const_cast<og_tree *>(tree);
+  Forest &F = t->F;
+  int prec = F.precision;
+  hipStream_t s = F.stream;
+  int64_t *nint = nullptr;
+  if (opts) {
+    if (opts->struct_size != sizeof(og_force_opts)) return fail(OG_EINVAL, "og_force_opts.struct_size mismatch");
+    if (opts->precision >= 0) {
+      if (opts->precision != OG_PREC_FP64 && opts->precision != OG_PREC_MIXED)
+        return fail(OG_EINVAL, "unknown precision %d", opts->precision);
+      prec = opts->precision;
+    }
+    if (opts->stream) s = (hipStream_t)opts->stream;
+    nint = opts->n_inter;
+    if (nint && !is_device_ptr(nint)) return fail(OG_EINVAL, "n_inter must be a device pointer");
+  }
+  if (!is_device_ptr(acc)) return fail(OG_EINVAL, "acc must be a device pointer");
+  if (pot && !is_device_ptr(pot)) return fail(OG_EINVAL, "pot must be a device pointer");
+  if (s != F.stream) {
+    // order after the build on the tree's stream
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    hipEventRecord(ev, F.stream);
+    hipStreamWaitEvent(s, ev, 0);
+    hipEventDestroy(ev);
+  }
+  if (!targets || !targets->idx) {
+    if (targets && targets->M != (int64_t)F.N)
+      return fail(OG_EINVAL, "targets->idx NULL requires M == N");
+    return F.walk_all(prec, s, acc, pot, 1, nint);
+  }
+  if (targets->M < 1 || targets->M > (int64_t)kCountMask) return fail(OG_EINVAL, "targets->M out of range");
+  if (!is_device_ptr(targets->idx)) return fail(OG_EINVAL, "targets->idx must be a device pointer");
+  return F.walk_subset(prec, s, targets->idx, (uint32_t)targets->M, acc, pot, nint);
+}
+
+int og_tree_force(const og_tree *tree, const og_targets *targets, double *acc, double *pot) {
+  return og_tree_force_ex(tree, targets, nullptr, acc, pot);
+}
+
+int og_tree_status(const og_tree *tree) {
+  if (!tree) return fail(OG_EINVAL, "tree is NULL");
+  return const_cast<og_tree *>(tree)->F.read_status(tree->F.stream);
+}
+
+int og_tree_stats(const og_tree *tree, int64_t *n_nodes, int32_t *depth, size_t *bytes) {
+  if (!tree) return fail(OG_EINVAL, "tree is NULL");
+  Forest &F = const_cast<og_tree *>(tree)->F;
+  if (depth) launch_max_level(F.A, &F.A.scalars[5], F.stream);
+  hipError_t e = hipStreamSynchronize(F.stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  uint32_t sc[8];
+  e = hipMemcpy(sc, F.A.scalars, sizeof(sc), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(scalars)");
+  if (n_nodes) *n_nodes = sc[3];
+  if (depth) *depth = (int32_t)sc[5];
+  if (bytes) *bytes = F.bytes;
+  return OG_OK;
+}
+
+int og_tree_export(const og_tree *tree, uint64_t *keys, uint32_t *perm, uint32_t *first, uint32_t *count,
+                   uint8_t *level, uint32_t *skip, uint32_t *parent, double *node_m_com) {
+  if (!tree) return fail(OG_EINVAL, "tree is NULL");
+  Forest &F = const_cast<og_tree *>(tree)->F;
+  hipError_t e = hipStreamSynchronize(F.stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  uint32_t nn = 0;
+  e = hipMemcpy(&nn, &F.A.scalars[3], sizeof(nn), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  const uint32_t N = F.N;
+  auto cp = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+    if (!dst) return hipSuccess;
+    return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+  };
+  if ((e = cp(keys, F.A.keys_a, 8ull * N)) != hipSuccess) return hip_fail(e, "export keys");
+  if ((e = cp(perm, F.A.perm, 4ull * N)) != hipSuccess) return hip_fail(e, "export perm");
+  if ((e = cp(first, F.A.first, 4ull * nn)) != hipSuccess) return hip_fail(e, "export first");
+  if ((e = cp(skip, F.A.skip, 4ull * nn)) != hipSuccess) return hip_fail(e, "export skip");
+  if ((e = cp(parent, F.A.parent, 4ull * nn)) != hipSuccess) return hip_fail(e, "export parent");
+  if (count || level) {
+    std::vector<Topo> tp(nn);
+    if ((e = cp(tp.data(), F.A.topo, sizeof(Topo) * nn)) != hipSuccess) return hip_fail(e, "export topo");
+    for (uint32_t r = 0; r < nn; ++r) {
+      if (count) count[r] = tp[r].b & kCountMask;
+      if (level) level[r] = (uint8_t)(tp[r].b >> kCountBits);
+    }
+  }
+  if (node_m_com) {
+    std::vector<Mom64> m(nn);
+    if ((e = cp(m.data(), F.A.mom64, sizeof(Mom64) * nn)) != hipSuccess) return hip_fail(e, "export moments");
+    for (uint32_t r = 0; r < nn; ++r) {
+      node_m_com[4ull * r] = m[r].m;
+      node_m_com[4ull * r + 1] = m[r].cx;
+      node_m_com[4ull * r + 2] = m[r].cy;
+      node_m_com[4ull * r + 3] = m[r].cz;
+    }
+  }
+  return OG_OK;
+}
+
+int og_tree_free(og_tree *tree) {
+  if (!tree) return OG_OK;
+  hipStreamSynchronize(tree->F.stream);
+  tree->F.release();
+  delete tree;
+  return OG_OK;
+}
+
+// ---------------------------------------------------------------- batch --
+int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out) {
+  if (!out || !boxes) return fail(OG_EINVAL, "NULL argument");
+  if (B < 1 || B > 65536) return fail(OG_EINVAL, "B = %d outside 1..65536", B);
+  std::vector<BoxDev> hb(B);
+  uint64_t off = 0, cap = 0;
+  for (int b = 0; b < B; ++b) {
+    const og_box &x = boxes[b];
+    int rc = check_params(&x.params, x.N, x.box, false);
+    if (rc) return fail(rc, "box %d: %s", b, og_last_error());
+    if (!is_device_ptr(x.pos) || !is_device_ptr(x.mass) || !is_device_ptr(x.acc) ||
+        (x.pot && !is_device_ptr(x.pot)))
+      return fail(OG_EINVAL, "box %d: pos/mass/acc/pot must be device pointers", b);
+    if (x.params.precision != boxes[0].params.precision || x.params.group_max != boxes[0].params.group_max)
+      return fail(OG_EINVAL, "box %d: precision and group_max must match box 0", b);
+    if (off + (uint64_t)x.N > kCountMask) return fail(OG_EINVAL, "batch exceeds 2^27-1 particles");
+    fill_box(hb[b], x.pos, x.mass, x.N, x.box, x.params, (uint32_t)off);
+    hb[b].acc = x.acc;
+    hb[b].pot = x.pot;
+    off += (uint64_t)x.N;
+    cap += node_bound((uint64_t)x.N, x.params.leaf_max);
+  }
+  og_batch *bt = new (std::nothrow) og_batch();
+  if (!bt) return fail(OG_ENOMEM, "host allocation");
+  bt->boxes.assign(boxes, boxes + B);
+  int rc = bt->F.init(hb, cap, (hipStream_t)stream, boxes[0].params.precision, boxes[0].params.group_max,
+                      nullptr, 0);
+  if (rc == OG_OK) rc = bt->F.build();
+  if (rc != OG_OK) {
+    bt->F.release();
+    delete bt;
+    return rc;
+  }
+  *out = bt;
+  return OG_OK;
+}
+
+int og_batch_force(og_batch *b) {
+  if (!b) return fail(OG_EINVAL, "batch is NULL");
+  return b->F.walk_all(b->F.precision, b->F.stream, nullptr, nullptr, 0, nullptr);
+}
+
+int og_batch_graph_replay(og_batch *b) {
+  if (!b) return fail(OG_EINVAL, "batch is NULL");
+  Forest &F = b->F;
+  hipStream_t cs = F.stream;
+  hipError_t e;
+  if (!cs) {
+    if (!F.own_stream) {
+      e = hipStreamCreateWithFlags(&F.own_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    }
+    cs = F.own_stream;
+  }
+  if (!F.gexec) {
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipStream_t keep = F.stream;
+    F.stream = cs;
+    int rc1 = F.build();
+    int rc2 = F.walk_all(F.precision, cs, nullptr, nullptr, 0, nullptr);
+    F.stream = keep;
+    e = hipStreamEndCapture(cs, &g);
+    if (rc1 || rc2) {
+      if (g) hipGraphDestroy(g);
+      return rc1 ? rc1 : rc2;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&F.gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      F.gexec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+  }
+  if (cs != F.stream) {  // order the private stream after the caller's stream and back
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    hipEventRecord(ev, F.stream);
+    hipStreamWaitEvent(cs, ev, 0);
+    e = hipGraphLaunch(F.gexec, cs);
+    hipEventRecord(ev, cs);
+    hipStreamWaitEvent(F.stream, ev, 0);
+    hipEventDestroy(ev);
+  } else {
+    e = hipGraphLaunch(F.gexec, cs);
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return OG_OK;
+}
+
+int og_batch_status(const og_batch *b) {
+  if (!b) return fail(OG_EINVAL, "batch is NULL");
+  Forest &F = const_cast<og_batch *>(b)->F;
+  if (F.own_stream) {
+    hipError_t e = hipStreamSynchronize(F.own_stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  return F.read_status(F.stream);
+}
+
+int og_batch_free(og_batch *b) {
+  if (!b) return OG_OK;
+  hipStreamSynchronize(b->F.stream);
+  if (b->F.own_stream) hipStreamSynchronize(b->F.own_stream);
+  b->F.release();
+  delete b;
+  return OG_OK;
+}
+
+const char *og_strerror(int code) {
+  switch (code) {
+    case OG_OK: return "ok";
+    case OG_EINVAL: return "invalid argument";
+    case OG_ERANGE: return "position out of range";
+    case OG_ENOMEM: return "out of device memory";
+    case OG_EDEVICE: return "device error";
+    case OG_EBUSY: return "busy";
+    case OG_EUNSUPPORTED: return "unsupported";
+    case OG_ENOTFOUND: return "not found";
+    default: return "unknown error";
+  }
+}
+
+const char *og_last_error(void) { return og::g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// Host-side tree object shared by the single-tree, batch and server entry
+// points: owns (or borrows) one device allocation carved into the arrays of
+// BuildArrays, and launches build and walk on a stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/og.h"
+#include "og_kernels.h"
+
+namespace og {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+bool is_device_ptr(const void *p);
+int check_params(const og_params *p, int64_t N, double box, bool need_stream_fields);
+void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, double box, const og_params &p,
+              uint32_t p_off);
+uint64_t node_bound(uint64_t n, int leaf_max);
+size_t forest_bytes(uint32_t n, uint32_t node_cap, int B);
+
+struct Forest {
+  int B = 0;
+  uint32_t N = 0;
+  uint32_t node_cap = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;  // private capture stream when `stream` is the null stream
+  int precision = OG_PREC_MIXED;
+  uint32_t group_max = 64;
+  void *mem = nullptr;
+  size_t bytes = 0;
+  bool own = false;
+  std::vector<BoxDev> hboxes;
+  BuildArrays A{};
+  hipGraphExec_t gexec = nullptr;
+
+  int init(const std::vector<BoxDev> &boxes, uint64_t node_cap, hipStream_t s, int prec, int gmax,
+           void *workspace, size_t ws_bytes);
+  int build();
+  int walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint);
+  int walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
+                  int64_t *nint);
+  int read_status(hipStream_t s);
+  void release();
+};
+
+}  // namespace og

@@ -1,0 +1,110 @@
+// Internal device-side data layout of the tree force library (HIP, gfx950).
+//
+// A "forest" holds B >= 1 independent boxes whose particles are concatenated
+// in one global index space; box b owns global particle indices
+// [p_off, p_off + n) both in caller order and after the sort (the sort key
+// is (box, Morton key, index)), and the nodes [root, node_end) of its
+// pre-order tree.  A single tree is a forest with B = 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace og {
+
+constexpr int kLevels = 21;                 // deepest level; 2^21 cells per axis
+constexpr uint32_t kGrid = 1u << kLevels;
+constexpr int kCountBits = 27;              // node particle count field width
+constexpr uint32_t kCountMask = (1u << kCountBits) - 1u;
+constexpr uint64_t kLeafBit = 1ull << 63;   // in Topo::corner
+
+// Status bits written by kernels (read by the host at sync points).
+constexpr uint32_t kStatusRange = 1u;       // a position outside the box
+constexpr uint32_t kStatusNodes = 2u;       // node bound exceeded (never expected)
+
+// Per-box descriptor, device resident.
+struct BoxDev {
+  const double *pos;     // caller [n][3]
+  const double *mass;    // caller [n]
+  double *acc;           // batch output [n][3] (caller order) or null
+  double *pot;           // batch output [n] or null
+  double lo[3];          // root cube lower corner
+  double L;              // root cube side
+  double scale;          // 2^21 / L
+  double box;            // periodic box side
+  double G, eps2, r_s, rcut, rc2, theta2;
+  float Gf, eps2f, inv2rsf, rcutf, rc2f, theta2f, Lf, h22f;
+  uint32_t p_off, n;     // particle range
+  uint32_t root, node_end;  // node range, written on the device
+  int32_t periodic, cutoff, leaf_max, pad;
+};
+
+// Walk-order node record, 16 bytes.
+//   corner: cx | cy << 21 | cz << 42 (cube corner in level-21 cells), bit 63 = leaf
+//   a:      leaf ? first particle : skip (next node after the subtree)
+//   b:      count | level << 27
+struct __attribute__((aligned(16))) Topo {
+  uint64_t corner;
+  uint32_t a;
+  uint32_t b;
+};
+
+// Node moments: FP64 absolute centre of mass + mass; FP32 offset of the
+// centre of mass from the cube centre + mass.
+struct __attribute__((aligned(32))) Mom64 {
+  double cx, cy, cz, m;
+};
+struct __attribute__((aligned(16))) Mom32 {
+  float ox, oy, oz, m;
+};
+
+// Walk group: up to 64 targets inside node `node` of box `box`; targets are
+// entries [tstart, tstart + tcount) of the sorted target list (or sorted
+// particle positions when every particle is a target).
+struct __attribute__((aligned(16))) Group {
+  uint32_t node, tstart, tcount, box;
+};
+
+// ---- bit helpers ------------------------------------------------------
+__host__ __device__ inline uint64_t spread3(uint32_t v) {
+  // bits b of v (b < 21) -> bit 3b of the result
+  uint64_t x = v & 0x1fffffull;
+  x = (x | (x << 32)) & 0x001f00000000ffffull;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+__host__ __device__ inline uint32_t compact3(uint64_t x) {
+  // bit 3b of x -> bit b of the result
+  x &= 0x1249249249249249ull;
+  x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x | (x >> 8)) & 0x001f0000ff0000ffull;
+  x = (x | (x >> 16)) & 0x001f00000000ffffull;
+  x = (x | (x >> 32)) & 0x00000000001fffffull;
+  return (uint32_t)x;
+}
+__host__ __device__ inline uint64_t morton3(uint32_t cx, uint32_t cy, uint32_t cz) {
+  return (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+}
+
+// Number of leading 3-bit digits two keys share (0..21); keys < 2^63.
+__device__ inline int shared_levels(uint64_t a, uint64_t b) {
+  uint64_t x = a ^ b;
+  if (x == 0) return kLevels;
+  return (__clzll((long long)x) - 1) / 3;
+}
+
+// Box that owns global particle index g (offsets ascending, B entries).
+__device__ inline int box_of(const BoxDev *boxes, int B, uint32_t g) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (boxes[mid].p_off <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace og

@@ -1,0 +1,94 @@
+// Host-side launchers of the library's HIP kernels.  All take a stream and
+// enqueue only; none allocates or synchronises.
+#pragma once
+
+#include "og_internal.h"
+
+namespace og {
+
+// Exclusive scan of n = *n_dev (device scalar, <= cap) uint32 values:
+// out[0..n] with out[n] = total.  `partial` holds cap/kScanTile + 2 words.
+constexpr uint32_t kScanTile = 4096;
+void scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t cap,
+              uint32_t *partial, hipStream_t s);
+
+// LSD radix sort of (key, val) pairs, 8-bit digits.  Key passes
+// [pass_lo, pass_hi) on the 64-bit key, then `box_passes` passes on the box
+// of each value (global particle index).  Ping-pongs between a and b;
+// returns true when the result ends in b.
+constexpr uint32_t kSortTile = 4096;
+bool radix_sort(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *vals_b,
+                uint32_t n, int pass_lo, int pass_hi, int box_passes, const BoxDev *boxes,
+                int B, uint32_t *hist, uint32_t *digit_tot, hipStream_t s);
+size_t radix_hist_words(uint32_t n);
+
+struct BuildArrays {
+  BoxDev *boxes;
+  int B;
+  uint32_t n;                 // total particles
+  uint32_t node_cap;          // node capacity
+  uint64_t *minmax;           // [B][6] ordered-bits min/max for open boxes
+  uint64_t *keys_a, *keys_b;
+  uint32_t *vals_a, *vals_b;
+  uint32_t *hist, *digit_tot;
+  uint32_t *perm, *inv;
+  double4 *part64;
+  float4 *part32;
+  int8_t *lcp;
+  uint8_t *depth;
+  uint32_t *nstart, *S, *scan_partial;
+  Topo *topo;
+  Mom64 *mom64;
+  Mom32 *mom32;
+  uint32_t *first, *skip, *parent, *nchild, *arrive;
+  uint32_t *ng, *goff;
+  Group *groups;
+  uint32_t *scalars;          // [0] status [1] n_groups [2] walk counter [3] n_nodes [4] n
+                              // [5] deepest level (stats)
+  int any_open;               // some box has periodic = 0
+  uint32_t group_max;
+};
+
+void launch_build(BuildArrays &A, hipStream_t s);
+void launch_max_level(const BuildArrays &A, uint32_t *out, hipStream_t s);
+
+// Targets given as caller-order indices (per the single box 0): builds the
+// sorted target list and the walk groups for them.
+struct TargetArrays {
+  const int64_t *idx;
+  uint32_t M;
+  uint64_t *tkey_a, *tkey_b;
+  uint32_t *tval_a, *tval_b;
+  uint32_t *hist, *digit_tot;
+  uint32_t *ng, *goff, *scan_partial;
+  Group *groups;
+  uint32_t *scalars;          // [0] status [1] n_groups [2] walk counter
+  const uint64_t *tkey;       // result (points at a or b)
+  const uint32_t *tval;
+};
+void launch_targets(const BuildArrays &A, TargetArrays &T, hipStream_t s);
+
+struct WalkArgs {
+  const BoxDev *boxes;
+  const Topo *topo;
+  const Mom32 *mom32;
+  const Mom64 *mom64;
+  const float4 *part32;
+  const double4 *part64;
+  const uint32_t *perm;
+  const Group *groups;
+  const uint32_t *n_groups;
+  uint32_t *counter;
+  const uint64_t *tkey;       // sorted target positions, or null: all particles
+  const uint32_t *tval;       // target slots
+  double *acc;                // non-null: outputs by slot; null: per-box acc/pot
+  double *pot;
+  int64_t *nint;
+  int pot_override;           // 1: use `pot` (possibly null) instead of the box's
+};
+void launch_walk(const WalkArgs &W, int precision, uint32_t max_groups, hipStream_t s);
+void launch_reset(uint32_t *word, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace og
