@@ -192,13 +192,16 @@ __global__ __launch_bounds__(kThreads) void k_walk64(WalkArgs A) {
 }
 
 // ----------------------------------------------------------- mixed form --
-// Offsets are FP32 relative to the group's cube centre `ref`: node centres
-// from exact integer cell arithmetic (minimum image on integers), centre of
-// mass = node centre + the node's FP32 centre-of-mass offset, particles =
-// leaf centre + the particle's FP32 offset (both offsets were formed in FP64
-// at build time), targets = FP64 (x - ref) rounded once.
+// Every lane works in FP32 offsets from its own origin `ref`, the centre of
+// the level-21 cell holding its target.  Node centres relative to ref come
+// from exact integer cell arithmetic (periodic minimum image on integers,
+// the box being 2^22 half-cells long); a node's centre of mass is its centre
+// plus the node's FP32 offset, a particle is its leaf centre plus its FP32
+// offset (both offsets formed in FP64 at build time); the target itself is
+// FP64 (x - ref) rounded once.  The origin depends on the target only, so
+// results do not depend on how targets are grouped.
 struct Consts32 {
-  float G, eps2, inv2rs, rcut, rc2, theta2, h22, L;
+  float G, eps2, inv2rs, rcut, rc2, theta2, h22, L, half_box, box;
   bool cutoff, periodic;
 };
 
@@ -233,7 +236,14 @@ __device__ inline int wrap_half_cells(int d, bool periodic) {
   return d;
 }
 
+__device__ inline float wrap_box(float d, const Consts32 &k) {
+  if (d > k.half_box) return d - k.box;
+  if (d < -k.half_box) return d + k.box;
+  return d;
+}
+
 __global__ __launch_bounds__(kThreads) void k_walk32(WalkArgs A) {
+#pragma clang fp contract(fast)
   const uint32_t lane = threadIdx.x & 63;
   while (true) {
     uint32_t g = 0;
@@ -251,18 +261,20 @@ __global__ __launch_bounds__(kThreads) void k_walk32(WalkArgs A) {
     k.theta2 = bx.theta2f;
     k.h22 = bx.h22f;
     k.L = bx.Lf;
+    k.box = bx.Lf;
+    k.half_box = 0.5f * bx.Lf;
     k.cutoff = bx.cutoff;
     k.periodic = bx.periodic;
     uint32_t p = 0, slot = 0;
     const bool valid = lane_target(A, gr, bx, lane, p, slot);
-    // group reference point: centre of the group's node, in half-cells
-    const Topo tg = A.topo[gr.node];
-    const int lg = (int)(tg.b >> kCountBits);
-    const int r0 = 2 * (int)(tg.corner & 0x1fffffull) + (1 << (kLevels - lg));
-    const int r1 = 2 * (int)((tg.corner >> 21) & 0x1fffffull) + (1 << (kLevels - lg));
-    const int r2i = 2 * (int)((tg.corner >> 42) & 0x1fffffull) + (1 << (kLevels - lg));
+    // lane origin: centre of the target's level-21 cell, in half-cells
+    int r0 = 0, r1 = 0, r2i = 0;
     float xr = 0.0f, yr = 0.0f, zr = 0.0f;
     if (valid) {
+      const uint64_t key = A.skeys[p];
+      r0 = 2 * (int)compact3(key >> 2) + 1;
+      r1 = 2 * (int)compact3(key >> 1) + 1;
+      r2i = 2 * (int)compact3(key) + 1;
       const double h22 = bx.L * 0x1p-22;
       const double4 q = A.part64[p];
       xr = (float)(q.x - (bx.lo[0] + (double)r0 * h22));
@@ -280,13 +292,19 @@ __global__ __launch_bounds__(kThreads) void k_walk32(WalkArgs A) {
       const bool leaf = (t.corner & kLeafBit) != 0;
       const int lev = (int)(t.b >> kCountBits);
       const int hc = 1 << (kLevels - lev);
-      const int d0 = wrap_half_cells(2 * (int)(t.corner & 0x1fffffull) + hc - r0, k.periodic);
-      const int d1 = wrap_half_cells(2 * (int)((t.corner >> 21) & 0x1fffffull) + hc - r1, k.periodic);
-      const int d2 = wrap_half_cells(2 * (int)((t.corner >> 42) & 0x1fffffull) + hc - r2i, k.periodic);
-      const float cx = (float)d0 * k.h22, cy = (float)d1 * k.h22, cz = (float)d2 * k.h22;
       const float side = ldexpf(k.L, -lev);
-      const float dcx = cx - xr, dcy = cy - yr, dcz = cz - zr;
+      // offsets may need the minimum image once the node can reach half a box
+      const bool wrapd = k.periodic && (k.rcut + side >= k.half_box);
       bool open_int = false, open_leaf = false;
+      float dcx = 0.0f, dcy = 0.0f, dcz = 0.0f;
+      if (next == n || leaf) {
+        const int d0 = wrap_half_cells(2 * (int)(t.corner & 0x1fffffull) + hc - r0, k.periodic);
+        const int d1 = wrap_half_cells(2 * (int)((t.corner >> 21) & 0x1fffffull) + hc - r1, k.periodic);
+        const int d2 = wrap_half_cells(2 * (int)((t.corner >> 42) & 0x1fffffull) + hc - r2i, k.periodic);
+        dcx = (float)d0 * k.h22 - xr;
+        dcy = (float)d1 * k.h22 - yr;
+        dcz = (float)d2 * k.h22 - zr;
+      }
       if (next == n) {
         bool pruned = false;
         if (k.cutoff) {
@@ -296,7 +314,12 @@ __global__ __launch_bounds__(kThreads) void k_walk32(WalkArgs A) {
         if (pruned) {
           next = leaf ? n + 1 : t.a;
         } else {
-          const float dx = dcx + mm.ox, dy = dcy + mm.oy, dz = dcz + mm.oz;
+          float dx = dcx + mm.ox, dy = dcy + mm.oy, dz = dcz + mm.oz;
+          if (wrapd) {
+            dx = wrap_box(dx, k);
+            dy = wrap_box(dy, k);
+            dz = wrap_box(dz, k);
+          }
           const float r2 = dx * dx + dy * dy + dz * dz;
           const float near = 0.6f * side;
           const bool open = (side * side > k.theta2 * r2) ||
@@ -323,7 +346,12 @@ __global__ __launch_bounds__(kThreads) void k_walk32(WalkArgs A) {
             for (uint32_t j = 0; j < m; ++j) {
               const float qx = rdl(q.x, j), qy = rdl(q.y, j), qz = rdl(q.z, j), qm = rdl(q.w, j);
               if (open_leaf && f + base + j != p) {
-                const float dx = dcx + qx, dy = dcy + qy, dz = dcz + qz;
+                float dx = dcx + qx, dy = dcy + qy, dz = dcz + qz;
+                if (wrapd) {
+                  dx = wrap_box(dx, k);
+                  dy = wrap_box(dy, k);
+                  dz = wrap_box(dz, k);
+                }
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 if (!k.cutoff || r2 < k.rc2) pair32(dx, dy, dz, r2, qm, k, ax, ay, az, ph, ni);
               }

@@ -224,6 +224,7 @@ int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_
   W.part32 = A.part32;
   W.part64 = A.part64;
   W.perm = A.perm;
+  W.skeys = A.keys_a;
   W.groups = A.groups;
   W.n_groups = &A.scalars[1];
   W.counter = &A.scalars[2];
@@ -272,6 +273,7 @@ int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M,
   W.part32 = A.part32;
   W.part64 = A.part64;
   W.perm = A.perm;
+  W.skeys = A.keys_a;
   W.groups = T.groups;
   W.n_groups = &T.scalars[1];
   W.counter = &T.scalars[2];

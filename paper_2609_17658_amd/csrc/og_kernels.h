@@ -76,6 +76,7 @@ struct WalkArgs {
   const float4 *part32;
   const double4 *part64;
   const uint32_t *perm;
+  const uint64_t *skeys;      // sorted Morton keys
   const Group *groups;
   const uint32_t *n_groups;
   uint32_t *counter;
