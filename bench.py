@@ -1,0 +1,280 @@
+"""Benchmark: short-range TreePM tree force on one MI355X.
+
+One step = the whole hot path on one synthetic box: octree build (keys,
+radix sort, gather, topology, moments, groups) + force on every particle.
+Workload: N = 128^3 = 2,097,152 equal-mass particles in a periodic unit box,
+half uniform, half in 64 Plummer spheres (a = 0.005), eps = 1/(40*128),
+r_s = 1.25/256, r_cut = 4.5 r_s, theta = 0.5, leaf_max = 8.
+
+Prints ONE JSON line: particles/s of the mixed form (FP32 interactions,
+FP64 offsets and accumulation), the plain FP64 form beside it, per-step
+p50/p99 ms, error percentiles vs the FP64 CPU oracle, the walk kernel's
+achieved FP32 rate against the vector peak, and the oracle timed on the host
+cores as a baseline.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "short-range tree-force particles/s, FP32 vs FP64 at stated error; p99 ms"
+FLOP_PER_INTERACTION = 45          # 41 FP32 + 4 FP64 per accepted partner
+PEAK_FP32 = 157.3e12               # MI355X FP32 vector, FLOP/s
+PEAK_HBM = 8.0e12                  # MI355X HBM3E, B/s
+BUILD_BYTES_PER_PARTICLE = None    # computed from the tree (algorithmic bytes)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_bytes(n, n_nodes, n_groups_bound=None):
+    """Algorithmic HBM bytes of one build (every array read/written once per
+    pass it is needed in): keys 36 B/particle (24 in + 12 out), 8 radix
+    passes x (8 histogram read + 24 scatter read/write), gather 64 (32
+    random read, 32 + 8 written), topology 8 key + 6 lcp/depth + 12 scan
+    per particle plus 24 per node, moments 16 + 32 particle, 48 + 12 per
+    node, groups 16 per node."""
+    per_particle = 36 + 8 * 32 + 64 + 8 + 6 + 12 + 48
+    per_node = 24 + 60 + 16
+    return per_particle * n + per_node * n_nodes
+
+
+def git_hash():
+    try:
+        return subprocess.run(["git", "-C", ROOT, "rev-parse", "--short", "HEAD"], capture_output=True,
+                              text=True, timeout=5).stdout.strip() or None
+    except Exception:  # noqa: BLE001
+        return None
+
+
+def time_steps(og, torch, tp, tm, params, ws, precision, steps, warmup):
+    """Returns per-step ms, per-step walk ms, final (acc, pot) and the trees."""
+    stream = torch.cuda.current_stream()
+    trees = []
+
+    def one_step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        t = og.Tree(tp, tm, 1.0, params, stream=stream, workspace=ws, precision=precision)
+        if ev is not None:
+            ev[1].record(stream)
+        acc, pot = t.force()
+        if ev is not None:
+            ev[2].record(stream)
+        trees.append(t)
+        return acc, pot
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    for t in trees:
+        t.close()
+    trees.clear()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for k in range(steps):
+        out = one_step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
+    build_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    walk_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    total_ms = evs[0][0].elapsed_time(evs[-1][2])
+    return {"step_ms": step_ms, "build_ms": build_ms, "walk_ms": walk_ms, "total_ms": total_ms,
+            "wall_s": wall, "out": out, "trees": trees}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each box is independent; see the sharding notes in the design document).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2609_17658_amd import og, synth
+
+    assert torch.cuda.is_available(), "no GPU"
+    og.load()
+    dev = torch.device("cuda:0")
+    w = synth.mixture2m(theta=args.theta)
+    n = w.pos.shape[0]
+    prm = w.params.as_dict()
+    log("workload mixture2m: N=%d theta=%.2f" % (n, args.theta))
+    tp = torch.as_tensor(w.pos, device=dev)
+    tm = torch.as_tensor(w.mass, device=dev)
+    ws = torch.empty(og.og_tree_workspace_bound(n, og.make_params(prm)), dtype=torch.uint8, device=dev)
+
+    res = {}
+    for prec in ("mixed", "fp64"):
+        log("timing %s: %d warmup + %d steps" % (prec, args.warmup, args.steps))
+        r = time_steps(og, torch, tp, tm, prm, ws, prec, args.steps, args.warmup)
+        res[prec] = r
+        log("  %s: step %.3f ms (build %.3f, walk %.3f)" % (prec, r["step_ms"].mean(), r["build_ms"].mean(),
+                                                            r["walk_ms"].mean()))
+
+    # interaction counts and tree stats (outside the timed region)
+    t = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream(), workspace=ws)
+    st = t.stats()
+    acc_m, pot_m, nint_m = t.force(precision="mixed", with_counts=True)
+    acc_d, pot_d, nint_d = t.force(precision="fp64", with_counts=True)
+    torch.cuda.synchronize()
+    inter_m = int(nint_m.sum().item())
+    inter_d = int(nint_d.sum().item())
+    acc_m = acc_m.cpu().numpy()
+    acc_d = acc_d.cpu().numpy()
+    nint_d_np = nint_d.cpu().numpy()
+    nint_m_np = nint_m.cpu().numpy()
+    t.close()
+    for r in res.values():
+        for tr in r["trees"]:
+            tr.close()
+
+    K = args.steps
+    m = res["mixed"]
+    d = res["fp64"]
+    ms_step = m["total_ms"] / K
+    value = n / (ms_step * 1e-3)
+    fp64_value = n / (d["total_ms"] / K * 1e-3)
+    walk_ms = float(m["walk_ms"].mean())
+    flops = inter_m * FLOP_PER_INTERACTION
+    achieved = flops / (walk_ms * 1e-3)
+    bb = build_bytes(n, st["n_nodes"])
+    build_gbs = bb / (float(m["build_ms"].mean()) * 1e-3)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "mixture2m: N=128^3 periodic unit box, 50%% uniform + 64 Plummer spheres "
+                        "(a=0.005), eps=1/5120, r_s=1.25/256, r_cut=4.5 r_s, theta=%.2f, leaf_max=8"
+                        % args.theta,
+            "N": n, "theta": args.theta, "leaf_max": 8, "group_max": 64,
+            "precision": "mixed: FP32 interactions on node-relative offsets, FP64 offsets + accumulation",
+            "step": "og_tree_build + og_tree_force on all N targets",
+        },
+        "p50_ms": float(np.percentile(m["step_ms"], 50)),
+        "p99_ms": float(np.percentile(m["step_ms"], 99)),
+        "build_ms": float(m["build_ms"].mean()),
+        "walk_ms": walk_ms,
+        "fp64": {
+            "value": fp64_value, "unit": "particles/s", "ms_per_step": d["total_ms"] / K,
+            "build_ms": float(d["build_ms"].mean()), "walk_ms": float(d["walk_ms"].mean()),
+            "p99_ms": float(np.percentile(d["step_ms"], 99)),
+        },
+        "mixed_over_fp64": value / fp64_value,
+        "interactions_per_target": inter_m / n,
+        "tree": {"n_nodes": st["n_nodes"], "depth": st["depth"]},
+        "roofline": {
+            "bound": "alu", "kernel": "k_walk32 (mixed walk)",
+            "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32, "traffic": None,
+            "flop_per_interaction": FLOP_PER_INTERACTION, "interactions": inter_m,
+        },
+        "roofline_build": {
+            "bound": "hbm", "achieved": build_gbs / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": build_gbs / PEAK_HBM, "algorithmic_bytes": bb,
+        },
+        "git": git_hash(),
+    }
+
+    # oracle: error of both GPU forms and the CPU baseline
+    if args.no_oracle:
+        out["error"] = None
+        out["cpu_baseline"] = None
+        print(json.dumps(out), flush=True)
+        return
+    try:
+        import oracle
+        op = oracle.Params(**{k: prm[k] for k in ("G", "eps", "r_s", "r_cut", "theta", "periodic",
+                                                  "leaf_max")})
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        otree = oracle.build_tree(w.pos, w.mass, 1.0, op)
+        t_build = time.perf_counter() - t0
+        rng = np.random.default_rng(99)
+        probe = np.sort(rng.choice(n, 16384, replace=False))
+        t0 = time.perf_counter()
+        acc_o, _, nint_o = oracle.walk(otree, targets=probe)
+        t_probe = time.perf_counter() - t0
+        per_target = t_probe / probe.size
+        if not args.no_cpu_baseline and t_build + per_target * n <= args.cpu_budget_s:
+            sample = np.arange(n)
+        else:
+            k = int(max(16384, min(n, (args.cpu_budget_s - t_build) / max(per_target, 1e-9))))
+            sample = np.sort(rng.choice(n, k, replace=False))
+        t0 = time.perf_counter()
+        acc_s, _, nint_s = oracle.walk(otree, targets=sample)
+        t_walk = time.perf_counter() - t0
+        t_total = t_build + t_walk * (n / sample.size)
+        e_m = np.linalg.norm(acc_m[sample] - acc_s, axis=1) / np.linalg.norm(acc_s, axis=1)
+        e_d = np.linalg.norm(acc_d[sample] - acc_s, axis=1) / np.linalg.norm(acc_s, axis=1)
+        rms = np.sqrt(np.mean(np.sum(acc_s ** 2, axis=1)))
+        out["error"] = {
+            "vs": "FP64 CPU oracle tree walk, same tree parameters", "targets": int(sample.size),
+            "mixed_median": float(np.median(e_m)), "mixed_p99": float(np.percentile(e_m, 99)),
+            "mixed_max": float(e_m.max()),
+            "mixed_p99_over_rms": float(np.percentile(np.linalg.norm(acc_m[sample] - acc_s, axis=1), 99) / rms),
+            "fp64_median": float(np.median(e_d)), "fp64_max": float(e_d.max()),
+            "fp64_counts_equal": bool(np.array_equal(nint_d_np[sample], nint_s)),
+            "mixed_count_flips": int((nint_m_np[sample] != nint_s).sum()),
+        }
+        out["cpu_baseline"] = {
+            "value": n / t_total, "unit": "particles/s", "cores": cores, "kind": "oracle",
+            "sample": ("full tree build (%.2f s) + walk of %d of %d targets (%.2f s)%s"
+                       % (t_build, sample.size, n, t_walk,
+                          "" if sample.size == n else ", walk time scaled to all targets")),
+            "cpu": _cpu_model(),
+        }
+        if args.no_cpu_baseline:
+            out["cpu_baseline"] = None
+    except Exception as exc:  # noqa: BLE001 - report, do not hide
+        log("oracle leg failed: %r" % (exc,))
+        out["error"] = None
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

@@ -488,14 +488,16 @@ __global__ __launch_bounds__(kThreads) void k_emit(const BoxDev *boxes, int B, u
   }
 }
 
-// Parent links and child counts; clears the arrival counters.
+// Parent links and child counts; counts the internal nodes of each level.
 __global__ __launch_bounds__(kThreads) void k_links(const Topo *topo, const uint32_t *skip,
                                                     const uint32_t *scalars, uint32_t node_cap,
                                                     uint32_t *parent, uint32_t *nchild,
-                                                    uint32_t *arrive) {
+                                                    uint32_t *lvl_cnt) {
+  __shared__ uint32_t h[kLevels + 1];
+  if (threadIdx.x <= kLevels) h[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t tot = min(scalars[3], node_cap);
   for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
-    arrive[r] = 0;
     const Topo t = topo[r];
     uint32_t nc = 0;
     if (!(t.corner & kLeafBit)) {
@@ -507,8 +509,18 @@ __global__ __launch_bounds__(kThreads) void k_links(const Topo *topo, const uint
         if (nx <= c) break;  // never taken for a well-formed tree
         c = nx;
       }
+      atomicAdd(&h[t.b >> kCountBits], 1u);
     }
     nchild[r] = nc;
+  }
+  __syncthreads();
+  if (threadIdx.x <= kLevels && h[threadIdx.x]) atomicAdd(&lvl_cnt[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_zero_levels(uint32_t *lvl_cnt, uint32_t *lvl_fill) {
+  if (threadIdx.x <= kLevels) {
+    lvl_cnt[threadIdx.x] = 0;
+    lvl_fill[threadIdx.x] = 0;
   }
 }
 
@@ -527,112 +539,96 @@ __device__ inline void node_centre(const BoxDev &bx, uint64_t corner, int level,
   c[2] = bx.lo[2] + ((double)(uint32_t)((corner >> 42) & 0x1fffffull) + half) * h;
 }
 
-// Bottom-up moments.  Each leaf sums its particles (relative to the cube
-// centre) and writes the particles' FP32 offsets from that centre; then it
-// climbs: the last child to arrive at a parent (acq_rel counter at agent
-// scope) sums the parent's children in child order.  Every node is summed
-// exactly once, in a fixed order, so the result is deterministic.
-__global__ __launch_bounds__(kThreads) void k_moments(const BoxDev *boxes, int B, const Topo *topo,
-                                                      const uint32_t *skip, const uint32_t *parent,
-                                                      const uint32_t *nchild, uint32_t *arrive,
-                                                      const double4 *part64, float4 *part32,
-                                                      Mom64 *mom64, Mom32 *mom32,
-                                                      const uint32_t *scalars, uint32_t node_cap) {
+// Bottom-up moments, level by level (paper, "Tree construction": a
+// bottom-up pass computes each node's mass and centre of mass).  Leaves sum
+// their particles relative to the cube centre (and write each particle's
+// FP32 offset from that centre); internal nodes are bucketed by level and
+// each level, deepest first, sums its children in child order.  Every
+// node is summed once in a fixed order, so the result is deterministic, and
+// levels are separated by kernel boundaries only.
+__global__ __launch_bounds__(kThreads) void k_leaves_and_buckets(
+    const BoxDev *boxes, int B, const Topo *topo, const double4 *part64, float4 *part32, Mom64 *mom64,
+    Mom32 *mom32, const uint32_t *scalars, uint32_t node_cap, const uint32_t *lvl_cnt, uint32_t *lvl_fill,
+    uint32_t *lvl_nodes) {
+  __shared__ uint32_t base[kLevels + 1], lcount[kLevels + 1], lres[kLevels + 1];
+  if (threadIdx.x <= kLevels) {
+    uint32_t o = 0;
+    for (int l = 0; l < (int)threadIdx.x; ++l) o += lvl_cnt[l];
+    base[threadIdx.x] = o;
+  }
   const uint32_t tot = min(scalars[3], node_cap);
-  for (uint32_t r0 = blockIdx.x * kThreads + threadIdx.x; r0 < tot; r0 += gridDim.x * kThreads) {
-    const Topo t = topo[r0];
-    if (!(t.corner & kLeafBit)) continue;
-    const uint32_t f = t.a, cnt = t.b & kCountMask;
-    const BoxDev &bx = boxes[box_of(boxes, B, f)];
-    double c[3];
-    node_centre(bx, t.corner, (int)(t.b >> kCountBits), c);
-    double M = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (uint32_t j = f; j < f + cnt; ++j) {
-      const double4 q = part64[j];
-      const double dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
-      M += q.w;
-      s0 += q.w * dx;
-      s1 += q.w * dy;
-      s2 += q.w * dz;
-      part32[j] = make_float4((float)dx, (float)dy, (float)dz, (float)q.w);
-    }
-    double com[3] = {c[0] + s0 / M, c[1] + s1 / M, c[2] + s2 / M};
-    mom64[r0] = Mom64{com[0], com[1], com[2], M};
-    mom32[r0] = Mom32{(float)(com[0] - c[0]), (float)(com[1] - c[1]), (float)(com[2] - c[2]), (float)M};
-    uint32_t r = r0;
-    while (true) {
-      const uint32_t par = parent[r];
-      if (par == 0xffffffffu) break;
-      const uint32_t old =
-          __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (old + 1 != nchild[par]) break;
-      const Topo tp = topo[par];
-      double cp[3];
-      node_centre(bx, tp.corner, (int)(tp.b >> kCountBits), cp);
-      double Mp = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
-      const uint32_t pend = min(tp.a, tot);
-      for (uint32_t ch = par + 1; ch < pend;) {
-        const Mom64 m = mom64[ch];
-        Mp += m.m;
-        q0 += m.m * (m.cx - cp[0]);
-        q1 += m.m * (m.cy - cp[1]);
-        q2 += m.m * (m.cz - cp[2]);
-        const uint32_t nx = skip[ch];
-        if (nx <= ch) break;  // never taken for a well-formed tree
-        ch = nx;
+  const uint32_t stride = gridDim.x * kThreads;
+  // round-based so that each block reserves bucket slots once per round
+  for (uint32_t r0 = blockIdx.x * kThreads; r0 < tot; r0 += stride) {
+    const uint32_t r = r0 + threadIdx.x;
+    if (threadIdx.x <= kLevels) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    int lvl = -1;
+    uint32_t slot = 0;
+    if (r < tot) {
+      const Topo t = topo[r];
+      if (t.corner & kLeafBit) {
+        const uint32_t f = t.a, cnt = t.b & kCountMask;
+        const BoxDev &bx = boxes[box_of(boxes, B, f)];
+        double c[3];
+        node_centre(bx, t.corner, (int)(t.b >> kCountBits), c);
+        double M = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (uint32_t j = f; j < f + cnt; ++j) {
+          const double4 q = part64[j];
+          const double dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
+          M += q.w;
+          s0 += q.w * dx;
+          s1 += q.w * dy;
+          s2 += q.w * dz;
+          part32[j] = make_float4((float)dx, (float)dy, (float)dz, (float)q.w);
+        }
+        const double com[3] = {c[0] + s0 / M, c[1] + s1 / M, c[2] + s2 / M};
+        mom64[r] = Mom64{com[0], com[1], com[2], M};
+        mom32[r] = Mom32{(float)(com[0] - c[0]), (float)(com[1] - c[1]), (float)(com[2] - c[2]), (float)M};
+      } else {
+        lvl = (int)(t.b >> kCountBits);
+        slot = atomicAdd(&lcount[lvl], 1u);
       }
-      const double cm[3] = {cp[0] + q0 / Mp, cp[1] + q1 / Mp, cp[2] + q2 / Mp};
-      mom64[par] = Mom64{cm[0], cm[1], cm[2], Mp};
-      mom32[par] = Mom32{(float)(cm[0] - cp[0]), (float)(cm[1] - cp[1]), (float)(cm[2] - cp[2]),
-                         (float)Mp};
-      r = par;
     }
+    __syncthreads();
+    if (threadIdx.x <= kLevels && lcount[threadIdx.x])
+      lres[threadIdx.x] = atomicAdd(&lvl_fill[threadIdx.x], lcount[threadIdx.x]);
+    __syncthreads();
+    if (lvl >= 0) lvl_nodes[base[lvl] + lres[lvl] + slot] = r;
+    __syncthreads();
   }
 }
 
-// -------------------------------------------------------------- groups --
-// Walk groups when every particle is a target: the maximal nodes holding
-// <= group_max particles (and chunks of leaves that hold more).
-__global__ __launch_bounds__(kThreads) void k_group_count(const BoxDev *boxes, int B, const Topo *topo,
-                                                          const uint32_t *parent, const uint32_t *scalars,
-                                                          uint32_t node_cap, uint32_t G, uint32_t *ng) {
+__global__ __launch_bounds__(kThreads) void k_moments_level(const BoxDev *boxes, int B, int level,
+                                                            const Topo *topo, const uint32_t *first,
+                                                            const uint32_t *skip, const uint32_t *lvl_cnt,
+                                                            const uint32_t *lvl_nodes, const uint32_t *scalars,
+                                                            uint32_t node_cap, Mom64 *mom64, Mom32 *mom32) {
+  uint32_t o = 0;
+  for (int l = 0; l < level; ++l) o += lvl_cnt[l];
+  const uint32_t cnt = lvl_cnt[level];
   const uint32_t tot = min(scalars[3], node_cap);
-  for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
-    const Topo t = topo[r];
-    const uint32_t cnt = t.b & kCountMask;
-    const uint32_t par = parent[r];
-    uint32_t k = 0;
-    if (cnt <= G) {
-      if (par == 0xffffffffu || (topo[par].b & kCountMask) > G) k = 1;
-    } else if (t.corner & kLeafBit) {
-      k = (cnt + G - 1) / G;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < cnt; i += gridDim.x * kThreads) {
+    const uint32_t par = lvl_nodes[o + i];
+    const Topo tp = topo[par];
+    const BoxDev &bx = boxes[box_of(boxes, B, first[par])];
+    double cp[3];
+    node_centre(bx, tp.corner, level, cp);
+    double Mp = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    const uint32_t pend = min(tp.a, tot);
+    for (uint32_t ch = par + 1; ch < pend;) {
+      const Mom64 m = mom64[ch];
+      Mp += m.m;
+      q0 += m.m * (m.cx - cp[0]);
+      q1 += m.m * (m.cy - cp[1]);
+      q2 += m.m * (m.cz - cp[2]);
+      const uint32_t nx = skip[ch];
+      if (nx <= ch) break;  // never taken for a well-formed tree
+      ch = nx;
     }
-    ng[r] = k;
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void k_group_emit(const BoxDev *boxes, int B, const Topo *topo,
-                                                         const uint32_t *first, const uint32_t *ng,
-                                                         const uint32_t *goff, const uint32_t *scalars,
-                                                         uint32_t node_cap, uint32_t G, Group *groups,
-                                                         uint32_t *n_groups) {
-  const uint32_t tot = min(scalars[3], node_cap);
-  const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
-  if (gid == 0) *n_groups = goff[tot];
-  for (uint32_t r = gid; r < tot; r += gridDim.x * kThreads) {
-    const uint32_t k = ng[r];
-    if (k == 0) continue;
-    const uint32_t cnt = topo[r].b & kCountMask, f = first[r];
-    const uint32_t b = (uint32_t)box_of(boxes, B, f);
-    const uint32_t o = goff[r];
-    for (uint32_t c = 0; c < k; ++c) {
-      Group gr;
-      gr.node = r;
-      gr.tstart = f + c * G;
-      gr.tcount = min(G, cnt - c * G);
-      gr.box = b;
-      groups[o + c] = gr;
-    }
+    const double cm[3] = {cp[0] + q0 / Mp, cp[1] + q1 / Mp, cp[2] + q2 / Mp};
+    mom64[par] = Mom64{cm[0], cm[1], cm[2], Mp};
+    mom32[par] = Mom32{(float)(cm[0] - cp[0]), (float)(cm[1] - cp[1]), (float)(cm[2] - cp[2]), (float)Mp};
   }
 }
 
@@ -653,68 +649,34 @@ __global__ __launch_bounds__(kThreads) void k_targets_map(const BoxDev *boxes, c
   tval[t] = t;
 }
 
-__device__ inline uint32_t lower_bound_u64(const uint64_t *a, uint32_t n, uint64_t v) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-__global__ __launch_bounds__(kThreads) void k_group_count_sub(const Topo *topo, const uint32_t *first,
-                                                              const uint32_t *parent, const uint32_t *scalars,
-                                                              uint32_t node_cap, uint32_t G,
-                                                              const uint64_t *tkey, uint32_t M,
-                                                              uint32_t *ng) {
+// Walk records for the mixed-precision walk (see WNode).
+__global__ __launch_bounds__(kThreads) void k_wnodes(const BoxDev *boxes, int B, const Topo *topo,
+                                                     const Mom32 *mom32, const uint32_t *first,
+                                                     const uint32_t *scalars, uint32_t node_cap, WNode *wn) {
   const uint32_t tot = min(scalars[3], node_cap);
   for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
     const Topo t = topo[r];
-    const uint32_t f = first[r], cnt = t.b & kCountMask;
-    const uint32_t sel = lower_bound_u64(tkey, M, (uint64_t)f + cnt) - lower_bound_u64(tkey, M, f);
-    uint32_t k = 0;
-    if (sel > 0) {
-      const uint32_t par = parent[r];
-      if (sel <= G) {
-        if (par == 0xffffffffu) {
-          k = 1;
-        } else {
-          const uint32_t pf = first[par], pc = topo[par].b & kCountMask;
-          const uint32_t psel = lower_bound_u64(tkey, M, (uint64_t)pf + pc) - lower_bound_u64(tkey, M, pf);
-          if (psel > G) k = 1;
-        }
-      } else if (t.corner & kLeafBit) {
-        k = (sel + G - 1) / G;
-      }
-    }
-    ng[r] = k;
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void k_group_emit_sub(const Topo *topo, const uint32_t *first,
-                                                             const uint32_t *ng, const uint32_t *goff,
-                                                             const uint32_t *scalars_tree,
-                                                             uint32_t node_cap, uint32_t G,
-                                                             const uint64_t *tkey, uint32_t M,
-                                                             Group *groups, uint32_t *n_groups) {
-  const uint32_t tot = min(scalars_tree[3], node_cap);
-  const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
-  if (gid == 0) *n_groups = goff[tot];
-  for (uint32_t r = gid; r < tot; r += gridDim.x * kThreads) {
-    const uint32_t k = ng[r];
-    if (k == 0) continue;
-    const uint32_t f = first[r], cnt = topo[r].b & kCountMask;
-    const uint32_t t0 = lower_bound_u64(tkey, M, f);
-    const uint32_t sel = lower_bound_u64(tkey, M, (uint64_t)f + cnt) - t0;
-    const uint32_t o = goff[r];
-    for (uint32_t c = 0; c < k; ++c) {
-      Group gr;
-      gr.node = r;
-      gr.tstart = t0 + c * G;
-      gr.tcount = min(G, sel - c * G);
-      gr.box = 0;
-      groups[o + c] = gr;
-    }
+    const Mom32 m = mom32[r];
+    const BoxDev &bx = boxes[box_of(boxes, B, first[r])];
+    const int lev = (int)(t.b >> kCountBits);
+    const int hc = 1 << (kLevels - lev);
+    const bool leaf = (t.corner & kLeafBit) != 0;
+    const float side = ldexpf(bx.Lf, -lev);
+    WNode w;
+    w.c[0] = 2 * (int)(t.corner & 0x1fffffull) + hc;
+    w.c[1] = 2 * (int)((t.corner >> 21) & 0x1fffffull) + hc;
+    w.c[2] = 2 * (int)((t.corner >> 42) & 0x1fffffull) + hc;
+    w.side2 = side * side;
+    w.o[0] = m.ox;
+    w.o[1] = m.oy;
+    w.o[2] = m.oz;
+    w.m = m.m;
+    w.reach = bx.rcutf + 0.5f * side;
+    w.near = 0.6f * side;
+    w.a = t.a;
+    w.cf = (t.b & kCountMask) | (leaf ? kWLeaf : 0u) |
+           ((bx.periodic && bx.rcutf + side >= 0.5f * bx.Lf) ? kWWrap : 0u);
+    wn[r] = w;
   }
 }
 
@@ -733,6 +695,9 @@ __global__ __launch_bounds__(kThreads) void k_max_level(const Topo *topo, const 
 }
 
 __global__ void k_reset(uint32_t *w) { *w = 0; }
+__global__ void k_reset_n(uint32_t *w, int n) {
+  if ((int)threadIdx.x < n) w[threadIdx.x] = 0;
+}
 __global__ void k_set(uint32_t *w, uint32_t v) { *w = v; }
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -754,6 +719,7 @@ int device_cu_count() {
 }
 
 void launch_reset(uint32_t *word, hipStream_t s) { k_reset<<<1, 1, 0, s>>>(word); }
+void launch_reset_n(uint32_t *words, int n, hipStream_t s) { k_reset_n<<<1, 64, 0, s>>>(words, n); }
 
 void launch_max_level(const BuildArrays &A, uint32_t *out, hipStream_t s) {
   k_reset<<<1, 1, 0, s>>>(out);
@@ -815,15 +781,19 @@ void launch_build(BuildArrays &A, hipStream_t s) {
   k_emit<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.S, A.node_cap, A.topo,
                                  A.first, A.skip);
   const uint32_t gnodes = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kThreads), 8192));
-  k_links<<<gnodes, kThreads, 0, s>>>(A.topo, A.skip, A.scalars, A.node_cap, A.parent, A.nchild, A.arrive);
+  k_zero_levels<<<1, 64, 0, s>>>(A.lvl_cnt, A.lvl_fill);
+  k_links<<<gnodes, kThreads, 0, s>>>(A.topo, A.skip, A.scalars, A.node_cap, A.parent, A.nchild, A.lvl_cnt);
   k_roots<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.parent);
-  k_moments<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.skip, A.parent, A.nchild, A.arrive,
-                                        A.part64, A.part32, A.mom64, A.mom32, A.scalars, A.node_cap);
-  k_group_count<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.parent, A.scalars, A.node_cap,
-                                            A.group_max, A.ng);
-  scan_u32(A.ng, A.goff, &A.scalars[3], A.node_cap, A.scan_partial, s);
-  k_group_emit<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.first, A.ng, A.goff, A.scalars,
-                                           A.node_cap, A.group_max, A.groups, &A.scalars[1]);
+  k_leaves_and_buckets<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.part64, A.part32, A.mom64,
+                                                   A.mom32, A.scalars, A.node_cap, A.lvl_cnt, A.lvl_fill,
+                                                   A.lvl_nodes);
+  // internal nodes at level L number at most n / (leaf_max + 1) <= n / 2
+  const uint32_t glev = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(n / 2 + 1, kThreads), 2048));
+  for (int L = kLevels - 1; L >= 0; --L)
+    k_moments_level<<<glev, kThreads, 0, s>>>(A.boxes, A.B, L, A.topo, A.first, A.skip, A.lvl_cnt,
+                                              A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32);
+  k_wnodes<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.mom32, A.first, A.scalars, A.node_cap,
+                                       A.wnode);
 }
 
 void launch_targets(const BuildArrays &A, TargetArrays &T, hipStream_t s) {
@@ -837,12 +807,6 @@ void launch_targets(const BuildArrays &A, TargetArrays &T, hipStream_t s) {
                          T.digit_tot, s);
   T.tkey = in_b ? T.tkey_b : T.tkey_a;
   T.tval = in_b ? T.tval_b : T.tval_a;
-  const uint32_t gnodes = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kThreads), 8192));
-  k_group_count_sub<<<gnodes, kThreads, 0, s>>>(A.topo, A.first, A.parent, A.scalars, A.node_cap,
-                                                A.group_max, T.tkey, M, T.ng);
-  scan_u32(T.ng, T.goff, &A.scalars[3], A.node_cap, T.scan_partial, s);
-  k_group_emit_sub<<<gnodes, kThreads, 0, s>>>(A.topo, A.first, T.ng, T.goff, A.scalars, A.node_cap,
-                                               A.group_max, T.tkey, M, T.groups, &T.scalars[1]);
 }
 
 }  // namespace og

@@ -6,23 +6,23 @@
 // directly.  Paper, "Force evaluation" / "Particle Mesh": every accepted
 // node or particle adds the short-range (erfc) part of the split force.
 //
-// GPU mapping: a persistent grid; each wavefront pops a group of <= 64
-// spatially adjacent targets (one node of the tree) from an atomic queue
-// and walks the tree once for the whole group.  Lane i owns target i and
-// keeps `next`, the next node of ITS OWN per-target walk.  At node n the
-// lanes with next == n apply the per-target rules; the wave goes to n + 1
-// when any lane opened n, otherwise to skip(n).  A lane therefore sees
-// exactly the node sequence of its own walk, in the same order, so its
-// result does not depend on the group it was placed in.  Node records are
-// wave-uniform (scalar loads); a leaf's particles are loaded once,
-// coalesced, and broadcast lane by lane with readlane.
+// GPU mapping: a persistent grid; each wavefront pops a group of up to 64
+// consecutive targets in curve order (spatial neighbours) from an atomic
+// queue and walks the tree once for the whole group.  Lane i owns target i
+// and keeps `next`, the next node of ITS OWN per-target walk.  At node n
+// the lanes with next == n apply the per-target rules; the wave goes to
+// n + 1 when any lane opened n (ballot), otherwise to skip(n).  A lane
+// therefore sees exactly the node sequence of its own walk, in the same
+// order, so its result does not depend on the group it was placed in.
+// Node records are wave-uniform: they are read with scalar loads, and the
+// records of both possible successors are requested before the decision.
+#include <cstdlib>
+
 #include "og_kernels.h"
 
 namespace og {
 
 namespace {
-
-constexpr int kThreads = 256;
 
 // 2/sqrt(pi)
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
@@ -36,6 +36,67 @@ constexpr float kAsA3 = 1.421413741f;
 constexpr float kAsA4 = -1.453152027f;
 constexpr float kAsA5 = 1.061405429f;
 
+// Read-only tree data is read through the constant address space: the
+// compiler may then use scalar (SMEM) loads for wave-uniform addresses.  The
+// walk never writes these arrays.
+template <class T>
+__device__ inline const __attribute__((address_space(4))) T *cptr(const T *p) {
+  return (const __attribute__((address_space(4))) T *)(uintptr_t)p;
+}
+__device__ inline Topo ld(const Topo *p) {
+  const auto q = cptr(p);
+  Topo t;
+  t.corner = q->corner;
+  t.a = q->a;
+  t.b = q->b;
+  return t;
+}
+__device__ inline Mom32 ld(const Mom32 *p) {
+  const auto q = cptr(p);
+  return Mom32{q->ox, q->oy, q->oz, q->m};
+}
+__device__ inline Mom64 ld(const Mom64 *p) {
+  const auto q = cptr(p);
+  return Mom64{q->cx, q->cy, q->cz, q->m};
+}
+__device__ inline BoxDev ld(const BoxDev *p) {
+  const auto q = cptr(p);
+  BoxDev b;
+  b.pos = q->pos;
+  b.mass = q->mass;
+  b.acc = q->acc;
+  b.pot = q->pot;
+  b.lo[0] = q->lo[0];
+  b.lo[1] = q->lo[1];
+  b.lo[2] = q->lo[2];
+  b.L = q->L;
+  b.scale = q->scale;
+  b.box = q->box;
+  b.G = q->G;
+  b.eps2 = q->eps2;
+  b.r_s = q->r_s;
+  b.rcut = q->rcut;
+  b.rc2 = q->rc2;
+  b.theta2 = q->theta2;
+  b.Gf = q->Gf;
+  b.eps2f = q->eps2f;
+  b.inv2rsf = q->inv2rsf;
+  b.rcutf = q->rcutf;
+  b.rc2f = q->rc2f;
+  b.theta2f = q->theta2f;
+  b.Lf = q->Lf;
+  b.h22f = q->h22f;
+  b.p_off = q->p_off;
+  b.n = q->n;
+  b.root = q->root;
+  b.node_end = q->node_end;
+  b.periodic = q->periodic;
+  b.cutoff = q->cutoff;
+  b.leaf_max = q->leaf_max;
+  b.g_off = q->g_off;
+  return b;
+}
+
 __device__ inline float rdl(float v, uint32_t j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)j));
 }
@@ -46,8 +107,34 @@ __device__ inline double rdl(double v, uint32_t j) {
   return __longlong_as_double(((long long)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Target of lane `lane` in group gr: sorted particle position and output slot.
-__device__ inline bool lane_target(const WalkArgs &A, const Group &gr, const BoxDev &bx, uint32_t lane,
+// Group g: box and target range.  Every particle a target: the targets of box
+// b are cut into chunks of `chunk` consecutive sorted particles, box b's
+// chunks numbered from g_off.  A target list: chunks of that list (box 0).
+struct GroupRef {
+  uint32_t box, tstart, tcount;
+};
+__device__ inline GroupRef group_of(const WalkArgs &A, uint32_t g) {
+  GroupRef r;
+  if (A.tkey) {
+    r.box = 0;
+    r.tstart = g * A.chunk;
+    r.tcount = min(A.chunk, A.n_targets - r.tstart);
+    return r;
+  }
+  int lo = 0, hi = A.B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cptr(A.boxes + mid)->g_off <= g) lo = mid; else hi = mid - 1;
+  }
+  const uint32_t off = cptr(A.boxes + lo)->g_off, p0 = cptr(A.boxes + lo)->p_off, nb = cptr(A.boxes + lo)->n;
+  r.box = (uint32_t)lo;
+  r.tstart = p0 + (g - off) * A.chunk;
+  r.tcount = min(A.chunk, p0 + nb - r.tstart);
+  return r;
+}
+
+// Target of lane `lane`: sorted particle position and output slot.
+__device__ inline bool lane_target(const WalkArgs &A, const GroupRef &gr, const BoxDev &bx, uint32_t lane,
                                    uint32_t &p, uint32_t &slot) {
   if (lane >= gr.tcount) return false;
   if (A.tkey) {
@@ -71,12 +158,48 @@ __device__ inline void write_out(const WalkArgs &A, const BoxDev &bx, uint32_t s
   if (A.nint) A.nint[slot] = (int64_t)ni;
 }
 
+// Group queues.  Workgroups are dispatched round-robin over the chip's
+// kQueues XCDs, each with its own L2, so the groups (consecutive in curve
+// order) are split into kQueues contiguous ranges and workgroup b starts on
+// range b % kQueues: the waves of one XCD sweep one region of space and
+// share its tree nodes in their L2.  A wave whose range is exhausted moves
+// on to the next range, so every group is processed exactly once and every
+// wave leaves the loop once all ranges are exhausted.
+struct GroupQueue {
+  uint32_t *counters;
+  uint32_t n_groups;
+  uint32_t q, tried;
+};
+__device__ inline uint32_t range_begin(uint32_t n_groups, uint32_t q) {
+  return (uint32_t)(((uint64_t)n_groups * q) / kQueues);
+}
+// Next group for this wave, or n_groups when all are taken.
+__device__ inline uint32_t pop_group(GroupQueue &Q, uint32_t lane) {
+  while (Q.tried < kQueues) {
+    const uint32_t b = range_begin(Q.n_groups, Q.q), e = range_begin(Q.n_groups, Q.q + 1);
+    uint32_t i = 0;
+    if (lane == 0) i = atomicAdd(&Q.counters[Q.q], 1u);
+    i = __builtin_amdgcn_readlane(i, 0);  // wave-uniform
+    if (b + i < e) return b + i;
+    Q.q = (Q.q + 1) % kQueues;
+    ++Q.tried;
+  }
+  return Q.n_groups;
+}
+__device__ inline GroupQueue make_queue(const WalkArgs &A) {
+  GroupQueue Q;
+  Q.counters = A.counter;
+  Q.n_groups = A.n_groups;
+  Q.q = blockIdx.x % kQueues;
+  Q.tried = 0;
+  return Q;
+}
+
 // ------------------------------------------------------------ FP64 form --
 __device__ inline double minimg(double d, bool periodic, double box) {
-  if (!periodic) return d;
-  if (d > 0.5 * box) return d - box;
-  if (d < -0.5 * box) return d + box;
-  return d;
+  const double hi = d > 0.5 * box ? d - box : d;
+  const double w = d < -0.5 * box ? d + box : hi;
+  return periodic ? w : d;
 }
 
 __device__ inline void pair64(double dx, double dy, double dz, double m, const BoxDev &bx, double &ax,
@@ -101,31 +224,38 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, const B
   ++ni;
 }
 
-__global__ __launch_bounds__(kThreads) void k_walk64(WalkArgs A) {
+// Plain FP64 walk: every quantity in double precision, with the same
+// expressions (and no contraction) as a direct reading of the walk rules.
+__global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
 #pragma clang fp contract(off)
   const uint32_t lane = threadIdx.x & 63;
+  GroupQueue Q = make_queue(A);
   while (true) {
-    uint32_t g = 0;
-    if (lane == 0) g = atomicAdd(A.counter, 1u);
-    g = __shfl(g, 0, 64);
-    if (g >= *A.n_groups) break;
-    const Group gr = A.groups[g];
-    const BoxDev &bx = A.boxes[gr.box];
+    const uint32_t g = pop_group(Q, lane);
+    if (g >= A.n_groups) break;
+    const GroupRef gr = group_of(A, g);
+    const BoxDev bx = ld(A.boxes + gr.box);
     uint32_t p = 0, slot = 0;
     const bool valid = lane_target(A, gr, bx, lane, p, slot);
     double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
     if (valid) xi = A.part64[p];
-    const bool periodic = bx.periodic, cutoff = bx.cutoff;
+    const bool periodic = bx.periodic;
     const double box = bx.box, h = bx.L * 0x1p-21;
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
     uint32_t ni = 0;
     uint32_t n = bx.root;
     const uint32_t nend = bx.node_end;
     uint32_t next = valid ? n : nend;
+    Topo t = ld(A.topo + n);
+    Mom64 mm = ld(A.mom64 + n);
     while (n < nend) {
-      const Topo t = A.topo[n];
-      const Mom64 mm = A.mom64[n];
       const bool leaf = (t.corner & kLeafBit) != 0;
+      const uint32_t ns = leaf ? n + 1 : t.a;
+      const uint32_t n1c = min(n + 1, nend - 1), nsc = min(ns, nend - 1);
+      const Topo t1 = ld(A.topo + n1c);
+      const Mom64 m1 = ld(A.mom64 + n1c);
+      const Topo ts = ld(A.topo + nsc);
+      const Mom64 msk = ld(A.mom64 + nsc);
       const int lev = (int)(t.b >> kCountBits);
       const double side = ldexp(bx.L, -lev);
       const double half = ldexp(1.0, 20 - lev);
@@ -138,12 +268,12 @@ __global__ __launch_bounds__(kThreads) void k_walk64(WalkArgs A) {
         const double dcy = minimg(c1 - xi.y, periodic, box);
         const double dcz = minimg(c2 - xi.z, periodic, box);
         bool pruned = false;
-        if (cutoff) {
+        if (bx.cutoff) {
           const double reach = bx.rcut + 0.5 * side;
           pruned = fabs(dcx) > reach || fabs(dcy) > reach || fabs(dcz) > reach;
         }
         if (pruned) {
-          next = leaf ? n + 1 : t.a;
+          next = ns;
         } else {
           const double dx = minimg(mm.cx - xi.x, periodic, box);
           const double dy = minimg(mm.cy - xi.y, periodic, box);
@@ -154,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_walk64(WalkArgs A) {
                             (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
           if (!open) {
             pair64(dx, dy, dz, mm.m, bx, ax, ay, az, ph, ni);
-            next = leaf ? n + 1 : t.a;
+            next = ns;
           } else if (!leaf) {
             open_int = true;
             next = n + 1;
@@ -164,6 +294,7 @@ __global__ __launch_bounds__(kThreads) void k_walk64(WalkArgs A) {
           }
         }
       }
+      uint32_t nn;
       if (leaf) {
         if (__ballot(open_leaf)) {
           const uint32_t f = t.a, cnt = t.b & kCountMask;
@@ -182,31 +313,75 @@ __global__ __launch_bounds__(kThreads) void k_walk64(WalkArgs A) {
             }
           }
         }
-        n = n + 1;
+        nn = n + 1;
       } else {
-        n = (__ballot(open_int) || t.a <= n) ? n + 1 : t.a;
+        nn = (__ballot(open_int) || t.a <= n) ? n + 1 : t.a;
       }
+      const bool first_child = nn == n + 1;
+      t = first_child ? t1 : ts;
+      mm = first_child ? m1 : msk;
+      n = nn;
     }
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
 
 // ----------------------------------------------------------- mixed form --
-// Every lane works in FP32 offsets from its own origin `ref`, the centre of
-// the level-21 cell holding its target.  Node centres relative to ref come
-// from exact integer cell arithmetic (periodic minimum image on integers,
-// the box being 2^22 half-cells long); a node's centre of mass is its centre
-// plus the node's FP32 offset, a particle is its leaf centre plus its FP32
-// offset (both offsets formed in FP64 at build time); the target itself is
-// FP64 (x - ref) rounded once.  The origin depends on the target only, so
-// results do not depend on how targets are grouped.
+// Every lane works in FP32 offsets from its own origin, the centre of the
+// level-21 cell holding its target.  Cell indices (in half-cells, < 2^23)
+// are exact, so a node centre relative to a lane's origin is one exact
+// integer difference times the half-cell size; the periodic minimum image is
+// applied to that exact difference, and skipped for a node when a scalar
+// test shows that no lane of the group can need it.  A node's centre of
+// mass is its centre plus the node's FP32 offset, a particle is its leaf's
+// centre plus its FP32 offset (both offsets formed in FP64 at build time),
+// and the target is FP64 (x - origin) rounded once.  Node data comes from
+// 64-byte walk records (one scalar load each).
+//
+// Accepted partners are not evaluated at the node: each lane appends
+// (offset, mass) to its own list in LDS, in traversal order, and the lists
+// are evaluated lane-parallel when one of them is full and at the end of
+// the walk.  The per-target summation order is thus the traversal order,
+// and a lane evaluates only its own partners, so the interaction arithmetic
+// runs with (nearly) all lanes busy even though the lanes' decisions at a
+// node differ.  The per-lane decisions are computed without branches.
+constexpr int kWalk32Threads = 64;       // one wavefront per workgroup
+
 struct Consts32 {
-  float G, eps2, inv2rs, rcut, rc2, theta2, h22, L, half_box, box;
+  float G, eps2, inv2rs, rc2, theta2, h22, half_box, box;
   bool cutoff, periodic;
 };
 
-__device__ inline void pair32(float dx, float dy, float dz, float r2, float m, const Consts32 &k, double &ax,
-                              double &ay, double &az, double &ph, uint32_t &ni) {
+struct F4 {
+  float x, y, z, w;
+};
+
+__device__ inline WNode ldw(const WNode *p) {
+  const auto q = cptr(p);
+  WNode w;
+  w.c[0] = q->c[0];
+  w.c[1] = q->c[1];
+  w.c[2] = q->c[2];
+  w.side2 = q->side2;
+  w.o[0] = q->o[0];
+  w.o[1] = q->o[1];
+  w.o[2] = q->o[2];
+  w.m = q->m;
+  w.reach = q->reach;
+  w.near = q->near;
+  w.a = q->a;
+  w.cf = q->cf;
+  return w;
+}
+
+__device__ inline F4 ldp(const float4 *p) {
+  const auto q = cptr(reinterpret_cast<const F4 *>(p));
+  return F4{q->x, q->y, q->z, q->w};
+}
+
+__device__ inline void eval32(float dx, float dy, float dz, float m, const Consts32 &k, double &ax,
+                              double &ay, double &az, double &ph) {
+  const float r2 = dx * dx + dy * dy + dz * dz;
   const float rinv = __builtin_amdgcn_rsqf(r2 + k.eps2);
   float S = 1.0f, pf = 1.0f;
   if (k.cutoff) {
@@ -224,171 +399,216 @@ __device__ inline void pair32(float dx, float dy, float dz, float r2, float m, c
   ay += (double)(f * dy);
   az += (double)(f * dz);
   ph -= (double)(mr * pf);
-  ++ni;
 }
 
-__device__ inline int wrap_half_cells(int d, bool periodic) {
+__device__ inline int wrap_cells(int d) {
   // the periodic box is 2^22 half-cells long
-  if (periodic) {
-    if (d > (1 << 21)) d -= (1 << 22);
-    else if (d < -(1 << 21)) d += (1 << 22);
-  }
-  return d;
+  const int hi = d > (1 << 21) ? d - (1 << 22) : d;
+  return d < -(1 << 21) ? d + (1 << 22) : hi;
 }
 
 __device__ inline float wrap_box(float d, const Consts32 &k) {
-  if (d > k.half_box) return d - k.box;
-  if (d < -k.half_box) return d + k.box;
-  return d;
+  const float hi = d > k.half_box ? d - k.box : d;
+  return d < -k.half_box ? d + k.box : hi;
 }
 
-__global__ __launch_bounds__(kThreads) void k_walk32(WalkArgs A) {
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ inline int wave_min_i32(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ inline int wave_max_i32(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Evaluate and empty every lane's list.
+template <int kCap>
+__device__ inline void flush(float4 (*list)[kWalk32Threads], uint32_t lane, uint32_t &cnt, const Consts32 &k,
+                             double &ax, double &ay, double &az, double &ph) {
+  const uint32_t kmax = wave_max_u32(cnt);
+  for (uint32_t e = 0; e < kmax; ++e) {
+    if (e < cnt) {
+      const float4 q = list[e][lane];
+      eval32(q.x, q.y, q.z, q.w, k, ax, ay, az, ph);
+    }
+  }
+  cnt = 0;
+}
+
+// kMode: 0 = cutoff and periodicity read from each box; 1 = cutoff, open
+// boundaries; 2 = cutoff, periodic; 3 = plain Newtonian, open boundaries.
+template <int kCap, int kMode>  // list entries per lane; box kind
+__global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
 #pragma clang fp contract(fast)
-  const uint32_t lane = threadIdx.x & 63;
+  __shared__ float4 list[kCap][kWalk32Threads];
+  const uint32_t lane = threadIdx.x;
+  GroupQueue Q = make_queue(A);
   while (true) {
-    uint32_t g = 0;
-    if (lane == 0) g = atomicAdd(A.counter, 1u);
-    g = __shfl(g, 0, 64);
-    if (g >= *A.n_groups) break;
-    const Group gr = A.groups[g];
-    const BoxDev &bx = A.boxes[gr.box];
+    const uint32_t g = pop_group(Q, lane);
+    if (g >= A.n_groups) break;
+    const GroupRef gr = group_of(A, g);
+    const BoxDev bx = ld(A.boxes + gr.box);
+    const bool kCut = kMode == 0 ? bx.cutoff != 0 : kMode != 3;
+    const bool kPer = kMode == 0 ? bx.periodic != 0 : kMode == 2;
     Consts32 k;
     k.G = bx.Gf;
     k.eps2 = bx.eps2f;
     k.inv2rs = bx.inv2rsf;
-    k.rcut = bx.rcutf;
     k.rc2 = bx.rc2f;
     k.theta2 = bx.theta2f;
     k.h22 = bx.h22f;
-    k.L = bx.Lf;
     k.box = bx.Lf;
     k.half_box = 0.5f * bx.Lf;
-    k.cutoff = bx.cutoff;
-    k.periodic = bx.periodic;
+    k.cutoff = kCut;
+    k.periodic = kPer;
     uint32_t p = 0, slot = 0;
     const bool valid = lane_target(A, gr, bx, lane, p, slot);
     // lane origin: centre of the target's level-21 cell, in half-cells
-    int r0 = 0, r1 = 0, r2i = 0;
+    int o0 = 0, o1 = 0, o2 = 0;
     float xr = 0.0f, yr = 0.0f, zr = 0.0f;
     if (valid) {
       const uint64_t key = A.skeys[p];
-      r0 = 2 * (int)compact3(key >> 2) + 1;
-      r1 = 2 * (int)compact3(key >> 1) + 1;
-      r2i = 2 * (int)compact3(key) + 1;
+      o0 = 2 * (int)compact3(key >> 2) + 1;
+      o1 = 2 * (int)compact3(key >> 1) + 1;
+      o2 = 2 * (int)compact3(key) + 1;
       const double h22 = bx.L * 0x1p-22;
       const double4 q = A.part64[p];
-      xr = (float)(q.x - (bx.lo[0] + (double)r0 * h22));
-      yr = (float)(q.y - (bx.lo[1] + (double)r1 * h22));
-      zr = (float)(q.z - (bx.lo[2] + (double)r2i * h22));
+      xr = (float)(q.x - (bx.lo[0] + (double)o0 * h22));
+      yr = (float)(q.y - (bx.lo[1] + (double)o1 * h22));
+      zr = (float)(q.z - (bx.lo[2] + (double)o2 * h22));
+    }
+    // Minimum image test: with g the first lane's origin and e the largest
+    // |o - g| over the group's lanes, a node centre c with |c - g| <= 2^21 - e
+    // on every axis is within half a box of every lane's origin.
+    int g0 = __builtin_amdgcn_readfirstlane(o0), g1 = __builtin_amdgcn_readfirstlane(o1),
+        g2 = __builtin_amdgcn_readfirstlane(o2);
+    int thr = 0;
+    if (kPer) {
+      const int e = valid ? max(abs(o0 - g0), max(abs(o1 - g1), abs(o2 - g2))) : 0;
+      thr = (1 << 21) - wave_max_i32(e);
     }
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
-    uint32_t ni = 0;
+    uint32_t ni = 0, cnt = 0;
     uint32_t n = bx.root;
     const uint32_t nend = bx.node_end;
     uint32_t next = valid ? n : nend;
+    WNode w = ldw(A.wnode + n);
     while (n < nend) {
-      const Topo t = A.topo[n];
-      const Mom32 mm = A.mom32[n];
-      const bool leaf = (t.corner & kLeafBit) != 0;
-      const int lev = (int)(t.b >> kCountBits);
-      const int hc = 1 << (kLevels - lev);
-      const float side = ldexpf(k.L, -lev);
-      // offsets may need the minimum image once the node can reach half a box
-      const bool wrapd = k.periodic && (k.rcut + side >= k.half_box);
-      bool open_int = false, open_leaf = false;
-      float dcx = 0.0f, dcy = 0.0f, dcz = 0.0f;
-      if (next == n || leaf) {
-        const int d0 = wrap_half_cells(2 * (int)(t.corner & 0x1fffffull) + hc - r0, k.periodic);
-        const int d1 = wrap_half_cells(2 * (int)((t.corner >> 21) & 0x1fffffull) + hc - r1, k.periodic);
-        const int d2 = wrap_half_cells(2 * (int)((t.corner >> 42) & 0x1fffffull) + hc - r2i, k.periodic);
-        dcx = (float)d0 * k.h22 - xr;
-        dcy = (float)d1 * k.h22 - yr;
-        dcz = (float)d2 * k.h22 - zr;
+      const bool leaf = (w.cf & kWLeaf) != 0;
+      const uint32_t ns = leaf ? n + 1 : w.a;
+      const WNode wa = ldw(A.wnode + min(n + 1, nend - 1));
+      const WNode wb = ldw(A.wnode + min(ns, nend - 1));
+      if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap>(list, lane, cnt, k, ax, ay, az, ph);
+      int d0 = w.c[0] - o0, d1 = w.c[1] - o1, d2 = w.c[2] - o2;
+      if (kPer && (abs(w.c[0] - g0) > thr || abs(w.c[1] - g1) > thr || abs(w.c[2] - g2) > thr)) {
+        d0 = wrap_cells(d0);
+        d1 = wrap_cells(d1);
+        d2 = wrap_cells(d2);
       }
-      if (next == n) {
-        bool pruned = false;
-        if (k.cutoff) {
-          const float reach = k.rcut + 0.5f * side;
-          pruned = fabsf(dcx) > reach || fabsf(dcy) > reach || fabsf(dcz) > reach;
-        }
-        if (pruned) {
-          next = leaf ? n + 1 : t.a;
-        } else {
-          float dx = dcx + mm.ox, dy = dcy + mm.oy, dz = dcz + mm.oz;
-          if (wrapd) {
-            dx = wrap_box(dx, k);
-            dy = wrap_box(dy, k);
-            dz = wrap_box(dz, k);
-          }
-          const float r2 = dx * dx + dy * dy + dz * dz;
-          const float near = 0.6f * side;
-          const bool open = (side * side > k.theta2 * r2) ||
-                            (fabsf(dcx) < near && fabsf(dcy) < near && fabsf(dcz) < near);
-          if (!open) {
-            if (!k.cutoff || r2 < k.rc2) pair32(dx, dy, dz, r2, mm.m, k, ax, ay, az, ph, ni);
-            next = leaf ? n + 1 : t.a;
-          } else if (!leaf) {
-            open_int = true;
-            next = n + 1;
-          } else {
-            open_leaf = true;
-            next = n + 1;
-          }
-        }
+      const float dcx = (float)d0 * k.h22 - xr, dcy = (float)d1 * k.h22 - yr, dcz = (float)d2 * k.h22 - zr;
+      const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
+      float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
+      if (kPer && (w.cf & kWWrap)) {
+        dx = wrap_box(dx, k);
+        dy = wrap_box(dy, k);
+        dz = wrap_box(dz, k);
       }
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const bool act = next == n;
+      const bool live = act && !(kCut && mdc > w.reach);
+      const bool open = (w.side2 > k.theta2 * r2) || (mdc < w.near);
+      const bool contrib = live && !open && (!kCut || r2 < k.rc2);
+      const bool open_here = live && open;
+      list[cnt][lane] = make_float4(dx, dy, dz, w.m);
+      cnt += contrib ? 1u : 0u;
+      ni += contrib ? 1u : 0u;
+      next = act ? (open_here ? n + 1 : ns) : next;
+      uint32_t nn;
       if (leaf) {
-        if (__ballot(open_leaf)) {
-          const uint32_t f = t.a, cnt = t.b & kCountMask;
-          for (uint32_t base = 0; base < cnt; base += 64) {
-            float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (base + lane < cnt) q = A.part32[f + base + lane];
-            const uint32_t m = min(64u, cnt - base);
-            for (uint32_t j = 0; j < m; ++j) {
-              const float qx = rdl(q.x, j), qy = rdl(q.y, j), qz = rdl(q.z, j), qm = rdl(q.w, j);
-              if (open_leaf && f + base + j != p) {
-                float dx = dcx + qx, dy = dcy + qy, dz = dcz + qz;
+        if (__ballot(open_here)) {
+          const uint32_t f = w.a, lc = w.cf & kWCount;
+          const bool wrapd = kPer && (w.cf & kWWrap) != 0;
+          for (uint32_t j0 = 0; j0 < lc; j0 += 8) {
+            F4 q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[i] = ldp(A.part32 + f + min(j0 + i, lc - 1));
+            const uint32_t m = min(8u, lc - j0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              if ((uint32_t)i < m) {
+                if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap>(list, lane, cnt, k, ax, ay, az, ph);
+                float px = dcx + q[i].x, py = dcy + q[i].y, pz = dcz + q[i].z;
                 if (wrapd) {
-                  dx = wrap_box(dx, k);
-                  dy = wrap_box(dy, k);
-                  dz = wrap_box(dz, k);
+                  px = wrap_box(px, k);
+                  py = wrap_box(py, k);
+                  pz = wrap_box(pz, k);
                 }
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (!k.cutoff || r2 < k.rc2) pair32(dx, dy, dz, r2, qm, k, ax, ay, az, ph, ni);
+                const float s2 = px * px + py * py + pz * pz;
+                const bool c = open_here && (f + j0 + (uint32_t)i != p) && (!kCut || s2 < k.rc2);
+                list[cnt][lane] = make_float4(px, py, pz, q[i].w);
+                cnt += c ? 1u : 0u;
+                ni += c ? 1u : 0u;
               }
             }
           }
         }
-        n = n + 1;
+        nn = n + 1;
       } else {
-        n = (__ballot(open_int) || t.a <= n) ? n + 1 : t.a;
+        nn = (__ballot(open_here) || ns <= n) ? n + 1 : ns;
       }
+      w = nn == n + 1 ? wa : wb;
+      n = nn;
     }
+    flush<kCap>(list, lane, cnt, k, ax, ay, az, ph);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
 
-int g_blocks[2] = {0, 0};
-
 }  // namespace
 
-void launch_walk(const WalkArgs &W, int precision, uint32_t max_groups, hipStream_t s) {
-  const int which = precision == 0 ? 0 : 1;
-  if (g_blocks[which] == 0) {
-    int per_cu = 0;
-    hipError_t e = which == 0
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk64, kThreads, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk32, kThreads, 0);
-    if (e != hipSuccess || per_cu <= 0) per_cu = 2;
-    g_blocks[which] = per_cu * device_cu_count();
+int walk_list_capacity() {
+  static int cap = -1;
+  if (cap < 0) {
+    const char *e = getenv("OG_WALK_LIST_CAP");
+    const int v = e ? atoi(e) : 0;
+    cap = (v == 8 || v == 16 || v == 32) ? v : 8;
   }
-  uint32_t waves_needed = max_groups > 0 ? max_groups : 1;
-  uint32_t blocks = std::min<uint32_t>((uint32_t)g_blocks[which], (waves_needed + 3) / 4);
-  if (blocks == 0) blocks = 1;
-  launch_reset(W.counter, s);
-  if (which == 0)
-    k_walk64<<<blocks, kThreads, 0, s>>>(W);
-  else
-    k_walk32<<<blocks, kThreads, 0, s>>>(W);
+  return cap;
+}
+
+void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
+  const uint32_t cus = (uint32_t)device_cu_count();
+  const uint32_t groups = W.n_groups > 0 ? W.n_groups : 1;
+  launch_reset_n(W.counter, kQueues, s);
+  if (precision == 0) {
+    // 4 waves per workgroup; this kernel's registers allow 3 waves per SIMD
+    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(3u * cus, (groups + 3) / 4));
+    k_walk64<<<blocks, 256, 0, s>>>(W);
+  } else {
+    // one wave per workgroup; LDS per wave = cap x 1 KB of lists
+    const int cap = walk_list_capacity();
+    const uint32_t per_cu = std::min<uint32_t>(32u, 160u / (uint32_t)cap);
+    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(per_cu * cus, groups));
+    const int mode = W.box_kind;
+#define OG_WALK32(C)                                                          \
+  do {                                                                        \
+    if (mode == 2) k_walk32<C, 2><<<blocks, kWalk32Threads, 0, s>>>(W);       \
+    else if (mode == 1) k_walk32<C, 1><<<blocks, kWalk32Threads, 0, s>>>(W);  \
+    else if (mode == 3) k_walk32<C, 3><<<blocks, kWalk32Threads, 0, s>>>(W);  \
+    else k_walk32<C, 0><<<blocks, kWalk32Threads, 0, s>>>(W);                 \
+  } while (0)
+    if (cap == 8) OG_WALK32(8);
+    else if (cap == 32) OG_WALK32(32);
+    else OG_WALK32(16);
+#undef OG_WALK32
+  }
 }
 
 }  // namespace og

@@ -84,15 +84,15 @@ void carve(Carver &c, BuildArrays &A, uint32_t n, uint32_t node_cap, int B) {
   A.topo = c.take<Topo>(node_cap);
   A.mom64 = c.take<Mom64>(node_cap);
   A.mom32 = c.take<Mom32>(node_cap);
+  A.wnode = c.take<WNode>(node_cap);
   A.first = c.take<uint32_t>(node_cap);
   A.skip = c.take<uint32_t>(node_cap);
   A.parent = c.take<uint32_t>(node_cap);
   A.nchild = c.take<uint32_t>(node_cap);
-  A.arrive = c.take<uint32_t>(node_cap);
-  A.ng = c.take<uint32_t>(node_cap);
-  A.goff = c.take<uint32_t>(node_cap + 1ull);
-  A.groups = c.take<Group>(n);
-  A.scalars = c.take<uint32_t>(16);
+  A.lvl_cnt = c.take<uint32_t>(32);
+  A.lvl_fill = c.take<uint32_t>(32);
+  A.lvl_nodes = c.take<uint32_t>(node_cap);
+  A.scalars = c.take<uint32_t>(32);
 }
 }  // namespace
 
@@ -180,6 +180,13 @@ int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream
   precision = prec;
   group_max = gmax > 0 ? (uint32_t)gmax : 64u;
   hboxes = boxes;
+  // walk groups: chunks of group_max consecutive sorted particles per box
+  uint64_t gtot = 0;
+  for (auto &b : hboxes) {
+    b.g_off = (uint32_t)gtot;
+    gtot += (b.n + group_max - 1) / group_max;
+  }
+  n_groups = (uint32_t)gtot;
   bytes = forest_bytes(N, node_cap, B);
   if (workspace) {
     if (!is_device_ptr(workspace)) return fail(OG_EINVAL, "workspace is not device memory");
@@ -200,7 +207,6 @@ int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream
   A.B = B;
   A.n = N;
   A.node_cap = node_cap;
-  A.group_max = group_max;
   A.any_open = 0;
   for (auto &b : hboxes) A.any_open |= b.periodic ? 0 : 1;
   hipError_t e = hipMemcpyAsync(A.boxes, hboxes.data(), sizeof(BoxDev) * B, hipMemcpyHostToDevice, stream);
@@ -215,24 +221,35 @@ int Forest::build() {
   return OG_OK;
 }
 
-int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint) {
+WalkArgs Forest::walk_args() const {
   WalkArgs W{};
   W.boxes = A.boxes;
   W.topo = A.topo;
   W.mom32 = A.mom32;
+  W.wnode = A.wnode;
   W.mom64 = A.mom64;
   W.part32 = A.part32;
   W.part64 = A.part64;
   W.perm = A.perm;
   W.skeys = A.keys_a;
-  W.groups = A.groups;
-  W.n_groups = &A.scalars[1];
-  W.counter = &A.scalars[2];
+  W.chunk = group_max;
+  W.B = B;
+  auto kind = [](const BoxDev &b) { return b.cutoff ? (b.periodic ? 2 : 1) : 3; };
+  W.box_kind = kind(hboxes[0]);
+  for (const auto &b : hboxes)
+    if (kind(b) != W.box_kind) W.box_kind = 0;
+  W.counter = &A.scalars[8];
+  return W;
+}
+
+int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint) {
+  WalkArgs W = walk_args();
+  W.n_groups = n_groups;
   W.acc = acc;
   W.pot = pot;
   W.pot_override = pot_override;
   W.nint = nint;
-  launch_walk(W, prec, N, s);
+  launch_walk(W, prec, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "walk launch");
   return OG_OK;
@@ -240,7 +257,6 @@ int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_
 
 int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
                         int64_t *nint) {
-  Carver c;
   TargetArrays T{};
   auto plan = [&](Carver &cv) {
     T.tkey_a = cv.take<uint64_t>(M);
@@ -249,12 +265,9 @@ int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M,
     T.tval_b = cv.take<uint32_t>(M);
     T.hist = cv.take<uint32_t>(radix_hist_words(M));
     T.digit_tot = cv.take<uint32_t>(256);
-    T.ng = cv.take<uint32_t>(node_cap);
-    T.goff = cv.take<uint32_t>(node_cap + 1ull);
-    T.scan_partial = cv.take<uint32_t>(node_cap / kScanTile + 4);
-    T.groups = cv.take<Group>(M);
-    T.scalars = cv.take<uint32_t>(16);
+    T.scalars = cv.take<uint32_t>(32);
   };
+  Carver c;
   plan(c);
   void *tmp = nullptr;
   hipError_t e = hipMallocAsync(&tmp, c.off + 256, s);
@@ -265,25 +278,17 @@ int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M,
   T.idx = idx;
   T.M = M;
   launch_targets(A, T, s);
-  WalkArgs W{};
-  W.boxes = A.boxes;
-  W.topo = A.topo;
-  W.mom32 = A.mom32;
-  W.mom64 = A.mom64;
-  W.part32 = A.part32;
-  W.part64 = A.part64;
-  W.perm = A.perm;
-  W.skeys = A.keys_a;
-  W.groups = T.groups;
-  W.n_groups = &T.scalars[1];
-  W.counter = &T.scalars[2];
+  WalkArgs W = walk_args();
+  W.n_groups = (M + group_max - 1) / group_max;
+  W.n_targets = M;
+  W.counter = &T.scalars[8];
   W.tkey = T.tkey;
   W.tval = T.tval;
   W.acc = acc;
   W.pot = pot;
   W.pot_override = 1;
   W.nint = nint;
-  launch_walk(W, prec, M, s);
+  launch_walk(W, prec, s);
   e = hipGetLastError();
   hipError_t e2 = hipFreeAsync(tmp, s);
   if (e != hipSuccess) return hip_fail(e, "walk launch (targets)");

@@ -29,6 +29,7 @@ struct Forest {
   hipStream_t own_stream = nullptr;  // private capture stream when `stream` is the null stream
   int precision = OG_PREC_MIXED;
   uint32_t group_max = 64;
+  uint32_t n_groups = 0;
   void *mem = nullptr;
   size_t bytes = 0;
   bool own = false;
@@ -39,6 +40,7 @@ struct Forest {
   int init(const std::vector<BoxDev> &boxes, uint64_t node_cap, hipStream_t s, int prec, int gmax,
            void *workspace, size_t ws_bytes);
   int build();
+  WalkArgs walk_args() const;
   int walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint);
   int walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
                   int64_t *nint);

@@ -36,7 +36,8 @@ struct BoxDev {
   float Gf, eps2f, inv2rsf, rcutf, rc2f, theta2f, Lf, h22f;
   uint32_t p_off, n;     // particle range
   uint32_t root, node_end;  // node range, written on the device
-  int32_t periodic, cutoff, leaf_max, pad;
+  int32_t periodic, cutoff, leaf_max;
+  uint32_t g_off;          // first walk group of this box
 };
 
 // Walk-order node record, 16 bytes.
@@ -58,11 +59,22 @@ struct __attribute__((aligned(16))) Mom32 {
   float ox, oy, oz, m;
 };
 
-// Walk group: up to 64 targets inside node `node` of box `box`; targets are
-// entries [tstart, tstart + tcount) of the sorted target list (or sorted
-// particle positions when every particle is a target).
-struct __attribute__((aligned(16))) Group {
-  uint32_t node, tstart, tcount, box;
+// Walk record of a node for the mixed-precision walk, 48 bytes (scalar
+// loads): everything the per-node decisions need, precomputed in FP32.
+//   c[3]:   cube centre in half-cells of the level-21 grid (exact integers)
+//   side2:  side^2;  reach: r_cut + side/2;  near: 0.6 side
+//   o[3]:   centre of mass minus cube centre;  m: mass
+//   a:      leaf ? first particle : skip (the next node after the subtree)
+//   cf:     particle count | kWLeaf | kWWrap (offsets inside the node may
+//           need the minimum image)
+constexpr uint32_t kWLeaf = 1u << 30, kWWrap = 1u << 31, kWCount = (1u << 30) - 1u;
+struct __attribute__((aligned(16))) WNode {
+  int32_t c[3];
+  float side2;
+  float o[3];
+  float m;
+  float reach, near;
+  uint32_t a, cf;
 };
 
 // ---- bit helpers ------------------------------------------------------

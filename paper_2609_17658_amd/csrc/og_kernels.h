@@ -40,29 +40,26 @@ struct BuildArrays {
   Topo *topo;
   Mom64 *mom64;
   Mom32 *mom32;
-  uint32_t *first, *skip, *parent, *nchild, *arrive;
-  uint32_t *ng, *goff;
-  Group *groups;
-  uint32_t *scalars;          // [0] status [1] n_groups [2] walk counter [3] n_nodes [4] n
+  WNode *wnode;
+  uint32_t *first, *skip, *parent, *nchild;
+  uint32_t *lvl_cnt, *lvl_fill, *lvl_nodes;   // internal nodes bucketed by level
+  uint32_t *scalars;          // [0] status [3] n_nodes [4] n [8..15] walk queues
                               // [5] deepest level (stats)
   int any_open;               // some box has periodic = 0
-  uint32_t group_max;
 };
 
 void launch_build(BuildArrays &A, hipStream_t s);
 void launch_max_level(const BuildArrays &A, uint32_t *out, hipStream_t s);
 
-// Targets given as caller-order indices (per the single box 0): builds the
-// sorted target list and the walk groups for them.
+// Targets given as caller-order indices (box 0 only): the target list
+// sorted by tree position (so that consecutive targets are neighbours).
 struct TargetArrays {
   const int64_t *idx;
   uint32_t M;
   uint64_t *tkey_a, *tkey_b;
   uint32_t *tval_a, *tval_b;
   uint32_t *hist, *digit_tot;
-  uint32_t *ng, *goff, *scan_partial;
-  Group *groups;
-  uint32_t *scalars;          // [0] status [1] n_groups [2] walk counter
+  uint32_t *scalars;          // [0] status [8..15] walk queues
   const uint64_t *tkey;       // result (points at a or b)
   const uint32_t *tval;
 };
@@ -72,14 +69,19 @@ struct WalkArgs {
   const BoxDev *boxes;
   const Topo *topo;
   const Mom32 *mom32;
+  const WNode *wnode;
   const Mom64 *mom64;
   const float4 *part32;
   const double4 *part64;
   const uint32_t *perm;
   const uint64_t *skeys;      // sorted Morton keys
-  const Group *groups;
-  const uint32_t *n_groups;
-  uint32_t *counter;
+  uint32_t n_groups;          // walk groups (chunks of `chunk` targets)
+  uint32_t chunk;             // targets per group, <= 64
+  uint32_t n_targets;         // length of the target list (tkey != null)
+  int B;                      // boxes
+  int box_kind;               // shared by all boxes: 1 cutoff+open, 2 cutoff+periodic,
+                              // 3 Newtonian+open; 0 mixed
+  uint32_t *counter;          // kQueues group counters
   const uint64_t *tkey;       // sorted target positions, or null: all particles
   const uint32_t *tval;       // target slots
   double *acc;                // non-null: outputs by slot; null: per-box acc/pot
@@ -87,8 +89,12 @@ struct WalkArgs {
   int64_t *nint;
   int pot_override;           // 1: use `pot` (possibly null) instead of the box's
 };
-void launch_walk(const WalkArgs &W, int precision, uint32_t max_groups, hipStream_t s);
+void launch_walk(const WalkArgs &W, int precision, hipStream_t s);
 void launch_reset(uint32_t *word, hipStream_t s);
+void launch_reset_n(uint32_t *words, int n, hipStream_t s);
+
+// Walk group queues: one per XCD (see k_walk.hip).
+constexpr uint32_t kQueues = 8;
 
 int device_cu_count();
 
