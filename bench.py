@@ -47,6 +47,26 @@ def build_bytes(n, n_nodes, n_groups_bound=None):
     return per_particle * n + per_node * n_nodes
 
 
+def walk_traffic_bytes():
+    """HBM bytes per walk launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    scaled by a 1 GiB copy), valid only while the walk source is unchanged."""
+    import hashlib
+    try:
+        rec = {}
+        with open(os.path.join(ROOT, "profiles", "k_walk32_mixture2m_traffic.txt")) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    rec[k.strip()] = v.strip()
+        with open(os.path.join(ROOT, "paper_2609_17658_amd", "csrc", "k_walk.hip"), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+        if rec.get("source_sha256") != h:
+            return None
+        return float(rec["walk_traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def git_hash():
     try:
         return subprocess.run(["git", "-C", ROOT, "rev-parse", "--short", "HEAD"], capture_output=True,
@@ -198,7 +218,9 @@ def main():
         "roofline": {
             "bound": "alu", "kernel": "k_walk32 (mixed walk)",
             "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32, "traffic": None,
+            "frac": achieved / PEAK_FP32, "traffic": walk_traffic_bytes(),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
+            "peak_unpacked_fp32": 78.6,
             "flop_per_interaction": FLOP_PER_INTERACTION, "interactions": inter_m,
         },
         "roofline_build": {

@@ -1,0 +1,66 @@
+"""Small drivers for hardware-counter runs (run under rocprofv3).
+
+  python paper_2609_17658_amd/profiling.py walk --prec mixed --reps 3
+      builds the 2M-particle mixture tree once and runs the force walk
+      `reps` times (the build kernels run once, the walk kernel `reps` times);
+  python paper_2609_17658_amd/profiling.py copy --mib 1024 --reps 3
+      device-to-device copy of a buffer of known size, the reference for
+      scaling FETCH_SIZE / WRITE_SIZE readings to bytes.
+"""
+import argparse
+import os
+import sys
+
+if __package__ in (None, ""):  # run as a file (profilers exec the script path)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+
+def _walk(prec: str, reps: int, workload: str):
+    import torch
+
+    from paper_2609_17658_amd import og, synth
+
+    w = synth.WORKLOADS[workload]()
+    dev = torch.device("cuda:0")
+    tp = torch.as_tensor(w.pos, device=dev)
+    tm = torch.as_tensor(w.mass, device=dev)
+    t = og.Tree(tp, tm, w.box, w.params.as_dict(), stream=torch.cuda.current_stream())
+    for _ in range(reps):
+        t.force(precision=prec)
+    torch.cuda.synchronize()
+    t.close()
+    print("walk %s x%d on %s: done" % (prec, reps, workload), flush=True)
+
+
+def _copy(mib: int, reps: int):
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy %d MiB x%d: done" % (mib, reps), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    w = sub.add_parser("walk")
+    w.add_argument("--prec", default="mixed")
+    w.add_argument("--reps", type=int, default=3)
+    w.add_argument("--workload", default="mixture2m")
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=1024)
+    c.add_argument("--reps", type=int, default=3)
+    a = ap.parse_args(argv)
+    if a.cmd == "walk":
+        _walk(a.prec, a.reps, a.workload)
+    else:
+        _copy(a.mib, a.reps)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
