@@ -84,13 +84,16 @@ typedef struct og_params {
     int32_t precision;      /* OG_PREC_FP64 or OG_PREC_MIXED (default MIXED) */
     int32_t group_max;      /* targets per wavefront group, 1..64, 0 = 64;
                                the result does not depend on it */
+    int32_t walk_list_cap;  /* mixed walk: accepted partners buffered per
+                               target before evaluation, 8, 16 or 32; 0 =
+                               default (8); the result does not depend on it */
     void *stream;           /* hipStream_t, NULL = default stream */
     void *workspace;        /* optional caller device buffer for the tree */
     size_t workspace_bytes; /* its size; must be >= og_tree_workspace_bound */
 } og_params;
 
 /* Defaults: G 1, eps 0, r_s 0, r_cut 0, theta 0.5, periodic 1, leaf_max 8,
- * MIXED, group_max 0, no stream, no workspace. */
+ * MIXED, group_max 0, walk_list_cap 0, no stream, no workspace. */
 void og_params_default(og_params *p);
 
 /* Device bytes one tree over N particles needs (upper bound, independent of
@@ -109,7 +112,8 @@ typedef struct og_tree og_tree;
  * device: the tree is then marked and og_tree_status reports OG_ERANGE;
  * the keys of such particles are clamped so that every kernel stays in
  * bounds.  Errors: OG_EINVAL (N < 1 or > 2^27-1, box <= 0, eps < 0,
- * theta < 0, leaf_max outside 1..4096, group_max outside 0..64, periodic
+ * theta < 0, leaf_max outside 1..4096, group_max outside 0..64,
+ * walk_list_cap not 0, 8, 16 or 32, periodic
  * with r_s <= 0 or r_cut >= box/2, null pointers, host pointers),
  * OG_ENOMEM, OG_EDEVICE. */
 int og_tree_build(const double *pos, const double *mass, int64_t N, double box,
@@ -172,7 +176,8 @@ typedef struct og_box {
     int64_t N;
     double box;
     og_params params;    /* per box; stream/workspace fields ignored;
-                            precision and group_max taken from box 0 */
+                            precision, group_max and walk_list_cap must
+                            equal box 0's */
     double *acc;         /* device [N][3] output, caller order */
     double *pot;         /* device [N] output or NULL */
 } og_box;

@@ -593,7 +593,7 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
     k_walk64<<<blocks, 256, 0, s>>>(W);
   } else {
     // one wave per workgroup; LDS per wave = cap x 1 KB of lists
-    const int cap = walk_list_capacity();
+    const int cap = W.list_cap > 0 ? W.list_cap : walk_list_capacity();
     const uint32_t per_cu = std::min<uint32_t>(32u, 160u / (uint32_t)cap);
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(per_cu * cus, groups));
     const int mode = W.box_kind;

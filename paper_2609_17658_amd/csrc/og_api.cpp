@@ -118,6 +118,8 @@ int check_params(const og_params *p, int64_t N, double box, bool need_stream_fie
   if (!std::isfinite(p->G)) return fail(OG_EINVAL, "G must be finite");
   if (p->leaf_max < 1 || p->leaf_max > 4096) return fail(OG_EINVAL, "leaf_max outside 1..4096");
   if (p->group_max < 0 || p->group_max > 64) return fail(OG_EINVAL, "group_max outside 0..64");
+  if (p->walk_list_cap != 0 && p->walk_list_cap != 8 && p->walk_list_cap != 16 && p->walk_list_cap != 32)
+    return fail(OG_EINVAL, "walk_list_cap must be 0, 8, 16 or 32");
   if (p->precision != OG_PREC_FP64 && p->precision != OG_PREC_MIXED)
     return fail(OG_EINVAL, "unknown precision %d", p->precision);
   if (!std::isfinite(p->r_s) || !std::isfinite(p->r_cut) || p->r_cut < 0.0)
@@ -233,6 +235,7 @@ WalkArgs Forest::walk_args() const {
   W.perm = A.perm;
   W.skeys = A.keys_a;
   W.chunk = group_max;
+  W.list_cap = list_cap;
   W.B = B;
   auto kind = [](const BoxDev &b) { return b.cutoff ? (b.periodic ? 2 : 1) : 3; };
   W.box_kind = kind(hboxes[0]);
@@ -331,6 +334,12 @@ struct og_batch {
   std::vector<og_box> boxes;
 };
 
+void og::tree_free_nosync(og_tree *t) {
+  if (!t) return;
+  t->F.release();
+  delete t;
+}
+
 extern "C" {
 
 void og_params_default(og_params *p) {
@@ -361,6 +370,7 @@ int og_tree_build(const double *pos, const double *mass, int64_t N, double box, 
   if (!t) return fail(OG_ENOMEM, "host allocation");
   std::vector<BoxDev> boxes(1);
   fill_box(boxes[0], pos, mass, N, box, *params, 0);
+  t->F.list_cap = params->walk_list_cap;
   rc = t->F.init(boxes, node_bound((uint64_t)N, params->leaf_max), (hipStream_t)params->stream,
                  params->precision, params->group_max, params->workspace, params->workspace_bytes);
   if (rc == OG_OK) rc = t->F.build();
@@ -498,8 +508,9 @@ int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out)
     if (!is_device_ptr(x.pos) || !is_device_ptr(x.mass) || !is_device_ptr(x.acc) ||
         (x.pot && !is_device_ptr(x.pot)))
       return fail(OG_EINVAL, "box %d: pos/mass/acc/pot must be device pointers", b);
-    if (x.params.precision != boxes[0].params.precision || x.params.group_max != boxes[0].params.group_max)
-      return fail(OG_EINVAL, "box %d: precision and group_max must match box 0", b);
+    if (x.params.precision != boxes[0].params.precision || x.params.group_max != boxes[0].params.group_max ||
+        x.params.walk_list_cap != boxes[0].params.walk_list_cap)
+      return fail(OG_EINVAL, "box %d: precision, group_max and walk_list_cap must match box 0", b);
     if (off + (uint64_t)x.N > kCountMask) return fail(OG_EINVAL, "batch exceeds 2^27-1 particles");
     fill_box(hb[b], x.pos, x.mass, x.N, x.box, x.params, (uint32_t)off);
     hb[b].acc = x.acc;
@@ -510,6 +521,7 @@ int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out)
   og_batch *bt = new (std::nothrow) og_batch();
   if (!bt) return fail(OG_ENOMEM, "host allocation");
   bt->boxes.assign(boxes, boxes + B);
+  bt->F.list_cap = boxes[0].params.walk_list_cap;
   int rc = bt->F.init(hb, cap, (hipStream_t)stream, boxes[0].params.precision, boxes[0].params.group_max,
                       nullptr, 0);
   if (rc == OG_OK) rc = bt->F.build();

@@ -30,6 +30,7 @@ struct Forest {
   int precision = OG_PREC_MIXED;
   uint32_t group_max = 64;
   uint32_t n_groups = 0;
+  int list_cap = 0;  // mixed walk list capacity (0 = default)
   void *mem = nullptr;
   size_t bytes = 0;
   bool own = false;
@@ -47,5 +48,8 @@ struct Forest {
   int read_status(hipStream_t s);
   void release();
 };
+
+// Free a tree whose queued work is known to be complete (no stream sync).
+void tree_free_nosync(og_tree *t);
 
 }  // namespace og

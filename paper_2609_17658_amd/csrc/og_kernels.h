@@ -77,6 +77,7 @@ struct WalkArgs {
   const uint64_t *skeys;      // sorted Morton keys
   uint32_t n_groups;          // walk groups (chunks of `chunk` targets)
   uint32_t chunk;             // targets per group, <= 64
+  int list_cap;               // mixed walk list entries per lane (0 = default)
   uint32_t n_targets;         // length of the target list (tkey != null)
   int B;                      // boxes
   int box_kind;               // shared by all boxes: 1 cutoff+open, 2 cutoff+periodic,

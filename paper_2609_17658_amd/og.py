@@ -27,7 +27,7 @@ class og_params(ctypes.Structure):
                 ("r_s", ctypes.c_double), ("r_cut", ctypes.c_double), ("theta", ctypes.c_double),
                 ("periodic", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("group_max", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("walk_list_cap", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -352,7 +352,7 @@ def box_struct(pos, mass, box, params, acc, pot=None) -> og_box:
 class Batch:
     """B independent boxes built and walked by one set of launches."""
 
-    def __init__(self, items, stream=None, precision="mixed", group_max=0):
+    def __init__(self, items, stream=None, precision="mixed", group_max=0, walk_list_cap=0):
         """items: list of (pos, mass, box, params) with device tensors."""
         import torch
         self.outputs = []
@@ -360,7 +360,8 @@ class Batch:
         for pos, mass, box, params in items:
             acc = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
             pot = torch.empty(pos.shape[0], dtype=torch.float64, device=pos.device)
-            p = make_params(params, precision=precision, group_max=group_max)
+            p = make_params(params, precision=precision, group_max=group_max,
+                            walk_list_cap=walk_list_cap)
             structs.append(box_struct(pos, mass, box, p, acc, pot))
             self.outputs.append((acc, pot))
         self._keep = items
@@ -381,6 +382,59 @@ class Batch:
         if getattr(self, "handle", None):
             og_batch_free(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Server:
+    """Continuous-batching server (og_server_*): requests are admitted as
+    memory and stream slots free up, and trees stay resident until release."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4):
+        self.handle = og_server_create(hbm_budget_bytes, max_slots)
+        self._keep = {}
+
+    def submit(self, pos, mass, box, params, precision="mixed", group_max=0, walk_list_cap=0,
+               acc=None, pot=None):
+        import torch
+        if acc is None:
+            acc = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
+        if pot is None:
+            pot = torch.empty(pos.shape[0], dtype=torch.float64, device=pos.device)
+        p = make_params(params, precision=precision, group_max=group_max, walk_list_cap=walk_list_cap)
+        t = og_server_submit(self.handle, box_struct(pos, mass, box, p, acc, pot))
+        self._keep[t] = (pos, mass, acc, pot)
+        return t
+
+    def poll(self, ticket):
+        return og_server_poll(self.handle, ticket)
+
+    def progress(self):
+        og_server_progress(self.handle)
+
+    def wait(self, ticket):
+        og_server_wait(self.handle, ticket)
+
+    def result(self, ticket):
+        _, _, acc, pot = self._keep[ticket]
+        return acc, pot
+
+    def release(self, ticket):
+        og_server_release(self.handle, ticket)
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        return og_server_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            og_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -116,9 +116,9 @@ def zeldovich(n_grid: int, seed: int, rms_cells: float = 0.3, box: float = 1.0) 
     del amp
     q1 = (np.arange(n) + 0.5) * box / n
     psi = np.empty((n, n, n, 3))
-    psi[..., 0] = np.fft.irfftn(1j * kx * dk, s=(n, n, n))
-    psi[..., 1] = np.fft.irfftn(1j * ky * dk, s=(n, n, n))
-    psi[..., 2] = np.fft.irfftn(1j * kzz * dk, s=(n, n, n))
+    psi[..., 0] = np.fft.irfftn(1j * kx * dk, s=(n, n, n), axes=(0, 1, 2))
+    psi[..., 1] = np.fft.irfftn(1j * ky * dk, s=(n, n, n), axes=(0, 1, 2))
+    psi[..., 2] = np.fft.irfftn(1j * kzz * dk, s=(n, n, n), axes=(0, 1, 2))
     del dk
     rms = math.sqrt(float(np.mean(np.sum(psi * psi, axis=-1))))
     psi *= (rms_cells * box / n) / rms

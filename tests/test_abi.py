@@ -30,10 +30,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_default_and_struct_layout():
     p = og.og_params_default()
-    assert p.struct_size == ctypes.sizeof(og.og_params) == 88
+    assert p.struct_size == ctypes.sizeof(og.og_params) == 96
     assert (p.G, p.eps, p.r_s, p.r_cut, p.theta) == (1.0, 0.0, 0.0, 0.0, 0.5)
-    assert (p.periodic, p.leaf_max, p.precision, p.group_max) == (1, 8, og.OG_PREC_MIXED, 0)
-    assert ctypes.sizeof(og.og_box) == 8 + 8 + 8 + 8 + 88 + 8 + 8
+    assert (p.periodic, p.leaf_max, p.precision, p.group_max, p.walk_list_cap) == (1, 8, og.OG_PREC_MIXED, 0, 0)
+    assert ctypes.sizeof(og.og_box) == 8 + 8 + 8 + 8 + 96 + 8 + 8
     assert ctypes.sizeof(og.og_force_opts) == 24
 
 
@@ -52,7 +52,7 @@ def test_workspace_bound_monotone_and_rejects_bad_input():
 
 @pytest.mark.parametrize("field,value", [
     ("eps", -1.0), ("theta", -0.1), ("leaf_max", 0), ("leaf_max", 5000), ("group_max", 65),
-    ("precision", 7), ("r_s", 0.0), ("r_cut", 0.6),
+    ("precision", 7), ("r_s", 0.0), ("r_cut", 0.6), ("walk_list_cap", 12),
 ])
 def test_build_rejects_bad_params_on_host(field, value):
     lib = og.load()

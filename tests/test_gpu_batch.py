@@ -1,0 +1,119 @@
+"""Batched boxes: one set of launches over many independent boxes of uneven
+size and parameters.  Each box's result must equal the result of building
+and walking that box alone (bitwise: the same per-lane walk and the same
+arithmetic), for the eager path and for replays of the captured graph;
+replays re-read positions, so a changed input gives the changed result."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_17658_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def og_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_17658_amd import og
+    og.load()
+    return og
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _boxes(n_boxes, seed, nmin=50, nmax=6000, periodic=True):
+    rng = np.random.default_rng(seed)
+    sizes = np.round(np.exp(rng.uniform(np.log(nmin), np.log(nmax), n_boxes))).astype(int)
+    items = []
+    for b, n in enumerate(sizes):
+        n = int(n)
+        pos = synth.mixture_box(n, 5000 + b)
+        mass = rng.uniform(0.5, 1.5, n) / n
+        prm = synth.scale_free_params(max(n, 1000), theta=[0.3, 0.5, 0.7][b % 3],
+                                      leaf_max=[8, 4, 16][b % 3]).as_dict()
+        if not periodic and b % 2:
+            prm.update(periodic=0)
+        items.append((pos, mass, 1.0, prm))
+    return items
+
+
+def _alone(og, pos, mass, box, prm, prec):
+    tp = torch.as_tensor(pos, device="cuda")
+    tm = torch.as_tensor(mass, device="cuda")
+    t = og.Tree(tp, tm, box, prm, stream=torch.cuda.current_stream())
+    a, p = t.force(precision=prec)
+    torch.cuda.synchronize()
+    t.close()
+    return a.cpu().numpy(), p.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_batch_equals_alone(og_mod, prec):
+    items = _boxes(24, 11)
+    _note("batch of %d boxes, %d particles (%s)" % (len(items), sum(i[0].shape[0] for i in items), prec))
+    dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), b, prm)
+           for p, m, b, prm in items]
+    bt = og_mod.Batch(dev, stream=torch.cuda.current_stream(), precision=prec)
+    outs = bt.force()
+    torch.cuda.synchronize()
+    assert bt.status() == 0
+    for (pos, mass, box, prm), (a, p) in zip(items, outs):
+        ra, rp = _alone(og_mod, pos, mass, box, prm, prec)
+        assert np.array_equal(a.cpu().numpy(), ra)
+        assert np.array_equal(p.cpu().numpy(), rp)
+    bt.close()
+
+
+def test_batch_mixed_kinds_matches_alone(og_mod):
+    """Periodic and open boxes in one batch (generic walk variant)."""
+    items = _boxes(10, 12, periodic=False)
+    dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), b, prm)
+           for p, m, b, prm in items]
+    for prec in ("fp64", "mixed"):
+        bt = og_mod.Batch(dev, stream=torch.cuda.current_stream(), precision=prec)
+        outs = bt.force()
+        torch.cuda.synchronize()
+        for (pos, mass, box, prm), (a, p) in zip(items, outs):
+            ra, rp = _alone(og_mod, pos, mass, box, prm, prec)
+            a = a.cpu().numpy()
+            if prec == "fp64":
+                assert np.array_equal(a, ra)
+            else:
+                e = np.linalg.norm(a - ra, axis=1) / np.maximum(np.linalg.norm(ra, axis=1), 1e-300)
+                assert np.median(e) <= 1e-6 and e.max() <= 1e-3
+        bt.close()
+
+
+def test_graph_replay_equals_eager_and_rereads_inputs(og_mod):
+    items = _boxes(16, 13)
+    dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), b, prm)
+           for p, m, b, prm in items]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bt = og_mod.Batch(dev, stream=stream, precision="mixed")
+        eager = [(a.clone(), p.clone()) for a, p in bt.force()]
+        for rep in range(3):
+            for a, p in bt.outputs:
+                a.zero_()
+                p.zero_()
+            bt.replay()
+            stream.synchronize()
+            for (a, p), (ea, ep) in zip(bt.outputs, eager):
+                assert torch.equal(a, ea) and torch.equal(p, ep), rep
+        # change one box's positions: the next replay must see it
+        pos2 = synth.mixture_box(items[3][0].shape[0], 777)
+        dev[3][0].copy_(torch.as_tensor(pos2, device="cuda"))
+        bt.replay()
+        stream.synchronize()
+    ra, rp = _alone(og_mod, pos2, items[3][1], 1.0, items[3][3], "mixed")
+    assert np.array_equal(bt.outputs[3][0].cpu().numpy(), ra)
+    assert bt.status() == 0
+    bt.close()
