@@ -123,6 +123,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    ap.add_argument("--legs", default="batch,serving,zeldovich",
+                    help="extra workloads reported beside the headline: batch, serving, zeldovich "
+                         "(comma list, or 'none')")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -230,6 +234,20 @@ def main():
         "git": git_hash(),
     }
 
+    legs = [l for l in args.legs.split(",") if l and l != "none"]
+    # free the headline workload's device memory before the extra legs
+    del tp, tm, ws
+    torch.cuda.empty_cache()
+    for leg in legs:
+        fn = {"batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich}[leg]
+        log("leg %s" % leg)
+        try:
+            out[LEG_NAMES[leg]] = fn(og, torch, synth, args)
+        except Exception as exc:  # noqa: BLE001 - report, do not hide
+            log("leg %s failed: %r" % (leg, exc))
+            out[LEG_NAMES[leg]] = {"failed": repr(exc)}
+        torch.cuda.empty_cache()
+
     # oracle: error of both GPU forms and the CPU baseline
     if args.no_oracle:
         out["error"] = None
@@ -285,6 +303,188 @@ def main():
         out["error"] = None
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+LEG_NAMES = {"batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256"}
+
+
+def _oracle_params(oracle, prm):
+    return oracle.Params(**{k: prm[k] for k in ("G", "eps", "r_s", "r_cut", "theta", "periodic",
+                                                "leaf_max")})
+
+
+def _rel_err(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+def leg_batch(og, torch, synth, args):
+    """512 independent periodic boxes, N_b log-uniform in [1e3, 2e5]: one
+    captured graph (build + walk of every box), launch shape autotuned."""
+    from paper_2609_17658_amd import tune
+
+    ws = synth.batch512()
+    n_tot = int(sum(w.pos.shape[0] for w in ws))
+    dev = [(torch.as_tensor(w.pos, device="cuda"), torch.as_tensor(w.mass, device="cuda"), w.box,
+            w.params.as_dict()) for w in ws]
+    tuned = tune.tune_batch(dev, reps=2, log=log)
+    best = {k: tuned["best"][k] for k in ("group_max", "walk_list_cap", "leaf_max")}
+    ms = tune.time_batch(dev, reps=max(3, args.steps), **best)
+    # the same boxes one tree at a time (one reused workspace), for comparison
+    stream = torch.cuda.current_stream()
+    wsz = max(og.og_tree_workspace_bound(w.pos.shape[0], og.make_params(w.params.as_dict(),
+                                                                          leaf_max=best["leaf_max"]))
+              for w in ws)
+    wbuf = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    acc = torch.empty((max(w.pos.shape[0] for w in ws), 3), dtype=torch.float64, device="cuda")
+    pot = torch.empty(acc.shape[0], dtype=torch.float64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    trees = []
+    e0.record(stream)
+    for (pos, mass, box, prm) in dev:
+        t = og.Tree(pos, mass, box, prm, stream=stream, workspace=wbuf, leaf_max=best["leaf_max"],
+                    group_max=best["group_max"], walk_list_cap=best["walk_list_cap"])
+        t.force(acc=acc[:pos.shape[0]], pot=pot[:pos.shape[0]])
+        trees.append(t)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1)
+    for t in trees:
+        t.close()
+    del wbuf, acc, pot
+    # parity of the tuned batch against the oracle at the tuned leaf size, sampled boxes
+    err = None
+    try:
+        import oracle
+        bt = og.Batch([(p, m, b, dict(prm, leaf_max=best["leaf_max"])) for p, m, b, prm in dev],
+                      precision="mixed", group_max=best["group_max"],
+                      walk_list_cap=best["walk_list_cap"])
+        outs = bt.force()
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(7)
+        pick = sorted(rng.choice(len(ws), 8, replace=False))
+        errs = []
+        for b in pick:
+            w = ws[b]
+            op = _oracle_params(oracle, dict(w.params.as_dict(), leaf_max=best["leaf_max"]))
+            a_o, _, _ = oracle.tree_force(w.pos, w.mass, w.box, op)
+            errs.append(_rel_err(outs[b][0].cpu().numpy(), a_o))
+        bt.close()
+        e = np.concatenate(errs)
+        err = {"boxes": [int(b) for b in pick], "targets": int(e.size),
+               "mixed_median": float(np.median(e)), "mixed_p99": float(np.percentile(e, 99))}
+    except Exception as exc:  # noqa: BLE001
+        log("batch parity failed: %r" % (exc,))
+    return {"boxes": len(ws), "N_total": n_tot, "ms_per_pass": ms, "value": n_tot / (ms * 1e-3),
+            "unit": "particles/s", "tuned": best, "tuning": tuned["trials"],
+            "one_tree_at_a_time_ms": loop_ms, "speedup_vs_one_at_a_time": loop_ms / ms,
+            "error_vs_oracle": err,
+            "workload": "512 periodic boxes, N_b log-uniform [1e3, 2e5], half uniform + 8 Plummer "
+                        "spheres (a=0.01), box seed 1000+b, scale-free eps and r_s, theta 0.5; "
+                        "graph replay of build + mixed walk"}
+
+
+def leg_serving(og, torch, synth, args):
+    """Poisson request stream, N log-uniform in [1e4, 4e6] (Zel'dovich or
+    mixture): continuous batching with HBM admission; p50/p99 latency from
+    arrival to completion, throughput = particles / makespan."""
+    pool_n = 16
+    reqs = synth.request_stream(pool_n, 1.0, seed=5)
+    pool = []
+    for r in reqs:
+        w = r.workload()
+        pool.append((torch.as_tensor(w.pos, device="cuda"), torch.as_tensor(w.mass, device="cuda"),
+                     w.params.as_dict()))
+    budget = 48 << 30
+    srv = og.Server(budget, max_slots=4)
+    # closed-loop calibration: everything at once
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tk = [srv.submit(p, m, 1.0, prm) for p, m, prm in pool]
+    for t in tk:
+        srv.wait(t)
+    calib = time.perf_counter() - t0
+    for t in tk:
+        srv.release(t)
+    sustain = pool_n / calib
+    rate = 0.7 * sustain
+    K = args.serve_requests
+    rng = np.random.default_rng(11)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, K))
+    arrivals -= arrivals[0]
+    lat, inflight, n_done, parts = [], [], 0, 0
+    k = 0
+    start = time.perf_counter()
+    while n_done < K:
+        now = time.perf_counter() - start
+        while k < K and arrivals[k] <= now:
+            p, m, prm = pool[k % pool_n]
+            inflight.append((srv.submit(p, m, 1.0, prm), p.shape[0]))
+            k += 1
+        still = []
+        for t, n in inflight:
+            done, ta, td = srv.poll(t)
+            if done:
+                lat.append(td - ta)
+                parts += n
+                n_done += 1
+                srv.release(t)
+            else:
+                still.append((t, n))
+        inflight = still
+        if k < K and not inflight:
+            time.sleep(max(0.0, min(0.0005, arrivals[k] - (time.perf_counter() - start))))
+    makespan = time.perf_counter() - start
+    srv.close()
+    lat = np.array(lat) * 1e3
+    return {"requests": K, "pool": pool_n, "rate_per_s": rate, "sustainable_per_s": sustain,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "value": parts / makespan, "unit": "particles/s",
+            "makespan_s": makespan, "slots": 4, "hbm_budget_bytes": budget,
+            "pool_N": [int(p[0].shape[0]) for p in pool],
+            "workload": "Poisson arrivals at 0.7x the closed-loop rate; request k is pool box k mod 16, "
+                        "N log-uniform [1e4, 4e6], Zel'dovich or mixture by seeded coin; mixed walk"}
+
+
+def leg_zeldovich(og, torch, synth, args):
+    """N = 256^3 Zel'dovich-displaced grid (P(k) ~ k^-2, rms 0.3 cell): the
+    largest single box; both forms, error on sampled targets."""
+    w = synth.zeldovich256()
+    n = w.pos.shape[0]
+    prm = w.params.as_dict()
+    tp = torch.as_tensor(w.pos, device="cuda")
+    tm = torch.as_tensor(w.mass, device="cuda")
+    wsb = torch.empty(og.og_tree_workspace_bound(n, og.make_params(prm)), dtype=torch.uint8, device="cuda")
+    res = {}
+    for prec, steps in (("mixed", 5), ("fp64", 2)):
+        r = time_steps(og, torch, tp, tm, prm, wsb, prec, steps, 1)
+        for t in r["trees"]:
+            t.close()
+        res[prec] = {"value": n / (r["total_ms"] / steps * 1e-3), "ms_per_step": r["total_ms"] / steps,
+                     "build_ms": float(r["build_ms"].mean()), "walk_ms": float(r["walk_ms"].mean())}
+    t = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream(), workspace=wsb)
+    a_m, _ = t.force(precision="mixed")
+    a_d, _ = t.force(precision="fp64")
+    torch.cuda.synchronize()
+    t.close()
+    err = None
+    try:
+        import oracle
+        rng = np.random.default_rng(3)
+        tg = np.sort(rng.choice(n, 20000, replace=False))
+        a_o, _, _ = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, prm), targets=tg)
+        e_m = _rel_err(a_m.cpu().numpy()[tg], a_o)
+        e_d = _rel_err(a_d.cpu().numpy()[tg], a_o)
+        rms = np.sqrt(np.mean(np.sum(a_o ** 2, axis=1)))
+        err = {"targets": int(tg.size), "mixed_median": float(np.median(e_m)),
+               "mixed_p99": float(np.percentile(e_m, 99)),
+               "mixed_p99_over_rms": float(np.percentile(np.linalg.norm(a_m.cpu().numpy()[tg] - a_o, axis=1),
+                                                         99) / rms),
+               "fp64_max": float(e_d.max())}
+    except Exception as exc:  # noqa: BLE001
+        log("zeldovich parity failed: %r" % (exc,))
+    return {"N": n, "mixed": res["mixed"], "fp64": res["fp64"], "error_vs_oracle": err,
+            "workload": "256^3 grid, Gaussian field P(k)~k^-2 cut at k_Nyq, rms displacement 0.3 cell, "
+                        "eps=1/10240, r_s=1.25/512, theta 0.5, leaf_max 8"}
 
 
 def _cpu_model():
