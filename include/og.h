@@ -85,8 +85,8 @@ typedef struct og_params {
     int32_t group_max;      /* targets per wavefront group, 1..64, 0 = 64;
                                the result does not depend on it */
     int32_t walk_list_cap;  /* mixed walk: accepted partners buffered per
-                               target before evaluation, 8, 16 or 32; 0 =
-                               default (8); the result does not depend on it */
+                               target before evaluation, 4, 8, 16 or 32; 0 =
+                               default (4); the result does not depend on it */
     void *stream;           /* hipStream_t, NULL = default stream */
     void *workspace;        /* optional caller device buffer for the tree */
     size_t workspace_bytes; /* its size; must be >= og_tree_workspace_bound */
@@ -113,7 +113,7 @@ typedef struct og_tree og_tree;
  * the keys of such particles are clamped so that every kernel stays in
  * bounds.  Errors: OG_EINVAL (N < 1 or > 2^27-1, box <= 0, eps < 0,
  * theta < 0, leaf_max outside 1..4096, group_max outside 0..64,
- * walk_list_cap not 0, 8, 16 or 32, periodic
+ * walk_list_cap not 0, 4, 8, 16 or 32, periodic
  * with r_s <= 0 or r_cut >= box/2, null pointers, host pointers),
  * OG_ENOMEM, OG_EDEVICE. */
 int og_tree_build(const double *pos, const double *mass, int64_t N, double box,

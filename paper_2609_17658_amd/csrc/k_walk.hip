@@ -412,11 +412,6 @@ __device__ inline float wrap_box(float d, const Consts32 &k) {
   return d < -k.half_box ? d + k.box : hi;
 }
 
-__device__ inline uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
-  return __builtin_amdgcn_readfirstlane(v);
-}
 __device__ inline int wave_min_i32(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
@@ -428,15 +423,57 @@ __device__ inline int wave_max_i32(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Evaluate and empty every lane's list.
+// List entries (float4).  A monopole: (offset, mass), mass >= 0, already
+// known to pass the cutoff.  A leaf: (offset of the leaf centre, tag) with
+// the sign bit of the tag set, bits 0..26 the leaf's first particle, bits
+// 27..29 the number of particles minus one (at most 8 per entry) and bit 30
+// set when particle offsets may need the minimum image.
+constexpr uint32_t kTagLeaf = 0x80000000u, kTagWrap = 0x40000000u, kTagFirst = (1u << 27) - 1u;
+
+__device__ inline float leaf_tag(uint32_t first, uint32_t n, bool wrap) {
+  return __uint_as_float(kTagLeaf | (wrap ? kTagWrap : 0u) | ((n - 1u) << 27) | first);
+}
+
+// Evaluate and empty every lane's list, lane-parallel: each step every lane
+// takes the next partner of its own list (a monopole, or the next particle
+// of a leaf entry, read with a per-lane load), in list order.
 template <int kCap>
-__device__ inline void flush(float4 (*list)[kWalk32Threads], uint32_t lane, uint32_t &cnt, const Consts32 &k,
-                             double &ax, double &ay, double &az, double &ph) {
-  const uint32_t kmax = wave_max_u32(cnt);
-  for (uint32_t e = 0; e < kmax; ++e) {
+__device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], uint32_t lane, uint32_t p,
+                             uint32_t &cnt, const Consts32 &k, double &ax, double &ay, double &az, double &ph,
+                             uint32_t &ni) {
+  uint32_t e = 0, j = 0;
+  while (__ballot(e < cnt)) {
     if (e < cnt) {
       const float4 q = list[e][lane];
-      eval32(q.x, q.y, q.z, q.w, k, ax, ay, az, ph);
+      const uint32_t tag = __float_as_uint(q.w);
+      float dx = q.x, dy = q.y, dz = q.z, m = q.w;
+      bool use = true;
+      if (tag & kTagLeaf) {
+        const uint32_t first = tag & kTagFirst, n = ((tag >> 27) & 7u) + 1u;
+        const float4 pq = A.part32[first + j];
+        dx += pq.x;
+        dy += pq.y;
+        dz += pq.z;
+        if (tag & kTagWrap) {
+          dx = wrap_box(dx, k);
+          dy = wrap_box(dy, k);
+          dz = wrap_box(dz, k);
+        }
+        m = pq.w;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        use = (first + j != p) && (!k.cutoff || r2 < k.rc2);
+        ++j;
+        if (j == n) {
+          j = 0;
+          ++e;
+        }
+      } else {
+        ++e;
+      }
+      if (use) {
+        eval32(dx, dy, dz, m, k, ax, ay, az, ph);
+        ++ni;
+      }
     }
   }
   cnt = 0;
@@ -505,7 +542,10 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       const uint32_t ns = leaf ? n + 1 : w.a;
       const WNode wa = ldw(A.wnode + min(n + 1, nend - 1));
       const WNode wb = ldw(A.wnode + min(ns, nend - 1));
-      if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap>(list, lane, cnt, k, ax, ay, az, ph);
+      const uint32_t lc = w.cf & kWCount;
+      // room for this visit's entry (a leaf of more than 8 particles makes
+      // room entry by entry below)
+      if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
       int d0 = w.c[0] - o0, d1 = w.c[1] - o1, d2 = w.c[2] - o2;
       if (kPer && (abs(w.c[0] - g0) > thr || abs(w.c[1] - g1) > thr || abs(w.c[2] - g2) > thr)) {
         d0 = wrap_cells(d0);
@@ -514,8 +554,9 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       }
       const float dcx = (float)d0 * k.h22 - xr, dcy = (float)d1 * k.h22 - yr, dcz = (float)d2 * k.h22 - zr;
       const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
+      const bool wrapd = kPer && (w.cf & kWWrap) != 0;
       float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
-      if (kPer && (w.cf & kWWrap)) {
+      if (wrapd) {
         dx = wrap_box(dx, k);
         dy = wrap_box(dy, k);
         dz = wrap_box(dz, k);
@@ -526,39 +567,30 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       const bool open = (w.side2 > k.theta2 * r2) || (mdc < w.near);
       const bool contrib = live && !open && (!kCut || r2 < k.rc2);
       const bool open_here = live && open;
-      list[cnt][lane] = make_float4(dx, dy, dz, w.m);
-      cnt += contrib ? 1u : 0u;
-      ni += contrib ? 1u : 0u;
+      if (leaf && lc > 8u) {
+        // a leaf of more than 8 particles: an opening lane appends one entry
+        // per 8 particles, an accepting lane its monopole once
+        for (uint32_t j0 = 0; j0 < lc; j0 += 8) {
+          if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
+          if (open_here || (contrib && j0 == 0)) {
+            list[cnt][lane] = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a + j0, min(8u, lc - j0), wrapd))
+                                        : make_float4(dx, dy, dz, w.m);
+            ++cnt;
+          }
+        }
+        ni += contrib ? 1u : 0u;
+      } else {
+        // one entry: the monopole, or the opened leaf
+        const float4 entry = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a, lc, wrapd))
+                                       : make_float4(dx, dy, dz, w.m);
+        list[cnt][lane] = entry;
+        const bool add = contrib || (leaf && open_here);
+        cnt += add ? 1u : 0u;
+        ni += contrib ? 1u : 0u;
+      }
       next = act ? (open_here ? n + 1 : ns) : next;
       uint32_t nn;
       if (leaf) {
-        if (__ballot(open_here)) {
-          const uint32_t f = w.a, lc = w.cf & kWCount;
-          const bool wrapd = kPer && (w.cf & kWWrap) != 0;
-          for (uint32_t j0 = 0; j0 < lc; j0 += 8) {
-            F4 q[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) q[i] = ldp(A.part32 + f + min(j0 + i, lc - 1));
-            const uint32_t m = min(8u, lc - j0);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              if ((uint32_t)i < m) {
-                if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap>(list, lane, cnt, k, ax, ay, az, ph);
-                float px = dcx + q[i].x, py = dcy + q[i].y, pz = dcz + q[i].z;
-                if (wrapd) {
-                  px = wrap_box(px, k);
-                  py = wrap_box(py, k);
-                  pz = wrap_box(pz, k);
-                }
-                const float s2 = px * px + py * py + pz * pz;
-                const bool c = open_here && (f + j0 + (uint32_t)i != p) && (!kCut || s2 < k.rc2);
-                list[cnt][lane] = make_float4(px, py, pz, q[i].w);
-                cnt += c ? 1u : 0u;
-                ni += c ? 1u : 0u;
-              }
-            }
-          }
-        }
         nn = n + 1;
       } else {
         nn = (__ballot(open_here) || ns <= n) ? n + 1 : ns;
@@ -566,7 +598,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       w = nn == n + 1 ? wa : wb;
       n = nn;
     }
-    flush<kCap>(list, lane, cnt, k, ax, ay, az, ph);
+    flush<kCap>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
@@ -578,7 +610,7 @@ int walk_list_capacity() {
   if (cap < 0) {
     const char *e = getenv("OG_WALK_LIST_CAP");
     const int v = e ? atoi(e) : 0;
-    cap = (v == 8 || v == 16 || v == 32) ? v : 8;
+    cap = (v == 4 || v == 8 || v == 16 || v == 32) ? v : 4;
   }
   return cap;
 }
@@ -605,6 +637,7 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
     else k_walk32<C, 0><<<blocks, kWalk32Threads, 0, s>>>(W);                 \
   } while (0)
     if (cap == 8) OG_WALK32(8);
+    else if (cap == 4) OG_WALK32(4);
     else if (cap == 32) OG_WALK32(32);
     else OG_WALK32(16);
 #undef OG_WALK32

@@ -118,8 +118,9 @@ int check_params(const og_params *p, int64_t N, double box, bool need_stream_fie
   if (!std::isfinite(p->G)) return fail(OG_EINVAL, "G must be finite");
   if (p->leaf_max < 1 || p->leaf_max > 4096) return fail(OG_EINVAL, "leaf_max outside 1..4096");
   if (p->group_max < 0 || p->group_max > 64) return fail(OG_EINVAL, "group_max outside 0..64");
-  if (p->walk_list_cap != 0 && p->walk_list_cap != 8 && p->walk_list_cap != 16 && p->walk_list_cap != 32)
-    return fail(OG_EINVAL, "walk_list_cap must be 0, 8, 16 or 32");
+  if (p->walk_list_cap != 0 && p->walk_list_cap != 4 && p->walk_list_cap != 8 && p->walk_list_cap != 16 &&
+      p->walk_list_cap != 32)
+    return fail(OG_EINVAL, "walk_list_cap must be 0, 4, 8, 16 or 32");
   if (p->precision != OG_PREC_FP64 && p->precision != OG_PREC_MIXED)
     return fail(OG_EINVAL, "unknown precision %d", p->precision);
   if (!std::isfinite(p->r_s) || !std::isfinite(p->r_cut) || p->r_cut < 0.0)

@@ -13,10 +13,10 @@ from __future__ import annotations
 import itertools
 import time
 
-DEFAULT_SPACE = {"group_max": [32, 64], "walk_list_cap": [8, 16], "leaf_max": [8, 16]}
+DEFAULT_SPACE = {"group_max": [32, 64], "walk_list_cap": [4, 8], "leaf_max": [8, 16]}
 
 
-def time_batch(items, group_max=64, walk_list_cap=8, leaf_max=None, precision="mixed", reps=3,
+def time_batch(items, group_max=64, walk_list_cap=4, leaf_max=None, precision="mixed", reps=3,
                stream=None):
     """Mean ms per graph replay (build + walk of every box) for one setting.
     items: list of (pos, mass, box, params-dict) with device tensors."""

@@ -175,6 +175,24 @@ def test_group_size_does_not_change_results(og_mod):
             assert np.array_equal(g["nint"], r["nint"]), (gm, prec)
 
 
+@pytest.mark.parametrize("case", ["mixture32k", "rand10007_lm16", "coincident300"])
+def test_list_depth_does_not_change_results(og_mod, case):
+    """The mixed walk evaluates each lane's buffered partners in the order
+    they were appended, whatever the buffer depth, so results are bitwise
+    independent of walk_list_cap (leaves larger than 8 particles take
+    several buffer entries)."""
+    _, pos, mass, box, prm = next(c for c in CASES if c[0] == case)
+    ref = None
+    for cap in (4, 8, 16, 32):
+        g = gpu_run(og_mod, pos, mass, box, prm, precision="mixed", walk_list_cap=cap)
+        if ref is None:
+            ref = g
+            continue
+        assert np.array_equal(g["acc"], ref["acc"]), cap
+        assert np.array_equal(g["pot"], ref["pot"]), cap
+        assert np.array_equal(g["nint"], ref["nint"]), cap
+
+
 def test_subset_targets_match_all_targets(og_mod):
     w = synth.mixture32k()
     rng = np.random.default_rng(5)
