@@ -7,9 +7,13 @@ and the benchmark's CPU-baseline leg may import this package.  It imports
 nothing from the HIP package, and the HIP package imports nothing from it.
 
 Parameters follow the paper's notation ("Gravity Solver" section): G, the
-Plummer softening ``eps``, the split scale ``r_s`` (the paper's A_smth),
-the cutoff ``r_cut`` (0 means 4.5 r_s), the opening angle ``theta``, the
-leaf size ``leaf_max`` and the ``periodic`` flag.
+Plummer(-equivalent) softening ``eps``, the split scale ``r_s`` (the paper's
+A_smth), the cutoff ``r_cut`` (0 means 4.5 r_s), the opening angle
+``theta``, the leaf size ``leaf_max``, the ``periodic`` flag, the softening
+kernel (``softening``: 0 Plummer, 1 cubic spline of support 2.8 eps, paper
+"Force evaluation") and the opening criterion (``criterion``: 0 Barnes-Hut,
+1 relative with tolerance ``alpha`` against the previous acceleration, paper
+"Tree walk").
 """
 import ctypes
 import os
@@ -46,9 +50,9 @@ def _load():
         lib.ogo_moments.argtypes = [P, P, I64, P, P, P, P, P]
         lib.ogo_moments.restype = None
         lib.ogo_walk.argtypes = [P, P, I64, P, P, P, P, P, P, P, P, I,
-                                 D, D, D, D, D, I, D, P, I64, P, P, P]
+                                 D, D, D, D, D, I, D, I, I, D, P, P, I64, P, P, P]
         lib.ogo_walk.restype = None
-        lib.ogo_direct.argtypes = [P, P, I64, D, I, D, D, D, D, P, I64, P, P, P]
+        lib.ogo_direct.argtypes = [P, P, I64, D, I, D, D, D, D, I, P, I64, P, P, P]
         lib.ogo_direct.restype = None
         _lib = lib
     return _lib
@@ -67,6 +71,9 @@ class Params:
     theta: float = 0.5
     periodic: int = 1
     leaf_max: int = 8
+    softening: int = 0      # 0 Plummer, 1 cubic spline (support 2.8 eps)
+    criterion: int = 0      # 0 Barnes-Hut (theta), 1 relative (alpha, a_old)
+    alpha: float = 0.0
 
     @property
     def rcut(self) -> float:
@@ -171,11 +178,15 @@ def build_tree(pos, mass, box, params: Params) -> Tree:
                 nmass, com, spos, smass, float(box), params)
 
 
-def walk(tree: Tree, targets=None, params: Params = None):
-    """Tree walk for caller-order target indices (None = all).
+def walk(tree: Tree, targets=None, params: Params = None, a_old=None):
+    """Tree walk for caller-order target indices (None = all).  With the
+    relative criterion, ``a_old`` holds every particle's previous
+    acceleration [N,3] in caller order.
     Returns (acc [M,3], pot [M], n_interactions [M]) in target order."""
     lib = _load()
     p = params or tree.params
+    if p.softening == 1 and not p.eps > 0:
+        raise OracleError("spline softening needs eps > 0")
     n = tree.spos.shape[0]
     inv = np.empty(n, dtype=np.uint32)
     inv[tree.perm] = np.arange(n, dtype=np.uint32)
@@ -184,20 +195,27 @@ def walk(tree: Tree, targets=None, params: Params = None):
     targets = np.ascontiguousarray(targets, dtype=np.int64)
     tpos = np.ascontiguousarray(inv[targets])
     M = tpos.shape[0]
+    if p.criterion == 1:
+        if a_old is None:
+            raise OracleError("the relative criterion needs a_old")
+        aold = np.ascontiguousarray(np.asarray(a_old, dtype=np.float64).reshape(n, 3)[targets])
+    else:
+        aold = np.zeros((1, 3))
     acc = np.empty((M, 3))
     pot = np.empty(M)
     nint = np.empty(M, dtype=np.int64)
     lib.ogo_walk(_p(tree.spos), _p(tree.smass), tree.n_nodes, _p(tree.first), _p(tree.count),
                  _p(tree.level), _p(tree.skip), _p(tree.centre), _p(tree.side), _p(tree.mass),
                  _p(tree.com), int(tree.params.leaf_max), float(p.G), float(p.eps), float(p.r_s),
-                 float(p.rcut), float(p.theta), int(p.periodic), float(tree.box), _p(tpos), M,
+                 float(p.rcut), float(p.theta), int(p.periodic), float(tree.box),
+                 int(p.softening), int(p.criterion), float(p.alpha), _p(aold), _p(tpos), M,
                  _p(acc), _p(pot), _p(nint))
     return acc, pot, nint
 
 
-def tree_force(pos, mass, box, params: Params, targets=None):
+def tree_force(pos, mass, box, params: Params, targets=None, a_old=None):
     """Build + walk.  Returns (acc, pot, n_interactions) in target order."""
-    return walk(build_tree(pos, mass, box, params), targets, params)
+    return walk(build_tree(pos, mass, box, params), targets, params, a_old)
 
 
 def direct(pos, mass, box, params: Params, targets=None):
@@ -214,7 +232,9 @@ def direct(pos, mass, box, params: Params, targets=None):
     acc = np.empty((M, 3))
     pot = np.empty(M)
     nint = np.empty(M, dtype=np.int64)
+    if params.softening == 1 and not params.eps > 0:
+        raise OracleError("spline softening needs eps > 0")
     lib.ogo_direct(_p(pos), _p(mass), n, float(box), int(params.periodic), float(params.G),
-                   float(params.eps), float(params.r_s), float(params.rcut), _p(targets), M,
-                   _p(acc), _p(pot), _p(nint))
+                   float(params.eps), float(params.r_s), float(params.rcut),
+                   int(params.softening), _p(targets), M, _p(acc), _p(pot), _p(nint))
     return acc, pot, nint

@@ -13,15 +13,39 @@
  *     phi_i -= G m_j erfc(u) / sqrt(r^2 + eps^2),   u = r / (2 r_s);
  *   Newtonian mode (r_s <= 0): every j contributes, with the bracket = 1 and
  *     erfc(u) replaced by 1, and no minimum image.
+ * With spline softening (paper, "Force evaluation": the point mass becomes
+ * the cubic spline density of support h = 2.8 eps) the factors
+ * (r^2 + eps^2)^(-3/2) and (r^2 + eps^2)^(-1/2) become q(r/h)/r^3 and
+ * q(r/h)/r + t(r/h)/h, where q is the spline's enclosed mass fraction and
+ * t(u) = 32 int_u^1 s f(s) ds its outer shells' potential (f the profile
+ * 1 - 6s^2 + 6s^3 below 1/2 and 2(1-s)^3 above, 32 = 4 pi * 8/pi).
  */
 #include <math.h>
 #include <stdint.h>
 
+/* Enclosed mass fraction q(u) = 32 int_0^u s^2 f(s) ds and outer term t(u). */
+static void ogo_spline_shells(double u, double *q, double *t)
+{
+    if (u >= 1.0) {
+        *q = 1.0;
+        *t = 0.0;
+    } else if (u < 0.5) {
+        *q = 32.0 / 3.0 * pow(u, 3) - 192.0 / 5.0 * pow(u, 5) + 32.0 * pow(u, 6);
+        *t = 14.0 / 5.0 - 16.0 * pow(u, 2) + 48.0 * pow(u, 4) - 192.0 / 5.0 * pow(u, 5);
+    } else {
+        *q = -1.0 / 15.0 + 64.0 / 3.0 * pow(u, 3) - 48.0 * pow(u, 4) + 192.0 / 5.0 * pow(u, 5)
+             - 32.0 / 3.0 * pow(u, 6);
+        *t = 16.0 / 5.0 - 32.0 * pow(u, 2) + 64.0 * pow(u, 3) - 48.0 * pow(u, 4)
+             + 64.0 / 5.0 * pow(u, 5);
+    }
+}
+
 void ogo_direct(const double *pos, const double *mass, int64_t n, double box,
                 int periodic, double G, double eps, double r_s, double r_cut,
-                const int64_t *targets, int64_t M, double *acc3, double *pot,
-                int64_t *nint)
+                int softening, const int64_t *targets, int64_t M, double *acc3,
+                double *pot, int64_t *nint)
 {
+    const double hs = 2.8 * eps;
     const int cut = r_s > 0.0;
     const double half = 0.5 * box, e2 = eps * eps, rc2 = r_cut * r_cut;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -47,12 +71,25 @@ void ogo_direct(const double *pos, const double *mass, int64_t n, double box,
                 wp = erfc(u);
                 w = wp + 2.0 * u / sqrt(M_PI) * exp(-u * u);
             }
-            double q = 1.0 / sqrt(rr + e2);
-            double g = G * mass[j] * q * q * q * w;
+            double f3, f1; /* softened 1/r^3 and 1/r */
+            if (softening == 1 && rr < hs * hs) {
+                double r = sqrt(rr), qm, tm;
+                ogo_spline_shells(r / hs, &qm, &tm);
+                f3 = r > 0.0 ? qm / (rr * r) : 32.0 / 3.0 / (hs * hs * hs);
+                f1 = (r > 0.0 ? qm / r : 0.0) + tm / hs;
+            } else if (softening == 1) {
+                f1 = 1.0 / sqrt(rr);
+                f3 = f1 * f1 * f1;
+            } else {
+                double q = 1.0 / sqrt(rr + e2);
+                f3 = q * q * q;
+                f1 = q;
+            }
+            double g = G * mass[j] * f3 * w;
             ax += g * dx;
             ay += g * dy;
             az += g * dz;
-            ph -= G * mass[j] * wp * q;
+            ph -= G * mass[j] * wp * f1;
             ++cnt;
         }
         acc3[3 * t] = ax;

@@ -22,6 +22,11 @@
  *       may be accepted as a monopole like any node.
  *   R10 key quantisation, R11 Morton bit order, R12 pre-order node order,
  *   R13 one-step minimum image, R14 self excluded by index.
+ *   R24 spline softening (switch): the point mass is replaced by the cubic
+ *       spline density of compact support h = 2.8 eps, and the short-range
+ *       factors of R2 multiply that softened force and potential.
+ *   R25 relative opening criterion (switch): open iff
+ *       G M side^2 > alpha |a_old| r^4 (r = |COM - x|), or by R6.
  *
  * Every function cites the passage it follows.  Summation order: the walk
  * adds contributions in traversal order; moments are summed particle by
@@ -239,6 +244,10 @@ void ogo_moments(const double *spos, const double *smass, int64_t n_nodes,
 typedef struct {
     double G, eps2, r_s, rcut, rc2, theta2, box;
     int periodic, cutoff;
+    int spline;      /* R24: 0 Plummer, 1 cubic spline of support h */
+    double h;        /* spline support, 2.8 eps */
+    int relative;    /* R25: 0 Barnes-Hut (R5), 1 relative criterion */
+    double alpha;    /* relative criterion tolerance */
 } ogo_walk_params;
 
 static double ogo_minimg(double d, const ogo_walk_params *p)
@@ -252,12 +261,51 @@ static double ogo_minimg(double d, const ogo_walk_params *p)
 
 static const double OGO_TWO_OVER_SQRTPI = 1.1283791670955126; /* 2/sqrt(pi) */
 
+/* R24: softened 1/r^3 (force) and 1/r (potential) of a unit point mass
+ * spread with the cubic spline density
+ *   rho(s) = 8/(pi h^3) (1 - 6q^2 + 6q^3)  for q = s/h < 1/2,
+ *            8/(pi h^3) 2 (1 - q)^3         for 1/2 <= q < 1,   0 beyond,
+ * (paper, "Force evaluation": spline kernel of compact support h, the
+ * Plummer-equivalent eps = h/2.8).  With u = r/h and M(u) the enclosed mass,
+ * the force factor is M(u)/r^3 and the potential factor M(u)/r plus
+ * 4 pi int_r^h s rho(s) ds; written out as polynomials in u:
+ *   u < 1/2:  g h^3 = 32/3 - 192/5 u^2 + 32 u^3
+ *             w h   = 14/5 - 16/3 u^2 + 48/5 u^4 - 32/5 u^5
+ *   u < 1:    g h^3 = 64/3 - 48 u + 192/5 u^2 - 32/3 u^3 - 1/(15 u^3)
+ *             w h   = 16/5 - 1/(15 u) - 32/3 u^2 + 16 u^3 - 48/5 u^4 + 32/15 u^5
+ *   u >= 1:   g = 1/r^3, w = 1/r.                                         */
+static void ogo_spline(double r, double h, double *g, double *w)
+{
+    if (r >= h) {
+        *g = 1.0 / (r * r * r);
+        *w = 1.0 / r;
+        return;
+    }
+    double u = r / h, u2 = u * u, h3 = h * h * h;
+    if (u < 0.5) {
+        *g = (32.0 / 3.0 - 192.0 / 5.0 * u2 + 32.0 * u2 * u) / h3;
+        *w = (14.0 / 5.0 - 16.0 / 3.0 * u2 + 48.0 / 5.0 * u2 * u2 - 32.0 / 5.0 * u2 * u2 * u) / h;
+    } else {
+        *g = (64.0 / 3.0 - 48.0 * u + 192.0 / 5.0 * u2 - 32.0 / 3.0 * u2 * u
+              - 1.0 / (15.0 * u2 * u)) / h3;
+        *w = (16.0 / 5.0 - 1.0 / (15.0 * u) - 32.0 / 3.0 * u2 + 16.0 * u2 * u
+              - 48.0 / 5.0 * u2 * u2 + 32.0 / 15.0 * u2 * u2 * u) / h;
+    }
+}
+
 static int ogo_pair(const double d[3], double m, const ogo_walk_params *p,
                     double acc[3], double *pot)
 {
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (p->cutoff && !(r2 < p->rc2)) return 0;
-    double rinv = 1.0 / sqrt(r2 + p->eps2);
+    double g, w; /* softened 1/r^3 and 1/r */
+    if (p->spline) {
+        ogo_spline(sqrt(r2), p->h, &g, &w);
+    } else {
+        double rinv = 1.0 / sqrt(r2 + p->eps2);
+        g = rinv * rinv * rinv;
+        w = rinv;
+    }
     double S = 1.0, pf = 1.0;
     if (p->cutoff) {
         double r = sqrt(r2);
@@ -266,11 +314,11 @@ static int ogo_pair(const double d[3], double m, const ogo_walk_params *p,
         S = e + OGO_TWO_OVER_SQRTPI * u * exp(-u * u);
         pf = e;
     }
-    double f = p->G * m * rinv * rinv * rinv * S;
+    double f = p->G * m * g * S;
     acc[0] += f * d[0];
     acc[1] += f * d[1];
     acc[2] += f * d[2];
-    *pot -= p->G * m * pf * rinv;
+    *pot -= p->G * m * pf * w;
     return 1;
 }
 
@@ -283,7 +331,7 @@ static int64_t ogo_walk_one(uint32_t ps, const double *spos, const double *smass
                             const uint32_t *skip, const double *centre3,
                             const double *side, const double *nmass,
                             const double *com3, const ogo_walk_params *p,
-                            double acc[3], double *pot)
+                            double aold, double acc[3], double *pot)
 {
     const double *xi = spos + 3 * (int64_t)ps;
     int64_t nint = 0;
@@ -303,7 +351,9 @@ static int64_t ogo_walk_one(uint32_t ps, const double *spos, const double *smass
         for (int k = 0; k < 3; ++k) d[k] = ogo_minimg(com3[3 * n + k] - xi[k], p);
         double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         double near = 0.6 * s;
-        int open = (s * s > p->theta2 * r2) ||
+        int far_open = p->relative ? (p->G * nmass[n] * s * s > p->alpha * aold * r2 * r2)
+                                   : (s * s > p->theta2 * r2);
+        int open = far_open ||
                    (fabs(dc[0]) < near && fabs(dc[1]) < near && fabs(dc[2]) < near);
         if (!open) {
             nint += ogo_pair(d, nmass[n], p, acc, pot);
@@ -325,13 +375,17 @@ static int64_t ogo_walk_one(uint32_t ps, const double *spos, const double *smass
 
 /* Tree walk for the targets given as sorted positions `tpos[M]`; outputs in
  * the same order.  Targets run in parallel; each target's own sum is
- * sequential in traversal order, so results do not depend on threads.     */
+ * sequential in traversal order, so results do not depend on threads.
+ * softening: 0 Plummer, 1 spline (R24).  criterion: 0 Barnes-Hut, 1
+ * relative (R25) with tolerance alpha and the targets' previous
+ * accelerations aold3[M][3] (target order).                               */
 void ogo_walk(const double *spos, const double *smass, int64_t n_nodes,
               const uint32_t *first, const uint32_t *count, const uint8_t *level,
               const uint32_t *skip, const double *centre3, const double *side,
               const double *nmass, const double *com3, int leaf_max,
               double G, double eps, double r_s, double r_cut, double theta,
-              int periodic, double box, const uint32_t *tpos, int64_t M,
+              int periodic, double box, int softening, int criterion, double alpha,
+              const double *aold3, const uint32_t *tpos, int64_t M,
               double *acc3, double *pot, int64_t *nint)
 {
     ogo_walk_params p;
@@ -344,14 +398,22 @@ void ogo_walk(const double *spos, const double *smass, int64_t n_nodes,
     p.theta2 = theta * theta;
     p.periodic = periodic;
     p.box = box;
+    p.spline = softening == 1;
+    p.h = 2.8 * eps;
+    p.relative = criterion == 1;
+    p.alpha = alpha;
     uint8_t *is_leaf = (uint8_t *)malloc((size_t)(n_nodes > 0 ? n_nodes : 1));
     for (int64_t r = 0; r < n_nodes; ++r)
         is_leaf[r] = !((int)count[r] > leaf_max && level[r] < OGO_LEVELS);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t t = 0; t < M; ++t) {
-        double a[3], ph;
+        double a[3], ph, ao = 0.0;
+        if (p.relative) {
+            const double *v = aold3 + 3 * t;
+            ao = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        }
         int64_t c = ogo_walk_one(tpos[t], spos, smass, n_nodes, first, count, is_leaf,
-                                 skip, centre3, side, nmass, com3, &p, a, &ph);
+                                 skip, centre3, side, nmass, com3, &p, ao, a, &ph);
         acc3[3 * t] = a[0];
         acc3[3 * t + 1] = a[1];
         acc3[3 * t + 2] = a[2];
