@@ -75,7 +75,7 @@ def git_hash():
         return None
 
 
-def time_steps(og, torch, tp, tm, params, ws, precision, steps, warmup):
+def time_steps(og, torch, tp, tm, params, ws, precision, steps, warmup, a_old=None):
     """Returns per-step ms, per-step walk ms, final (acc, pot) and the trees."""
     stream = torch.cuda.current_stream()
     trees = []
@@ -86,7 +86,7 @@ def time_steps(og, torch, tp, tm, params, ws, precision, steps, warmup):
         t = og.Tree(tp, tm, 1.0, params, stream=stream, workspace=ws, precision=precision)
         if ev is not None:
             ev[1].record(stream)
-        acc, pot = t.force()
+        acc, pot = t.force(a_old=a_old)
         if ev is not None:
             ev[2].record(stream)
         trees.append(t)
@@ -123,9 +123,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
-    ap.add_argument("--legs", default="batch,serving,zeldovich",
-                    help="extra workloads reported beside the headline: batch, serving, zeldovich "
-                         "(comma list, or 'none')")
+    ap.add_argument("--legs", default="batch,serving,zeldovich,variants",
+                    help="extra workloads reported beside the headline: batch, serving, zeldovich, "
+                         "variants (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -239,7 +239,8 @@ def main():
     del tp, tm, ws
     torch.cuda.empty_cache()
     for leg in legs:
-        fn = {"batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich}[leg]
+        fn = {"batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich,
+              "variants": leg_variants}[leg]
         log("leg %s" % leg)
         try:
             out[LEG_NAMES[leg]] = fn(og, torch, synth, args)
@@ -305,7 +306,8 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-LEG_NAMES = {"batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256"}
+LEG_NAMES = {"batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256",
+             "variants": "variants_mixture2m"}
 
 
 def _oracle_params(oracle, prm):
@@ -485,6 +487,78 @@ def leg_zeldovich(og, torch, synth, args):
     return {"N": n, "mixed": res["mixed"], "fp64": res["fp64"], "error_vs_oracle": err,
             "workload": "256^3 grid, Gaussian field P(k)~k^-2 cut at k_Nyq, rms displacement 0.3 cell, "
                         "eps=1/10240, r_s=1.25/512, theta 0.5, leaf_max 8"}
+
+
+VARIANT_LEGS = (
+    ("spline", dict(softening="spline")),
+    ("relative", dict(criterion="relative", alpha=0.0025)),
+    ("spline_relative", dict(softening="spline", criterion="relative", alpha=0.0025)),
+)
+
+
+def leg_variants(og, torch, synth, args):
+    """The headline box with the spline softening (support 2.8 eps) and the
+    relative opening criterion (alpha = 0.0025 against the previous
+    acceleration).  Timing uses this device's FP64 Barnes-Hut accelerations
+    as a_old (a previous step's result); the error check runs sampled
+    targets on both sides with a_old taken from the oracle's own
+    Barnes-Hut walk."""
+    w = synth.mixture2m(theta=args.theta)
+    n = w.pos.shape[0]
+    base = w.params.as_dict()
+    tp = torch.as_tensor(w.pos, device="cuda")
+    tm = torch.as_tensor(w.mass, device="cuda")
+    wsb = torch.empty(og.og_tree_workspace_bound(n, og.make_params(base)), dtype=torch.uint8, device="cuda")
+    t = og.Tree(tp, tm, 1.0, base, stream=torch.cuda.current_stream(), workspace=wsb)
+    a_prev, _ = t.force(precision="fp64")
+    torch.cuda.synchronize()
+    t.close()
+    out = {}
+    oracle = None
+    if not args.no_oracle:
+        import oracle
+        rng = np.random.default_rng(7)
+        tg = np.sort(rng.choice(n, 4096, replace=False))
+        a_bh, _, _ = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, base), targets=tg)
+        a_old_o = np.zeros((n, 3))
+        a_old_o[tg] = a_bh
+    for name, extra in VARIANT_LEGS:
+        prm = dict(base, **extra)
+        rel = prm.get("criterion") == "relative"
+        row = {}
+        for prec, steps in (("mixed", 5), ("fp64", 2)):
+            r = time_steps(og, torch, tp, tm, prm, wsb, prec, steps, 1, a_old=a_prev if rel else None)
+            for tr in r["trees"]:
+                tr.close()
+            row[prec] = {"value": n / (r["total_ms"] / steps * 1e-3), "ms_per_step": r["total_ms"] / steps,
+                         "build_ms": float(r["build_ms"].mean()), "walk_ms": float(r["walk_ms"].mean())}
+        t = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream(), workspace=wsb)
+        _, _, ni = t.force(precision="mixed", with_counts=True, a_old=a_prev if rel else None)
+        torch.cuda.synchronize()
+        row["interactions_per_target"] = float(ni.sum().item()) / n
+        if oracle is not None:
+            ao = torch.as_tensor(a_old_o, device="cuda") if rel else None
+            tgd = torch.as_tensor(tg, device="cuda")
+            am, _ = t.force(targets=tgd, precision="mixed", a_old=ao)
+            ad, _, nd = t.force(targets=tgd, precision="fp64", with_counts=True, a_old=ao)
+            torch.cuda.synchronize()
+            op = oracle.Params(**{**{k: base[k] for k in ("G", "eps", "r_s", "r_cut", "theta", "periodic",
+                                                          "leaf_max")},
+                                  "softening": 1 if prm.get("softening") == "spline" else 0,
+                                  "criterion": 1 if rel else 0, "alpha": prm.get("alpha", 0.0)})
+            a_o, _, n_o = oracle.tree_force(w.pos, w.mass, 1.0, op, targets=tg, a_old=a_old_o)
+            e_m = _rel_err(am.cpu().numpy(), a_o)
+            row["error_vs_oracle"] = {
+                "targets": int(tg.size), "mixed_median": float(np.median(e_m)),
+                "mixed_p99": float(np.percentile(e_m, 99)),
+                "fp64_max": float(_rel_err(ad.cpu().numpy(), a_o).max()),
+                "fp64_counts_equal": bool(np.array_equal(nd.cpu().numpy(), n_o))}
+        t.close()
+        log("  %s: mixed %.3f ms/step, fp64 %.3f" % (name, row["mixed"]["ms_per_step"], row["fp64"]["ms_per_step"]))
+        out[name] = row
+    out["workload"] = "mixture2m as the headline; variants: %s" % ", ".join(
+        "%s=%s" % (k, v) for k, v in VARIANT_LEGS)
+    return out
 
 
 def _cpu_model():

@@ -69,6 +69,25 @@ enum {
  * every contribution is accumulated per target in FP64. */
 enum { OG_PREC_FP64 = 0, OG_PREC_MIXED = 1 };
 
+/* Softening kernel (paper, "Force evaluation").  PLUMMER: the factors
+ * (r^2+eps^2)^(-3/2) and (r^2+eps^2)^(-1/2).  SPLINE: the point mass is
+ * spread with the cubic spline density of compact support h = 2.8 eps (eps
+ * is the Plummer-equivalent length): with u = r/h,
+ *   u < 1/2: 1/r^3 -> (32/3 - 192/5 u^2 + 32 u^3)/h^3,
+ *            1/r   -> (14/5 - 16/3 u^2 + 48/5 u^4 - 32/5 u^5)/h,
+ *   u < 1:   1/r^3 -> (64/3 - 48 u + 192/5 u^2 - 32/3 u^3 - 1/(15 u^3))/h^3,
+ *            1/r   -> (16/5 - 1/(15 u) - 32/3 u^2 + 16 u^3 - 48/5 u^4
+ *                      + 32/15 u^5)/h,
+ *   u >= 1:  unsoftened.
+ * The short-range factors (erfc split) multiply either kernel. */
+enum { OG_SOFT_PLUMMER = 0, OG_SOFT_SPLINE = 1 };
+
+/* Opening criterion for nodes beyond the boundary check (paper, "Tree
+ * walk").  BH: open iff side^2 > theta^2 r^2.  RELATIVE: open iff
+ * G M side^2 > alpha |a_old| r^4, with a_old the target's previous
+ * acceleration (og_force_opts.a_old); r = |COM - x| (minimum image). */
+enum { OG_OPEN_BH = 0, OG_OPEN_RELATIVE = 1 };
+
 typedef struct og_params {
     uint32_t struct_size;   /* = sizeof(og_params) (ABI check) */
     double G;               /* gravitational constant (default 1) */
@@ -77,6 +96,7 @@ typedef struct og_params {
                                no cutoff (then periodic must be 0) */
     double r_cut;           /* cutoff radius; 0 => 4.5 r_s; periodic: < box/2 */
     double theta;           /* opening angle, >= 0 (0 opens every node) */
+    double alpha;           /* relative criterion tolerance, > 0 when used */
     int32_t periodic;       /* 1: positions in [0,box)^3 with minimum image;
                                0: open boundaries, root = bounding cube */
     int32_t leaf_max;       /* max particles per leaf (default 8), 1..4096;
@@ -87,13 +107,17 @@ typedef struct og_params {
     int32_t walk_list_cap;  /* mixed walk: accepted partners buffered per
                                target before evaluation, 4, 8, 16 or 32; 0 =
                                default (4); the result does not depend on it */
+    int32_t softening;      /* OG_SOFT_PLUMMER (default) or OG_SOFT_SPLINE
+                               (needs eps > 0) */
+    int32_t criterion;      /* OG_OPEN_BH (default) or OG_OPEN_RELATIVE */
     void *stream;           /* hipStream_t, NULL = default stream */
     void *workspace;        /* optional caller device buffer for the tree */
     size_t workspace_bytes; /* its size; must be >= og_tree_workspace_bound */
 } og_params;
 
-/* Defaults: G 1, eps 0, r_s 0, r_cut 0, theta 0.5, periodic 1, leaf_max 8,
- * MIXED, group_max 0, walk_list_cap 0, no stream, no workspace. */
+/* Defaults: G 1, eps 0, r_s 0, r_cut 0, theta 0.5, alpha 0, periodic 1,
+ * leaf_max 8, MIXED, group_max 0, walk_list_cap 0, PLUMMER, BH, no stream,
+ * no workspace. */
 void og_params_default(og_params *p);
 
 /* Device bytes one tree over N particles needs (upper bound, independent of
@@ -114,7 +138,8 @@ typedef struct og_tree og_tree;
  * bounds.  Errors: OG_EINVAL (N < 1 or > 2^27-1, box <= 0, eps < 0,
  * theta < 0, leaf_max outside 1..4096, group_max outside 0..64,
  * walk_list_cap not 0, 4, 8, 16 or 32, periodic
- * with r_s <= 0 or r_cut >= box/2, null pointers, host pointers),
+ * with r_s <= 0 or r_cut >= box/2, unknown softening or criterion, SPLINE
+ * with eps = 0, RELATIVE with alpha <= 0, null pointers, host pointers),
  * OG_ENOMEM, OG_EDEVICE. */
 int og_tree_build(const double *pos, const double *mass, int64_t N, double box,
                   const og_params *params, og_tree **out);
@@ -130,7 +155,8 @@ typedef struct og_targets {
 /* Short-range force on the targets, with the tree's parameters.
  *   targets: NULL or {NULL, N} = all particles;
  *   acc: device [M][3] FP64, pot: device [M] FP64 or NULL, in target order.
- * Enqueued on the tree's stream. */
+ * Enqueued on the tree's stream.  A tree built with OG_OPEN_RELATIVE needs
+ * a_old (og_tree_force_ex); here it gives OG_EINVAL. */
 int og_tree_force(const og_tree *tree, const og_targets *targets, double *acc, double *pot);
 
 typedef struct og_force_opts {
@@ -139,6 +165,9 @@ typedef struct og_force_opts {
     void *stream;           /* NULL: the tree's stream */
     int64_t *n_inter;       /* device [M] or NULL: per-target count of
                                contributions that passed the cutoff */
+    const double *a_old;    /* device [N][3] FP64, caller order: previous
+                               accelerations for OG_OPEN_RELATIVE (required
+                               then, ignored otherwise) */
 } og_force_opts;
 
 /* As og_tree_force, with a precision, stream and interaction counts. */
@@ -177,7 +206,8 @@ typedef struct og_box {
     double box;
     og_params params;    /* per box; stream/workspace fields ignored;
                             precision, group_max and walk_list_cap must
-                            equal box 0's */
+                            equal box 0's; OG_OPEN_RELATIVE is not
+                            available here (OG_EUNSUPPORTED) */
     double *acc;         /* device [N][3] output, caller order */
     double *pot;         /* device [N] output or NULL */
 } og_box;

@@ -94,6 +94,12 @@ __device__ inline BoxDev ld(const BoxDev *p) {
   b.cutoff = q->cutoff;
   b.leaf_max = q->leaf_max;
   b.g_off = q->g_off;
+  b.spline = q->spline;
+  b.relative = q->relative;
+  b.hs = q->hs;
+  b.alpha = q->alpha;
+  b.hsf = q->hsf;
+  b.hinvf = q->hinvf;
   return b;
 }
 
@@ -202,12 +208,41 @@ __device__ inline double minimg(double d, bool periodic, double box) {
   return periodic ? w : d;
 }
 
+// Spline-softened 1/r^3 (g) and 1/r (w) of a unit mass spread with the
+// cubic spline density of support h (paper, "Force evaluation"); u = r/h.
+__device__ inline void spline64(double r, double h, double &g, double &w) {
+#pragma clang fp contract(off)
+  if (r >= h) {
+    g = 1.0 / (r * r * r);
+    w = 1.0 / r;
+    return;
+  }
+  const double u = r / h, u2 = u * u, h3 = h * h * h;
+  if (u < 0.5) {
+    g = (32.0 / 3.0 - 192.0 / 5.0 * u2 + 32.0 * u2 * u) / h3;
+    w = (14.0 / 5.0 - 16.0 / 3.0 * u2 + 48.0 / 5.0 * u2 * u2 - 32.0 / 5.0 * u2 * u2 * u) / h;
+  } else {
+    g = (64.0 / 3.0 - 48.0 * u + 192.0 / 5.0 * u2 - 32.0 / 3.0 * u2 * u - 1.0 / (15.0 * u2 * u)) / h3;
+    w = (16.0 / 5.0 - 1.0 / (15.0 * u) - 32.0 / 3.0 * u2 + 16.0 * u2 * u - 48.0 / 5.0 * u2 * u2 +
+         32.0 / 15.0 * u2 * u2 * u) /
+        h;
+  }
+}
+
+template <bool kExt>
 __device__ inline void pair64(double dx, double dy, double dz, double m, const BoxDev &bx, double &ax,
                               double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(off)
   const double r2 = dx * dx + dy * dy + dz * dz;
   if (bx.cutoff && !(r2 < bx.rc2)) return;
-  const double rinv = 1.0 / sqrt(r2 + bx.eps2);
+  double g, w;  // softened 1/r^3 and 1/r
+  if (kExt && bx.spline) {
+    spline64(sqrt(r2), bx.hs, g, w);
+  } else {
+    const double rinv = 1.0 / sqrt(r2 + bx.eps2);
+    g = rinv * rinv * rinv;
+    w = rinv;
+  }
   double S = 1.0, pf = 1.0;
   if (bx.cutoff) {
     const double r = sqrt(r2);
@@ -216,16 +251,19 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, const B
     S = e + kTwoOverSqrtPi * u * exp(-u * u);
     pf = e;
   }
-  const double f = bx.G * m * rinv * rinv * rinv * S;
+  const double f = bx.G * m * g * S;
   ax += f * dx;
   ay += f * dy;
   az += f * dz;
-  ph -= bx.G * m * pf * rinv;
+  ph -= bx.G * m * pf * w;
   ++ni;
 }
 
 // Plain FP64 walk: every quantity in double precision, with the same
 // expressions (and no contraction) as a direct reading of the walk rules.
+// kExt: the spline softening and the relative criterion are read from each
+// box.
+template <bool kExt>
 __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
 #pragma clang fp contract(off)
   const uint32_t lane = threadIdx.x & 63;
@@ -239,6 +277,12 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
     const bool valid = lane_target(A, gr, bx, lane, p, slot);
     double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
     if (valid) xi = A.part64[p];
+    double aold = 0.0;  // |previous acceleration| for the relative criterion
+    const bool relative = kExt && bx.relative;
+    if (valid && relative) {
+      const double *v = A.a_old + 3ull * (A.perm[p] - bx.p_off);
+      aold = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    }
     const bool periodic = bx.periodic;
     const double box = bx.box, h = bx.L * 0x1p-21;
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
@@ -280,10 +324,11 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
           const double dz = minimg(mm.cz - xi.z, periodic, box);
           const double r2 = dx * dx + dy * dy + dz * dz;
           const double near = 0.6 * side;
-          const bool open = (side * side > bx.theta2 * r2) ||
-                            (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
+          const bool far_open = relative ? (bx.G * mm.m * side * side > bx.alpha * aold * r2 * r2)
+                                            : (side * side > bx.theta2 * r2);
+          const bool open = far_open || (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
           if (!open) {
-            pair64(dx, dy, dz, mm.m, bx, ax, ay, az, ph, ni);
+            pair64<kExt>(dx, dy, dz, mm.m, bx, ax, ay, az, ph, ni);
             next = ns;
           } else if (!leaf) {
             open_int = true;
@@ -308,7 +353,7 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
                 const double dx = minimg(qx - xi.x, periodic, box);
                 const double dy = minimg(qy - xi.y, periodic, box);
                 const double dz = minimg(qz - xi.z, periodic, box);
-                pair64(dx, dy, dz, qm, bx, ax, ay, az, ph, ni);
+                pair64<kExt>(dx, dy, dz, qm, bx, ax, ay, az, ph, ni);
               }
             }
           }
@@ -349,7 +394,8 @@ constexpr int kWalk32Threads = 64;       // one wavefront per workgroup
 
 struct Consts32 {
   float G, eps2, inv2rs, rc2, theta2, h22, half_box, box;
-  bool cutoff, periodic;
+  float hs2, hinv;  // spline support squared and inverse
+  bool cutoff, periodic, spline;
 };
 
 struct F4 {
@@ -379,10 +425,39 @@ __device__ inline F4 ldp(const float4 *p) {
   return F4{q->x, q->y, q->z, q->w};
 }
 
+// Spline-softened 1/r^3 (g) and 1/r (w) inside the support, u = r/h < 1.
+__device__ inline void spline32(float u, float hinv, float &g, float &w) {
+  const float u2 = u * u, h3 = hinv * hinv * hinv;
+  if (u < 0.5f) {
+    g = (32.0f / 3.0f + u2 * (-192.0f / 5.0f + 32.0f * u)) * h3;
+    w = (14.0f / 5.0f + u2 * (-16.0f / 3.0f + u2 * (48.0f / 5.0f - 32.0f / 5.0f * u))) * hinv;
+  } else {
+    const float iu = __builtin_amdgcn_rcpf(u);
+    g = (64.0f / 3.0f + u * (-48.0f + u * (192.0f / 5.0f - 32.0f / 3.0f * u)) - (1.0f / 15.0f) * iu * iu * iu) * h3;
+    w = (16.0f / 5.0f - (1.0f / 15.0f) * iu + u2 * (-32.0f / 3.0f + u * (16.0f + u * (-48.0f / 5.0f + 32.0f / 15.0f * u)))) *
+        hinv;
+  }
+}
+
+template <bool kExt>
 __device__ inline void eval32(float dx, float dy, float dz, float m, const Consts32 &k, double &ax,
                               double &ay, double &az, double &ph) {
   const float r2 = dx * dx + dy * dy + dz * dz;
-  const float rinv = __builtin_amdgcn_rsqf(r2 + k.eps2);
+  float g, wv;  // softened 1/r^3 and 1/r
+  if (kExt && k.spline) {
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    if (r2 < k.hs2) {
+      const float r = r2 > 0.0f ? r2 * ri : 0.0f;
+      spline32(r * k.hinv, k.hinv, g, wv);
+    } else {
+      g = ri * ri * ri;
+      wv = ri;
+    }
+  } else {
+    const float rinv = __builtin_amdgcn_rsqf(r2 + k.eps2);
+    g = rinv * rinv * rinv;
+    wv = rinv;
+  }
   float S = 1.0f, pf = 1.0f;
   if (k.cutoff) {
     const float r = r2 > 0.0f ? r2 * __builtin_amdgcn_rsqf(r2) : 0.0f;
@@ -393,12 +468,12 @@ __device__ inline void eval32(float dx, float dy, float dz, float m, const Const
     S = ec + (float)kTwoOverSqrtPi * u * e;
     pf = ec;
   }
-  const float mr = k.G * m * rinv;
-  const float f = mr * rinv * rinv * S;
+  const float gm = k.G * m;
+  const float f = gm * g * S;
   ax += (double)(f * dx);
   ay += (double)(f * dy);
   az += (double)(f * dz);
-  ph -= (double)(mr * pf);
+  ph -= (double)(gm * wv * pf);
 }
 
 __device__ inline int wrap_cells(int d) {
@@ -437,7 +512,7 @@ __device__ inline float leaf_tag(uint32_t first, uint32_t n, bool wrap) {
 // Evaluate and empty every lane's list, lane-parallel: each step every lane
 // takes the next partner of its own list (a monopole, or the next particle
 // of a leaf entry, read with a per-lane load), in list order.
-template <int kCap>
+template <int kCap, bool kExt>
 __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], uint32_t lane, uint32_t p,
                              uint32_t &cnt, const Consts32 &k, double &ax, double &ay, double &az, double &ph,
                              uint32_t &ni) {
@@ -447,8 +522,9 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
       const float4 q = list[e][lane];
       const uint32_t tag = __float_as_uint(q.w);
       float dx = q.x, dy = q.y, dz = q.z, m = q.w;
-      bool use = true;
+      bool use = true, particle = false;  // monopoles were counted when appended
       if (tag & kTagLeaf) {
+        particle = true;
         const uint32_t first = tag & kTagFirst, n = ((tag >> 27) & 7u) + 1u;
         const float4 pq = A.part32[first + j];
         dx += pq.x;
@@ -471,8 +547,8 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
         ++e;
       }
       if (use) {
-        eval32(dx, dy, dz, m, k, ax, ay, az, ph);
-        ++ni;
+        eval32<kExt>(dx, dy, dz, m, k, ax, ay, az, ph);
+        ni += particle ? 1u : 0u;
       }
     }
   }
@@ -481,7 +557,9 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
 
 // kMode: 0 = cutoff and periodicity read from each box; 1 = cutoff, open
 // boundaries; 2 = cutoff, periodic; 3 = plain Newtonian, open boundaries.
-template <int kCap, int kMode>  // list entries per lane; box kind
+// kExt: the spline softening and the relative criterion are read from each
+// box (only with kMode 0).
+template <int kCap, int kMode, bool kExt>  // list entries per lane; box kind; variants
 __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ float4 list[kCap][kWalk32Threads];
@@ -505,8 +583,18 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
     k.half_box = 0.5f * bx.Lf;
     k.cutoff = kCut;
     k.periodic = kPer;
+    k.spline = kExt && bx.spline;
+    k.hs2 = bx.hsf * bx.hsf;
+    k.hinv = bx.hinvf;
+    const bool relative = kExt && bx.relative;
     uint32_t p = 0, slot = 0;
     const bool valid = lane_target(A, gr, bx, lane, p, slot);
+    // relative criterion: open iff M side^2 > (alpha |a_old| / G) r^4
+    float aol = 0.0f;
+    if (relative && valid) {
+      const double *v = A.a_old + 3ull * (A.perm[p] - bx.p_off);
+      aol = (float)(bx.alpha * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / bx.G);
+    }
     // lane origin: centre of the target's level-21 cell, in half-cells
     int o0 = 0, o1 = 0, o2 = 0;
     float xr = 0.0f, yr = 0.0f, zr = 0.0f;
@@ -545,7 +633,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       const uint32_t lc = w.cf & kWCount;
       // room for this visit's entry (a leaf of more than 8 particles makes
       // room entry by entry below)
-      if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
+      if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
       int d0 = w.c[0] - o0, d1 = w.c[1] - o1, d2 = w.c[2] - o2;
       if (kPer && (abs(w.c[0] - g0) > thr || abs(w.c[1] - g1) > thr || abs(w.c[2] - g2) > thr)) {
         d0 = wrap_cells(d0);
@@ -564,14 +652,15 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       const float r2 = dx * dx + dy * dy + dz * dz;
       const bool act = next == n;
       const bool live = act && !(kCut && mdc > w.reach);
-      const bool open = (w.side2 > k.theta2 * r2) || (mdc < w.near);
+      const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
+      const bool open = far_open || (mdc < w.near);
       const bool contrib = live && !open && (!kCut || r2 < k.rc2);
       const bool open_here = live && open;
       if (leaf && lc > 8u) {
         // a leaf of more than 8 particles: an opening lane appends one entry
         // per 8 particles, an accepting lane its monopole once
         for (uint32_t j0 = 0; j0 < lc; j0 += 8) {
-          if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
+          if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
           if (open_here || (contrib && j0 == 0)) {
             list[cnt][lane] = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a + j0, min(8u, lc - j0), wrapd))
                                         : make_float4(dx, dy, dz, w.m);
@@ -598,7 +687,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       w = nn == n + 1 ? wa : wb;
       n = nn;
     }
-    flush<kCap>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
+    flush<kCap, kExt>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
@@ -622,19 +711,21 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
   if (precision == 0) {
     // 4 waves per workgroup; this kernel's registers allow 3 waves per SIMD
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(3u * cus, (groups + 3) / 4));
-    k_walk64<<<blocks, 256, 0, s>>>(W);
+    if (W.ext) k_walk64<true><<<blocks, 256, 0, s>>>(W);
+    else k_walk64<false><<<blocks, 256, 0, s>>>(W);
   } else {
     // one wave per workgroup; LDS per wave = cap x 1 KB of lists
     const int cap = W.list_cap > 0 ? W.list_cap : walk_list_capacity();
     const uint32_t per_cu = std::min<uint32_t>(32u, 160u / (uint32_t)cap);
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(per_cu * cus, groups));
     const int mode = W.box_kind;
-#define OG_WALK32(C)                                                          \
-  do {                                                                        \
-    if (mode == 2) k_walk32<C, 2><<<blocks, kWalk32Threads, 0, s>>>(W);       \
-    else if (mode == 1) k_walk32<C, 1><<<blocks, kWalk32Threads, 0, s>>>(W);  \
-    else if (mode == 3) k_walk32<C, 3><<<blocks, kWalk32Threads, 0, s>>>(W);  \
-    else k_walk32<C, 0><<<blocks, kWalk32Threads, 0, s>>>(W);                 \
+#define OG_WALK32(C)                                                                 \
+  do {                                                                               \
+    if (W.ext) k_walk32<C, 0, true><<<blocks, kWalk32Threads, 0, s>>>(W);            \
+    else if (mode == 2) k_walk32<C, 2, false><<<blocks, kWalk32Threads, 0, s>>>(W);  \
+    else if (mode == 1) k_walk32<C, 1, false><<<blocks, kWalk32Threads, 0, s>>>(W);  \
+    else if (mode == 3) k_walk32<C, 3, false><<<blocks, kWalk32Threads, 0, s>>>(W);  \
+    else k_walk32<C, 0, false><<<blocks, kWalk32Threads, 0, s>>>(W);                 \
   } while (0)
     if (cap == 8) OG_WALK32(8);
     else if (cap == 4) OG_WALK32(4);

@@ -123,6 +123,13 @@ int check_params(const og_params *p, int64_t N, double box, bool need_stream_fie
     return fail(OG_EINVAL, "walk_list_cap must be 0, 4, 8, 16 or 32");
   if (p->precision != OG_PREC_FP64 && p->precision != OG_PREC_MIXED)
     return fail(OG_EINVAL, "unknown precision %d", p->precision);
+  if (p->softening != OG_SOFT_PLUMMER && p->softening != OG_SOFT_SPLINE)
+    return fail(OG_EINVAL, "unknown softening %d", p->softening);
+  if (p->softening == OG_SOFT_SPLINE && !(p->eps > 0.0)) return fail(OG_EINVAL, "spline softening needs eps > 0");
+  if (p->criterion != OG_OPEN_BH && p->criterion != OG_OPEN_RELATIVE)
+    return fail(OG_EINVAL, "unknown opening criterion %d", p->criterion);
+  if (p->criterion == OG_OPEN_RELATIVE && !(p->alpha > 0.0 && std::isfinite(p->alpha)))
+    return fail(OG_EINVAL, "the relative criterion needs alpha > 0");
   if (!std::isfinite(p->r_s) || !std::isfinite(p->r_cut) || p->r_cut < 0.0)
     return fail(OG_EINVAL, "r_s / r_cut invalid");
   const double rcut = p->r_cut > 0.0 ? p->r_cut : 4.5 * p->r_s;
@@ -158,6 +165,12 @@ void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, doubl
   b.rcutf = (float)b.rcut;
   b.rc2f = (float)b.rc2;
   b.theta2f = (float)b.theta2;
+  b.spline = p.softening == OG_SOFT_SPLINE ? 1 : 0;
+  b.relative = p.criterion == OG_OPEN_RELATIVE ? 1 : 0;
+  b.hs = 2.8 * p.eps;
+  b.alpha = p.alpha;
+  b.hsf = (float)b.hs;
+  b.hinvf = b.spline ? (float)(1.0 / b.hs) : 0.0f;
   if (b.periodic) {
     b.lo[0] = b.lo[1] = b.lo[2] = 0.0;
     b.L = box;
@@ -240,14 +253,18 @@ WalkArgs Forest::walk_args() const {
   W.B = B;
   auto kind = [](const BoxDev &b) { return b.cutoff ? (b.periodic ? 2 : 1) : 3; };
   W.box_kind = kind(hboxes[0]);
-  for (const auto &b : hboxes)
+  for (const auto &b : hboxes) {
     if (kind(b) != W.box_kind) W.box_kind = 0;
+    if (b.spline || b.relative) W.ext = 1;
+  }
   W.counter = &A.scalars[8];
   return W;
 }
 
-int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint) {
+int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint,
+                     const double *a_old) {
   WalkArgs W = walk_args();
+  W.a_old = a_old;
   W.n_groups = n_groups;
   W.acc = acc;
   W.pot = pot;
@@ -260,7 +277,7 @@ int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_
 }
 
 int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
-                        int64_t *nint) {
+                        int64_t *nint, const double *a_old) {
   TargetArrays T{};
   auto plan = [&](Carver &cv) {
     T.tkey_a = cv.take<uint64_t>(M);
@@ -292,6 +309,7 @@ int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M,
   W.pot = pot;
   W.pot_override = 1;
   W.nint = nint;
+  W.a_old = a_old;
   launch_walk(W, prec, s);
   e = hipGetLastError();
   hipError_t e2 = hipFreeAsync(tmp, s);
@@ -392,6 +410,7 @@ int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_fo
   int prec = F.precision;
   hipStream_t s = F.stream;
   int64_t *nint = nullptr;
+  const double *a_old = nullptr;
   if (opts) {
     if (opts->struct_size != sizeof(og_force_opts)) return fail(OG_EINVAL, "og_force_opts.struct_size mismatch");
     if (opts->precision >= 0) {
@@ -402,6 +421,13 @@ int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_fo
     if (opts->stream) s = (hipStream_t)opts->stream;
     nint = opts->n_inter;
     if (nint && !is_device_ptr(nint)) return fail(OG_EINVAL, "n_inter must be a device pointer");
+    a_old = opts->a_old;
+  }
+  if (F.hboxes[0].relative) {
+    if (!a_old) return fail(OG_EINVAL, "the relative criterion needs a_old (og_force_opts)");
+    if (!is_device_ptr(a_old)) return fail(OG_EINVAL, "a_old must be a device pointer");
+  } else {
+    a_old = nullptr;
   }
   if (!is_device_ptr(acc)) return fail(OG_EINVAL, "acc must be a device pointer");
   if (pot && !is_device_ptr(pot)) return fail(OG_EINVAL, "pot must be a device pointer");
@@ -417,11 +443,11 @@ int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_fo
   if (!targets || !targets->idx) {
     if (targets && targets->M != (int64_t)F.N)
       return fail(OG_EINVAL, "targets->idx NULL requires M == N");
-    return F.walk_all(prec, s, acc, pot, 1, nint);
+    return F.walk_all(prec, s, acc, pot, 1, nint, a_old);
   }
   if (targets->M < 1 || targets->M > (int64_t)kCountMask) return fail(OG_EINVAL, "targets->M out of range");
   if (!is_device_ptr(targets->idx)) return fail(OG_EINVAL, "targets->idx must be a device pointer");
-  return F.walk_subset(prec, s, targets->idx, (uint32_t)targets->M, acc, pot, nint);
+  return F.walk_subset(prec, s, targets->idx, (uint32_t)targets->M, acc, pot, nint, a_old);
 }
 
 int og_tree_force(const og_tree *tree, const og_targets *targets, double *acc, double *pot) {
@@ -509,6 +535,8 @@ int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out)
     if (!is_device_ptr(x.pos) || !is_device_ptr(x.mass) || !is_device_ptr(x.acc) ||
         (x.pot && !is_device_ptr(x.pot)))
       return fail(OG_EINVAL, "box %d: pos/mass/acc/pot must be device pointers", b);
+    if (x.params.criterion == OG_OPEN_RELATIVE)
+      return fail(OG_EUNSUPPORTED, "box %d: the relative criterion needs a_old, not available in a batch", b);
     if (x.params.precision != boxes[0].params.precision || x.params.group_max != boxes[0].params.group_max ||
         x.params.walk_list_cap != boxes[0].params.walk_list_cap)
       return fail(OG_EINVAL, "box %d: precision, group_max and walk_list_cap must match box 0", b);

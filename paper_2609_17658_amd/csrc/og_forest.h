@@ -42,9 +42,10 @@ struct Forest {
            void *workspace, size_t ws_bytes);
   int build();
   WalkArgs walk_args() const;
-  int walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint);
+  int walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint,
+               const double *a_old = nullptr);
   int walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
-                  int64_t *nint);
+                  int64_t *nint, const double *a_old = nullptr);
   int read_status(hipStream_t s);
   void release();
 };

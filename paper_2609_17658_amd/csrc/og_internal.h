@@ -38,6 +38,9 @@ struct BoxDev {
   uint32_t root, node_end;  // node range, written on the device
   int32_t periodic, cutoff, leaf_max;
   uint32_t g_off;          // first walk group of this box
+  int32_t spline, relative;  // softening kernel, opening criterion
+  double hs, alpha;          // spline support 2.8 eps; relative tolerance
+  float hsf, hinvf;          // FP32 support and its inverse
 };
 
 // Walk-order node record, 16 bytes.

@@ -89,6 +89,8 @@ struct WalkArgs {
   double *pot;
   int64_t *nint;
   int pot_override;           // 1: use `pot` (possibly null) instead of the box's
+  int ext;                    // some box uses spline softening or the relative criterion
+  const double *a_old;        // relative criterion: previous accelerations [n][3], caller order
 };
 void launch_walk(const WalkArgs &W, int precision, hipStream_t s);
 void launch_reset(uint32_t *word, hipStream_t s);

@@ -203,6 +203,8 @@ int og_server_submit(og_server *s, const og_box *req, uint64_t *ticket) {
   if (!s || !req || !ticket) return fail(OG_EINVAL, "NULL argument");
   int rc = check_params(&req->params, req->N, req->box, false);
   if (rc) return rc;
+  if (req->params.criterion == OG_OPEN_RELATIVE)
+    return fail(OG_EUNSUPPORTED, "the relative criterion needs a_old, not available to served requests");
   if (!is_device_ptr(req->pos) || !is_device_ptr(req->mass) || !is_device_ptr(req->acc) ||
       (req->pot && !is_device_ptr(req->pot)))
     return fail(OG_EINVAL, "pos/mass/acc/pot must be device pointers");

@@ -20,14 +20,19 @@ OG_OK, OG_EINVAL, OG_ERANGE, OG_ENOMEM, OG_EDEVICE, OG_EBUSY, OG_EUNSUPPORTED, O
 OG_PREC_FP64, OG_PREC_MIXED = 0, 1
 PRECISIONS = {"fp64": OG_PREC_FP64, "mixed": OG_PREC_MIXED, OG_PREC_FP64: OG_PREC_FP64,
               OG_PREC_MIXED: OG_PREC_MIXED}
+OG_SOFT_PLUMMER, OG_SOFT_SPLINE = 0, 1
+OG_OPEN_BH, OG_OPEN_RELATIVE = 0, 1
+SOFTENINGS = {"plummer": OG_SOFT_PLUMMER, "spline": OG_SOFT_SPLINE, 0: 0, 1: 1}
+CRITERIA = {"bh": OG_OPEN_BH, "relative": OG_OPEN_RELATIVE, 0: 0, 1: 1}
 
 
 class og_params(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("G", ctypes.c_double), ("eps", ctypes.c_double),
                 ("r_s", ctypes.c_double), ("r_cut", ctypes.c_double), ("theta", ctypes.c_double),
-                ("periodic", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("periodic", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("group_max", ctypes.c_int32),
-                ("walk_list_cap", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("walk_list_cap", ctypes.c_int32), ("softening", ctypes.c_int32),
+                ("criterion", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -37,7 +42,7 @@ class og_targets(ctypes.Structure):
 
 class og_force_opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("n_inter", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("n_inter", ctypes.c_void_p), ("a_old", ctypes.c_void_p)]
 
 
 class og_box(ctypes.Structure):
@@ -143,6 +148,10 @@ def make_params(params=None, stream=None, workspace=None, **kw) -> og_params:
     for k, v in d.items():
         if k == "precision":
             v = PRECISIONS[v]
+        elif k == "softening":
+            v = SOFTENINGS[v]
+        elif k == "criterion":
+            v = CRITERIA[v]
         setattr(p, k, v)
     p.stream = _stream_handle(stream)
     if workspace is not None:
@@ -181,13 +190,15 @@ def og_tree_build(pos, mass, N: int, box: float, params: og_params) -> ctypes.c_
     return h
 
 
-def og_tree_force(tree, targets, acc, pot, precision=None, stream=None, n_inter=None):
-    """targets: None (all) or an int64 device tensor of caller-order indices."""
+def og_tree_force(tree, targets, acc, pot, precision=None, stream=None, n_inter=None, a_old=None):
+    """targets: None (all) or an int64 device tensor of caller-order indices;
+    a_old: previous accelerations [N,3] (device, caller order) for the
+    relative criterion."""
     tg = None
     if targets is not None:
         tg = og_targets(_ptr(targets), int(targets.numel()))
     opts = og_force_opts(ctypes.sizeof(og_force_opts), -1 if precision is None else PRECISIONS[precision],
-                         _stream_handle(stream), _ptr(n_inter))
+                         _stream_handle(stream), _ptr(n_inter), _ptr(a_old))
     _check(load().og_tree_force_ex(tree, ctypes.byref(tg) if tg is not None else None,
                                    ctypes.byref(opts), _ptr(acc), _ptr(pot)))
 
@@ -307,7 +318,7 @@ class Tree:
         self.handle = og_tree_build(pos, mass, self.N, box, self.params)
 
     def force(self, targets=None, precision=None, with_pot=True, with_counts=False, stream=None,
-              acc=None, pot=None):
+              acc=None, pot=None, a_old=None):
         import torch
         M = self.N if targets is None else int(targets.numel())
         if acc is None:
@@ -316,7 +327,7 @@ class Tree:
             pot = torch.empty(M, dtype=torch.float64, device=self.device)
         nint = torch.empty(M, dtype=torch.int64, device=self.device) if with_counts else None
         og_tree_force(self.handle, targets, acc, pot if with_pot else None, precision=precision,
-                      stream=stream, n_inter=nint)
+                      stream=stream, n_inter=nint, a_old=a_old)
         if with_counts:
             return acc, pot, nint
         return acc, pot

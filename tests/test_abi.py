@@ -30,11 +30,12 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_default_and_struct_layout():
     p = og.og_params_default()
-    assert p.struct_size == ctypes.sizeof(og.og_params) == 96
-    assert (p.G, p.eps, p.r_s, p.r_cut, p.theta) == (1.0, 0.0, 0.0, 0.0, 0.5)
+    assert p.struct_size == ctypes.sizeof(og.og_params) == 112
+    assert (p.G, p.eps, p.r_s, p.r_cut, p.theta, p.alpha) == (1.0, 0.0, 0.0, 0.0, 0.5, 0.0)
     assert (p.periodic, p.leaf_max, p.precision, p.group_max, p.walk_list_cap) == (1, 8, og.OG_PREC_MIXED, 0, 0)
-    assert ctypes.sizeof(og.og_box) == 8 + 8 + 8 + 8 + 96 + 8 + 8
-    assert ctypes.sizeof(og.og_force_opts) == 24
+    assert (p.softening, p.criterion) == (og.OG_SOFT_PLUMMER, og.OG_OPEN_BH)
+    assert ctypes.sizeof(og.og_box) == 8 + 8 + 8 + 8 + 112 + 8 + 8
+    assert ctypes.sizeof(og.og_force_opts) == 32
 
 
 def test_workspace_bound_monotone_and_rejects_bad_input():
@@ -53,6 +54,9 @@ def test_workspace_bound_monotone_and_rejects_bad_input():
 @pytest.mark.parametrize("field,value", [
     ("eps", -1.0), ("theta", -0.1), ("leaf_max", 0), ("leaf_max", 5000), ("group_max", 65),
     ("precision", 7), ("r_s", 0.0), ("r_cut", 0.6), ("walk_list_cap", 12),
+    ("softening", 2), ("criterion", 3),
+    ("softening", 1),   # spline with eps = 0
+    ("criterion", 1),   # relative criterion with alpha = 0
 ])
 def test_build_rejects_bad_params_on_host(field, value):
     lib = og.load()
@@ -81,3 +85,30 @@ def test_strerror_codes():
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.og_strerror(code)
     assert lib.og_strerror(0) == b"ok"
+
+
+def test_header_layout_matches_binding(tmp_path):
+    """The C compiler's layout of og.h's structs equals the binding's."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = {"og_params": [f[0] for f in og.og_params._fields_],
+              "og_force_opts": [f[0] for f in og.og_force_opts._fields_],
+              "og_box": [f[0] for f in og.og_box._fields_],
+              "og_targets": [f[0] for f in og.og_targets._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "og.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (st, st))
+        for f in fs:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (st, f, st, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                         text=True).stdout.splitlines())
+    for st, fs in fields.items():
+        cls = getattr(og, st)
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in fs:
+            assert int(got["%s.%s" % (st, f)]) == getattr(cls, f).offset, (st, f)

@@ -153,6 +153,8 @@ def test_mixed_walk_error(og_mod, oracle_mod, case):
           % (np.median(e), np.percentile(e, 99), e.max(), int((g["nint"] != nint).sum())))
     assert np.median(e) <= 1e-3
     assert np.percentile(e, 99) <= 1e-2
+    # FP32 decisions may flip a few opening/cutoff tests, no more
+    assert (g["nint"] != nint).mean() <= 0.01
     pe = np.abs(g["pot"] - pot) / np.abs(pot).max()
     assert np.median(pe) <= 1e-4
 
