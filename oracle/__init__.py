@@ -39,7 +39,7 @@ def _load():
         I = ctypes.c_int
         lib.ogo_frame.argtypes = [P, I64, D, I, P, P]
         lib.ogo_frame.restype = I
-        lib.ogo_keys.argtypes = [P, I64, P, D, P]
+        lib.ogo_keys.argtypes = [P, I64, P, D, I, P]
         lib.ogo_keys.restype = None
         lib.ogo_sort.argtypes = [P, I64, P]
         lib.ogo_sort.restype = None
@@ -72,6 +72,7 @@ class Params:
     periodic: int = 1
     leaf_max: int = 8
     softening: int = 0      # 0 Plummer, 1 cubic spline (support 2.8 eps)
+    curve: int = 0          # 0 Morton, 1 Peano-Hilbert
     criterion: int = 0      # 0 Barnes-Hut (theta), 1 relative (alpha, a_old)
     alpha: float = 0.0
 
@@ -132,13 +133,14 @@ def frame(pos, box, periodic):
     return lo, float(L[0])
 
 
-def keys(pos, box, periodic=1):
-    """Morton keys (uint64, caller order) of the positions."""
+def keys(pos, box, periodic=1, curve=0):
+    """Curve keys (uint64, caller order) of the positions: Morton (curve 0)
+    or Peano-Hilbert (curve 1)."""
     lib = _load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     lo, L = frame(pos, box, periodic)
     k = np.empty(pos.shape[0], dtype=np.uint64)
-    lib.ogo_keys(_p(pos), pos.shape[0], _p(lo), L, _p(k))
+    lib.ogo_keys(_p(pos), pos.shape[0], _p(lo), L, int(curve), _p(k))
     return k
 
 
@@ -151,7 +153,7 @@ def build_tree(pos, mass, box, params: Params) -> Tree:
         raise OracleError("empty particle set")
     lo, L = frame(pos, box, params.periodic)
     k = np.empty(n, dtype=np.uint64)
-    lib.ogo_keys(_p(pos), n, _p(lo), L, _p(k))
+    lib.ogo_keys(_p(pos), n, _p(lo), L, int(params.curve), _p(k))
     perm = np.empty(n, dtype=np.uint32)
     lib.ogo_sort(_p(k), n, _p(perm))
     skeys = np.ascontiguousarray(k[perm])
@@ -166,10 +168,10 @@ def build_tree(pos, mass, box, params: Params) -> Tree:
     if nn < 0:
         raise OracleError("node bound exceeded")
     first, count, level, skip, parent = (a[:nn].copy() for a in (first, count, level, skip, parent))
+    spos = np.ascontiguousarray(pos[perm])
     centre = np.empty((nn, 3))
     side = np.empty(nn)
-    lib.ogo_node_centres(_p(skeys), nn, _p(first), _p(level), _p(lo), L, _p(centre), _p(side))
-    spos = np.ascontiguousarray(pos[perm])
+    lib.ogo_node_centres(_p(spos), nn, _p(first), _p(level), _p(lo), L, _p(centre), _p(side))
     smass = np.ascontiguousarray(mass[perm])
     nmass = np.empty(nn)
     com = np.empty((nn, 3))

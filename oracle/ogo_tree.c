@@ -27,6 +27,11 @@
  *       factors of R2 multiply that softened force and potential.
  *   R25 relative opening criterion (switch): open iff
  *       G M side^2 > alpha |a_old| r^4 (r = |COM - x|), or by R6.
+ *   R26 Peano-Hilbert keys (switch): the cell's three 21-bit coordinates
+ *       are turned into the transposed Hilbert index of Skilling (2004,
+ *       "Programming the Hilbert curve") and interleaved as in R11.  The
+ *       set of cells, hence of nodes, is the Morton one; children are
+ *       ordered along the curve.
  *
  * Every function cites the passage it follows.  Summation order: the walk
  * adds contributions in traversal order; moments are summed particle by
@@ -90,13 +95,44 @@ static uint32_t ogo_cell(double x, double lo, double scale)
     return (uint32_t)v; /* v >= 0: truncation toward zero */
 }
 
-void ogo_keys(const double *pos, int64_t n, const double *lo3, double L,
+/* R26: Skilling's transform of cell coordinates into the "transposed"
+ * Hilbert index (paper, "Tree construction" and "Domain decomposition":
+ * particles follow the Peano-Hilbert curve).  Going from the top bit down,
+ * at bit q the lower bits are either inverted (when coordinate i has bit q
+ * set) or exchanged between coordinate 0 and i; then the result is Gray
+ * coded.  Interleaving the three outputs, coordinate 0 first, gives the
+ * index along the curve.                                                   */
+static void ogo_hilbert(uint32_t c[3])
+{
+    for (uint32_t q = 1u << (OGO_LEVELS - 1); q > 1; q >>= 1) {
+        uint32_t low = q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (c[i] & q) {
+                c[0] ^= low;
+            } else {
+                uint32_t t = (c[0] ^ c[i]) & low;
+                c[0] ^= t;
+                c[i] ^= t;
+            }
+        }
+    }
+    c[1] ^= c[0];
+    c[2] ^= c[1];
+    uint32_t flip = 0;
+    for (uint32_t q = 1u << (OGO_LEVELS - 1); q > 1; q >>= 1)
+        if (c[2] & q) flip ^= q - 1;
+    for (int i = 0; i < 3; ++i) c[i] ^= flip;
+}
+
+/* curve: 0 Morton (R11), 1 Peano-Hilbert (R26). */
+void ogo_keys(const double *pos, int64_t n, const double *lo3, double L, int curve,
               uint64_t *keys)
 {
     double scale = OGO_GRID / L;
     for (int64_t i = 0; i < n; ++i) {
         uint32_t c[3];
         for (int k = 0; k < 3; ++k) c[k] = ogo_cell(pos[3 * i + k], lo3[k], scale);
+        if (curve == 1) ogo_hilbert(c);
         uint64_t key = 0;
         for (int b = 0; b < OGO_LEVELS; ++b) {
             key |= (uint64_t)((c[0] >> b) & 1u) << (3 * b + 2);
@@ -179,39 +215,31 @@ int64_t ogo_topology(const uint64_t *skeys, int64_t n, int leaf_max, int64_t cap
 
 /* ------------------------------------------------------------- geometry --
  * Cube of a node (paper, "Tree construction": cubic cell centre and side).
- * Corner cell c = the first particle's cell with the low (21 - level) bits
- * cleared; side = L 2^-level; centre = lo + (c + 2^(20-level)) L 2^-21.    */
-static void ogo_cell_of_key(uint64_t key, uint32_t c[3])
-{
-    c[0] = c[1] = c[2] = 0;
-    for (int b = 0; b < OGO_LEVELS; ++b) {
-        c[0] |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
-        c[1] |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
-        c[2] |= (uint32_t)((key >> (3 * b)) & 1u) << b;
-    }
-}
-
-static void ogo_node_geometry(uint64_t first_key, int level, const double *lo3,
+ * Corner cell c = the node's first particle's cell (as for its key) with
+ * the low (21 - level) bits cleared; side = L 2^-level;
+ * centre = lo + (c + 2^(20-level)) L 2^-21.  spos: sorted positions.      */
+static void ogo_node_geometry(const double *x, int level, const double *lo3,
                               double L, double centre[3], double *side)
 {
-    uint32_t c[3];
-    ogo_cell_of_key(first_key, c);
+    double scale = OGO_GRID / L;
     int drop = OGO_LEVELS - level;
     double h = ldexp(L, -OGO_LEVELS);
     double half = ldexp(1.0, drop - 1);
     for (int k = 0; k < 3; ++k) {
-        uint32_t corner = (c[k] >> drop) << drop;
+        uint32_t c = ogo_cell(x[k], lo3[k], scale);
+        uint32_t corner = (c >> drop) << drop;
         centre[k] = lo3[k] + ((double)corner + half) * h;
     }
     *side = ldexp(L, -level);
 }
 
-void ogo_node_centres(const uint64_t *skeys, int64_t n_nodes, const uint32_t *first,
+void ogo_node_centres(const double *spos, int64_t n_nodes, const uint32_t *first,
                       const uint8_t *level, const double *lo3, double L,
                       double *centre3, double *side)
 {
     for (int64_t r = 0; r < n_nodes; ++r)
-        ogo_node_geometry(skeys[first[r]], level[r], lo3, L, centre3 + 3 * r, side + r);
+        ogo_node_geometry(spos + 3 * (int64_t)first[r], level[r], lo3, L, centre3 + 3 * r,
+                          side + r);
 }
 
 /* -------------------------------------------------------------- moments --
