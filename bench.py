@@ -123,9 +123,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
-    ap.add_argument("--legs", default="batch,serving,zeldovich,variants",
+    ap.add_argument("--legs", default="batch,serving,zeldovich,variants,hilbert,active",
                     help="extra workloads reported beside the headline: batch, serving, zeldovich, "
-                         "variants (comma list, or 'none')")
+                         "variants, hilbert, active (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -240,7 +240,7 @@ def main():
     torch.cuda.empty_cache()
     for leg in legs:
         fn = {"batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich,
-              "variants": leg_variants}[leg]
+              "variants": leg_variants, "hilbert": leg_hilbert, "active": leg_active}[leg]
         log("leg %s" % leg)
         try:
             out[LEG_NAMES[leg]] = fn(og, torch, synth, args)
@@ -307,7 +307,7 @@ def main():
 
 
 LEG_NAMES = {"batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256",
-             "variants": "variants_mixture2m"}
+             "variants": "variants_mixture2m", "hilbert": "hilbert_mixture2m", "active": "active_mixture2m"}
 
 
 def _oracle_params(oracle, prm):
@@ -559,6 +559,101 @@ def leg_variants(og, torch, synth, args):
     out["workload"] = "mixture2m as the headline; variants: %s" % ", ".join(
         "%s=%s" % (k, v) for k, v in VARIANT_LEGS)
     return out
+
+
+def leg_hilbert(og, torch, synth, args):
+    """The headline box with Peano-Hilbert keys: same nodes, curve order for
+    the particles, the children and the walk groups."""
+    w = synth.mixture2m(theta=args.theta)
+    n = w.pos.shape[0]
+    prm = dict(w.params.as_dict(), curve="hilbert")
+    tp = torch.as_tensor(w.pos, device="cuda")
+    tm = torch.as_tensor(w.mass, device="cuda")
+    wsb = torch.empty(og.og_tree_workspace_bound(n, og.make_params(prm)), dtype=torch.uint8, device="cuda")
+    out = {}
+    for prec, steps in (("mixed", 5), ("fp64", 2)):
+        r = time_steps(og, torch, tp, tm, prm, wsb, prec, steps, 1)
+        for t in r["trees"]:
+            t.close()
+        out[prec] = {"value": n / (r["total_ms"] / steps * 1e-3), "ms_per_step": r["total_ms"] / steps,
+                     "build_ms": float(r["build_ms"].mean()), "walk_ms": float(r["walk_ms"].mean())}
+        log("  hilbert %s: %.3f ms/step (build %.3f, walk %.3f)" % (prec, out[prec]["ms_per_step"],
+                                                                   out[prec]["build_ms"], out[prec]["walk_ms"]))
+    if not args.no_oracle:
+        import oracle
+        rng = np.random.default_rng(11)
+        tg = np.sort(rng.choice(n, 4096, replace=False))
+        t = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream(), workspace=wsb)
+        tgd = torch.as_tensor(tg, device="cuda")
+        am, _ = t.force(targets=tgd, precision="mixed")
+        ad, _, nd = t.force(targets=tgd, precision="fp64", with_counts=True)
+        torch.cuda.synchronize()
+        t.close()
+        op = oracle.Params(**{**{k: w.params.as_dict()[k] for k in ("G", "eps", "r_s", "r_cut", "theta",
+                                                                    "periodic", "leaf_max")}, "curve": 1})
+        a_o, _, n_o = oracle.tree_force(w.pos, w.mass, 1.0, op, targets=tg)
+        e_m = _rel_err(am.cpu().numpy(), a_o)
+        out["error_vs_oracle"] = {"targets": int(tg.size), "mixed_median": float(np.median(e_m)),
+                                  "mixed_p99": float(np.percentile(e_m, 99)),
+                                  "fp64_max": float(_rel_err(ad.cpu().numpy(), a_o).max()),
+                                  "fp64_counts_equal": bool(np.array_equal(nd.cpu().numpy(), n_o))}
+    out["workload"] = "mixture2m as the headline, Peano-Hilbert keys"
+    return out
+
+
+def leg_active(og, torch, synth, args):
+    """Individual power-of-two time steps on a resident tree: time-step
+    levels from the Gadget-style criterion dt = sqrt(2 eta eps / |a|)
+    (eta = 0.025) on the headline box's forces, level b = floor(log2(dt /
+    dt_min)) capped at 6; one cycle of 64 substeps, substep s walking the
+    particles with level <= ctz(s) (og_tree_force_active, no host sync)."""
+    w = synth.mixture2m(theta=args.theta)
+    n = w.pos.shape[0]
+    prm = w.params.as_dict()
+    tp = torch.as_tensor(w.pos, device="cuda")
+    tm = torch.as_tensor(w.mass, device="cuda")
+    stream = torch.cuda.current_stream()
+    tree = og.Tree(tp, tm, 1.0, prm, stream=stream)
+    a, _ = tree.force(precision="mixed")
+    amag = torch.linalg.norm(a, dim=1).cpu().numpy()
+    dt = np.sqrt(2 * 0.025 * prm["eps"] / np.maximum(amag, 1e-300))
+    kmax = 6
+    bins_np = np.clip(np.floor(np.log2(dt / dt.min())), 0, kmax).astype(np.int8)
+    bins = torch.as_tensor(bins_np, device="cuda")
+    acc = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    pot = torch.empty(n, dtype=torch.float64, device="cuda")
+    nact = torch.zeros(2 ** kmax, dtype=torch.int64, device="cuda")
+    levels = [min((s & -s).bit_length() - 1, kmax) for s in range(1, 2 ** kmax + 1)]
+    for _ in range(2):  # warm-up cycle
+        for s, lev in enumerate(levels):
+            tree.force_active(bins, lev, acc, pot, n_active=nact[s:s + 1])
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for s, lev in enumerate(levels):
+        tree.force_active(bins, lev, acc, pot, n_active=nact[s:s + 1])
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    cycle_ms = ev[0].elapsed_time(ev[1])
+    counts = nact.cpu().numpy()
+    expect = np.array([(bins_np <= lev).sum() for lev in levels])
+    # the same cycle with every particle walked on every substep
+    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev2[0].record(stream)
+    for _ in range(4):
+        tree.force(precision="mixed", acc=acc, pot=pot)
+    ev2[1].record(stream)
+    torch.cuda.synchronize()
+    full_ms = ev2[0].elapsed_time(ev2[1]) / 4
+    tree.close()
+    tot = int(counts.sum())
+    return {"substeps": len(levels), "levels_histogram": np.bincount(bins_np, minlength=kmax + 1).tolist(),
+            "active_forces": tot, "cycle_ms": cycle_ms, "value": tot / (cycle_ms * 1e-3), "unit": "particles/s",
+            "counts_match": bool(np.array_equal(counts, expect)),
+            "all_particles_every_substep_ms": full_ms * len(levels),
+            "speedup_vs_all_every_substep": full_ms * len(levels) / cycle_ms,
+            "workload": "mixture2m resident tree (mixed walk), levels 0..%d from dt = sqrt(2 eta eps/|a|), "
+                        "eta 0.025; one cycle of %d substeps" % (kmax, len(levels))}
 
 
 def _cpu_model():

@@ -88,6 +88,14 @@ enum { OG_SOFT_PLUMMER = 0, OG_SOFT_SPLINE = 1 };
  * acceleration (og_force_opts.a_old); r = |COM - x| (minimum image). */
 enum { OG_OPEN_BH = 0, OG_OPEN_RELATIVE = 1 };
 
+/* Space-filling curve of the particle order and of the children of every
+ * node (paper, "Tree construction": insertion in Peano-Hilbert order).
+ * MORTON: 63-bit key, bit 3b+2 = x bit b, 3b+1 = y, 3b = z.  HILBERT: the
+ * cell coordinates are first mapped to the transposed Hilbert index
+ * (Skilling 2004) and then interleaved the same way.  The nodes (cells) are
+ * the same for both; only their order, hence the summation order, differs. */
+enum { OG_CURVE_MORTON = 0, OG_CURVE_HILBERT = 1 };
+
 typedef struct og_params {
     uint32_t struct_size;   /* = sizeof(og_params) (ABI check) */
     double G;               /* gravitational constant (default 1) */
@@ -110,14 +118,15 @@ typedef struct og_params {
     int32_t softening;      /* OG_SOFT_PLUMMER (default) or OG_SOFT_SPLINE
                                (needs eps > 0) */
     int32_t criterion;      /* OG_OPEN_BH (default) or OG_OPEN_RELATIVE */
+    int32_t curve;          /* OG_CURVE_MORTON (default) or OG_CURVE_HILBERT */
     void *stream;           /* hipStream_t, NULL = default stream */
     void *workspace;        /* optional caller device buffer for the tree */
     size_t workspace_bytes; /* its size; must be >= og_tree_workspace_bound */
 } og_params;
 
 /* Defaults: G 1, eps 0, r_s 0, r_cut 0, theta 0.5, alpha 0, periodic 1,
- * leaf_max 8, MIXED, group_max 0, walk_list_cap 0, PLUMMER, BH, no stream,
- * no workspace. */
+ * leaf_max 8, MIXED, group_max 0, walk_list_cap 0, PLUMMER, BH, MORTON, no
+ * stream, no workspace. */
 void og_params_default(og_params *p);
 
 /* Device bytes one tree over N particles needs (upper bound, independent of
@@ -138,7 +147,7 @@ typedef struct og_tree og_tree;
  * bounds.  Errors: OG_EINVAL (N < 1 or > 2^27-1, box <= 0, eps < 0,
  * theta < 0, leaf_max outside 1..4096, group_max outside 0..64,
  * walk_list_cap not 0, 4, 8, 16 or 32, periodic
- * with r_s <= 0 or r_cut >= box/2, unknown softening or criterion, SPLINE
+ * with r_s <= 0 or r_cut >= box/2, unknown softening, criterion or curve, SPLINE
  * with eps = 0, RELATIVE with alpha <= 0, null pointers, host pointers),
  * OG_ENOMEM, OG_EDEVICE. */
 int og_tree_build(const double *pos, const double *mass, int64_t N, double box,
@@ -173,6 +182,24 @@ typedef struct og_force_opts {
 /* As og_tree_force, with a precision, stream and interaction counts. */
 int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_force_opts *opts,
                      double *acc, double *pot);
+
+/* Forces on the active particles only (paper, "Code structure": particles
+ * move on individual power-of-two time steps; at a step, those on the
+ * current time-step level and below are active).  The tree stays resident
+ * and is walked only for them.
+ *   bin:   device [N] int8, caller order: each particle's time-step level
+ *   level: particle i is active iff bin[i] <= level
+ *   opts:  as og_tree_force_ex (NULL: the tree's precision and stream);
+ *          n_inter, when given, is [N] in caller order
+ *   acc:   device [N][3] FP64, pot: device [N] FP64 or NULL, caller order;
+ *          only the active particles' entries are written
+ *   n_active: device int64 [1] or NULL: receives the number of active
+ *          particles
+ * Nothing is read back to the host: the active list is compacted on the
+ * device, in curve order, and the walk reads its length there.  Errors as
+ * og_tree_force_ex. */
+int og_tree_force_active(const og_tree *tree, const int8_t *bin, int32_t level, const og_force_opts *opts,
+                         double *acc, double *pot, int64_t *n_active);
 
 /* Synchronise the tree's stream and report the device-side status of the
  * build: OG_OK or OG_ERANGE. */

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_keys(const BoxDev *boxes, int B, u
     c[k] = cell_of(v, bx.lo[k], bx.scale, bad);
   }
   if (bad) atomicOr(status, kStatusRange);
-  keys[g] = morton3(c[0], c[1], c[2]);
+  keys[g] = bx.curve ? hilbert3(c[0], c[1], c[2]) : morton3(c[0], c[1], c[2]);
   vals[g] = g;
 }
 
@@ -468,7 +468,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const BoxDev *boxes, int B, u
   const BoxDev &bx = boxes[box_of(boxes, B, p)];
   const uint32_t b1 = bx.p_off + bx.n;
   const uint64_t key = skeys[p];
-  const uint32_t cx = compact3(key >> 2), cy = compact3(key >> 1), cz = compact3(key);
+  uint32_t cc[3];
+  key_cell(key, bx.curve, cc);
+  const uint32_t cx = cc[0], cy = cc[1], cz = cc[2];
   uint32_t rank = S[p];
   for (int L = l0 + 1; L <= d; ++L, ++rank) {
     if (rank >= node_cap) return;
@@ -794,6 +796,42 @@ void launch_build(BuildArrays &A, hipStream_t s) {
                                               A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32);
   k_wnodes<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.mom32, A.first, A.scalars, A.node_cap,
                                        A.wnode);
+}
+
+// Active targets (see ActiveArrays).  Flags and the compaction run over the
+// sorted order, so the active list keeps the curve order of the tree.
+__global__ __launch_bounds__(kThreads) void k_active_flags(const uint32_t *perm, const int8_t *bin,
+                                                           int32_t level, uint32_t n, uint32_t *flags) {
+  const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  flags[p] = (int32_t)bin[perm[p]] <= level ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_active_scatter(const uint32_t *flags, const uint32_t *offs,
+                                                             const uint32_t *perm, uint32_t n, uint32_t chunk,
+                                                             uint64_t *tkey, uint32_t *tval, uint32_t *counts,
+                                                             int64_t *n_active) {
+  const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  if (p == 0) {
+    const uint32_t m = offs[n];
+    counts[0] = m;
+    counts[1] = (m + chunk - 1) / chunk;
+    if (n_active) *n_active = (int64_t)m;
+  }
+  if (p >= n || !flags[p]) return;
+  const uint32_t o = offs[p];
+  tkey[o] = p;
+  tval[o] = perm[p];
+}
+
+size_t scan_partial_words(uint32_t n) { return cdiv((uint64_t)n + 1, kScanTile) + 1; }
+
+void launch_active(const BuildArrays &A, ActiveArrays &T, uint32_t chunk, hipStream_t s) {
+  const uint32_t n = A.n;
+  k_active_flags<<<cdiv(n, kThreads), kThreads, 0, s>>>(A.perm, T.bin, T.level, n, T.flags);
+  scan_u32(T.flags, T.offs, &A.scalars[4], n, T.partial, s);
+  k_active_scatter<<<cdiv(n, kThreads), kThreads, 0, s>>>(T.flags, T.offs, A.perm, n, chunk, T.tkey, T.tval,
+                                                         T.counts, T.n_active);
 }
 
 void launch_targets(const BuildArrays &A, TargetArrays &T, hipStream_t s) {

@@ -100,6 +100,7 @@ __device__ inline BoxDev ld(const BoxDev *p) {
   b.alpha = q->alpha;
   b.hsf = q->hsf;
   b.hinvf = q->hinvf;
+  b.curve = q->curve;
   return b;
 }
 
@@ -192,6 +193,13 @@ __device__ inline uint32_t pop_group(GroupQueue &Q, uint32_t lane) {
   }
   return Q.n_groups;
 }
+// Target and group counts produced on the device (active targets).
+__device__ inline void device_counts(WalkArgs &A) {
+  if (A.dev_count) {
+    A.n_targets = cptr(A.dev_count)[0];
+    A.n_groups = cptr(A.dev_count)[1];
+  }
+}
 __device__ inline GroupQueue make_queue(const WalkArgs &A) {
   GroupQueue Q;
   Q.counters = A.counter;
@@ -267,6 +275,7 @@ template <bool kExt>
 __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
 #pragma clang fp contract(off)
   const uint32_t lane = threadIdx.x & 63;
+  device_counts(A);
   GroupQueue Q = make_queue(A);
   while (true) {
     const uint32_t g = pop_group(Q, lane);
@@ -564,6 +573,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ float4 list[kCap][kWalk32Threads];
   const uint32_t lane = threadIdx.x;
+  device_counts(A);
   GroupQueue Q = make_queue(A);
   while (true) {
     const uint32_t g = pop_group(Q, lane);
@@ -599,10 +609,11 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
     int o0 = 0, o1 = 0, o2 = 0;
     float xr = 0.0f, yr = 0.0f, zr = 0.0f;
     if (valid) {
-      const uint64_t key = A.skeys[p];
-      o0 = 2 * (int)compact3(key >> 2) + 1;
-      o1 = 2 * (int)compact3(key >> 1) + 1;
-      o2 = 2 * (int)compact3(key) + 1;
+      uint32_t cc[3];
+      key_cell(A.skeys[p], bx.curve, cc);
+      o0 = 2 * (int)cc[0] + 1;
+      o1 = 2 * (int)cc[1] + 1;
+      o2 = 2 * (int)cc[2] + 1;
       const double h22 = bx.L * 0x1p-22;
       const double4 q = A.part64[p];
       xr = (float)(q.x - (bx.lo[0] + (double)o0 * h22));

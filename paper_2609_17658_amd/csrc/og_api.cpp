@@ -126,6 +126,8 @@ int check_params(const og_params *p, int64_t N, double box, bool need_stream_fie
   if (p->softening != OG_SOFT_PLUMMER && p->softening != OG_SOFT_SPLINE)
     return fail(OG_EINVAL, "unknown softening %d", p->softening);
   if (p->softening == OG_SOFT_SPLINE && !(p->eps > 0.0)) return fail(OG_EINVAL, "spline softening needs eps > 0");
+  if (p->curve != OG_CURVE_MORTON && p->curve != OG_CURVE_HILBERT)
+    return fail(OG_EINVAL, "unknown curve %d", p->curve);
   if (p->criterion != OG_OPEN_BH && p->criterion != OG_OPEN_RELATIVE)
     return fail(OG_EINVAL, "unknown opening criterion %d", p->criterion);
   if (p->criterion == OG_OPEN_RELATIVE && !(p->alpha > 0.0 && std::isfinite(p->alpha)))
@@ -171,6 +173,7 @@ void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, doubl
   b.alpha = p.alpha;
   b.hsf = (float)b.hs;
   b.hinvf = b.spline ? (float)(1.0 / b.hs) : 0.0f;
+  b.curve = p.curve == OG_CURVE_HILBERT ? 1 : 0;
   if (b.periodic) {
     b.lo[0] = b.lo[1] = b.lo[2] = 0.0;
     b.L = box;
@@ -318,6 +321,49 @@ int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M,
   return OG_OK;
 }
 
+int Forest::walk_active(int prec, hipStream_t s, const int8_t *bin, int32_t level, double *acc, double *pot,
+                        int64_t *nint, const double *a_old, int64_t *n_active) {
+  ActiveArrays T{};
+  auto plan = [&](Carver &cv) {
+    T.flags = cv.take<uint32_t>(N);
+    T.offs = cv.take<uint32_t>((size_t)N + 1);
+    T.partial = cv.take<uint32_t>(scan_partial_words(N));
+    T.tkey = cv.take<uint64_t>(N);
+    T.tval = cv.take<uint32_t>(N);
+    T.counts = cv.take<uint32_t>(32);
+  };
+  Carver c;
+  plan(c);
+  void *tmp = nullptr;
+  hipError_t e = hipMallocAsync(&tmp, c.off + 256, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(active)");
+  Carver c2;
+  c2.base = static_cast<char *>(tmp);
+  plan(c2);
+  T.bin = bin;
+  T.level = level;
+  T.n_active = n_active;
+  launch_active(A, T, group_max, s);
+  WalkArgs W = walk_args();
+  W.n_groups = (N + group_max - 1) / group_max;  // bound for the grid; the count is read on the device
+  W.n_targets = N;
+  W.dev_count = T.counts;
+  W.counter = &T.counts[8];
+  W.tkey = T.tkey;
+  W.tval = T.tval;
+  W.acc = acc;
+  W.pot = pot;
+  W.pot_override = 1;
+  W.nint = nint;
+  W.a_old = a_old;
+  launch_walk(W, prec, s);
+  e = hipGetLastError();
+  hipError_t e2 = hipFreeAsync(tmp, s);
+  if (e != hipSuccess) return hip_fail(e, "walk launch (active)");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync(active)");
+  return OG_OK;
+}
+
 int Forest::read_status(hipStream_t s) {
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -452,6 +498,48 @@ int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_fo
 
 int og_tree_force(const og_tree *tree, const og_targets *targets, double *acc, double *pot) {
   return og_tree_force_ex(tree, targets, nullptr, acc, pot);
+}
+
+int og_tree_force_active(const og_tree *tree, const int8_t *bin, int32_t level, const og_force_opts *opts,
+                         double *acc, double *pot, int64_t *n_active) {
+  if (!tree) return fail(OG_EINVAL, "tree is NULL");
+  og_tree *t = const_cast<og_tree *>(tree);
+  Forest &F = t->F;
+  int prec = F.precision;
+  hipStream_t s = F.stream;
+  int64_t *nint = nullptr;
+  const double *a_old = nullptr;
+  if (opts) {
+    if (opts->struct_size != sizeof(og_force_opts)) return fail(OG_EINVAL, "og_force_opts.struct_size mismatch");
+    if (opts->precision >= 0) {
+      if (opts->precision != OG_PREC_FP64 && opts->precision != OG_PREC_MIXED)
+        return fail(OG_EINVAL, "unknown precision %d", opts->precision);
+      prec = opts->precision;
+    }
+    if (opts->stream) s = (hipStream_t)opts->stream;
+    nint = opts->n_inter;
+    a_old = opts->a_old;
+  }
+  if (!is_device_ptr(bin)) return fail(OG_EINVAL, "bin must be a device pointer");
+  if (!is_device_ptr(acc)) return fail(OG_EINVAL, "acc must be a device pointer");
+  if (pot && !is_device_ptr(pot)) return fail(OG_EINVAL, "pot must be a device pointer");
+  if (nint && !is_device_ptr(nint)) return fail(OG_EINVAL, "n_inter must be a device pointer");
+  if (n_active && !is_device_ptr(n_active)) return fail(OG_EINVAL, "n_active must be a device pointer");
+  if (F.hboxes[0].relative) {
+    if (!a_old) return fail(OG_EINVAL, "the relative criterion needs a_old (og_force_opts)");
+    if (!is_device_ptr(a_old)) return fail(OG_EINVAL, "a_old must be a device pointer");
+  } else {
+    a_old = nullptr;
+  }
+  if (s != F.stream) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    hipEventRecord(ev, F.stream);
+    hipStreamWaitEvent(s, ev, 0);
+    hipEventDestroy(ev);
+  }
+  return F.walk_active(prec, s, bin, level, acc, pot, nint, a_old, n_active);
 }
 
 int og_tree_status(const og_tree *tree) {

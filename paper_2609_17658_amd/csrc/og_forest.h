@@ -46,6 +46,8 @@ struct Forest {
                const double *a_old = nullptr);
   int walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
                   int64_t *nint, const double *a_old = nullptr);
+  int walk_active(int prec, hipStream_t s, const int8_t *bin, int32_t level, double *acc, double *pot,
+                  int64_t *nint, const double *a_old, int64_t *n_active);
   int read_status(hipStream_t s);
   void release();
 };

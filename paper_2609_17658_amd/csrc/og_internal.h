@@ -41,6 +41,7 @@ struct BoxDev {
   int32_t spline, relative;  // softening kernel, opening criterion
   double hs, alpha;          // spline support 2.8 eps; relative tolerance
   float hsf, hinvf;          // FP32 support and its inverse
+  int32_t curve;             // 0 Morton, 1 Peano-Hilbert keys
 };
 
 // Walk-order node record, 16 bytes.
@@ -103,6 +104,69 @@ __host__ __device__ inline uint32_t compact3(uint64_t x) {
 }
 __host__ __device__ inline uint64_t morton3(uint32_t cx, uint32_t cy, uint32_t cz) {
   return (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+}
+
+// Peano-Hilbert order of level-21 cells (Skilling 2004, "Programming the
+// Hilbert curve"): the coordinates are mapped to the transposed Hilbert
+// index and interleaved like Morton coordinates.  Encoding walks the bits
+// from the top: at bit q, the bits below q of coordinate 0 are inverted
+// when coordinate i has bit q set, otherwise the bits below q are swapped
+// between coordinate 0 and i; a Gray code finishes it.  Every level-l cell
+// is a run of 8^(21-l) consecutive keys whose top 3l bits name the cell.
+__host__ __device__ inline uint64_t hilbert3(uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t c[3] = {x, y, z};
+  for (uint32_t q = 1u << (kLevels - 1); q > 1; q >>= 1) {
+    const uint32_t low = q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (c[i] & q) {
+        c[0] ^= low;
+      } else {
+        const uint32_t t = (c[0] ^ c[i]) & low;
+        c[0] ^= t;
+        c[i] ^= t;
+      }
+    }
+  }
+  c[1] ^= c[0];
+  c[2] ^= c[1];
+  uint32_t flip = 0;
+  for (uint32_t q = 1u << (kLevels - 1); q > 1; q >>= 1)
+    if (c[2] & q) flip ^= q - 1;
+  return morton3(c[0] ^ flip, c[1] ^ flip, c[2] ^ flip);
+}
+// Inverse of hilbert3: the cell of a key.
+__host__ __device__ inline void hilbert3_cell(uint64_t key, uint32_t c[3]) {
+  c[0] = compact3(key >> 2);
+  c[1] = compact3(key >> 1);
+  c[2] = compact3(key);
+  // undo the Gray code
+  const uint32_t t = c[2] >> 1;
+  c[2] ^= c[1];
+  c[1] ^= c[0];
+  c[0] ^= t;
+  // undo the per-bit inversions and swaps, from the lowest bit up
+  for (uint32_t q = 2; q != (1u << kLevels); q <<= 1) {
+    const uint32_t low = q - 1;
+    for (int i = 2; i >= 0; --i) {
+      if (c[i] & q) {
+        c[0] ^= low;
+      } else {
+        const uint32_t u = (c[0] ^ c[i]) & low;
+        c[0] ^= u;
+        c[i] ^= u;
+      }
+    }
+  }
+}
+// Cell of a key on either curve (curve 0 Morton, 1 Peano-Hilbert).
+__host__ __device__ inline void key_cell(uint64_t key, int curve, uint32_t c[3]) {
+  if (curve) {
+    hilbert3_cell(key, c);
+  } else {
+    c[0] = compact3(key >> 2);
+    c[1] = compact3(key >> 1);
+    c[2] = compact3(key);
+  }
 }
 
 // Number of leading 3-bit digits two keys share (0..21); keys < 2^63.

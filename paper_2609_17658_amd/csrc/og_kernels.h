@@ -65,6 +65,22 @@ struct TargetArrays {
 };
 void launch_targets(const BuildArrays &A, TargetArrays &T, hipStream_t s);
 
+// Active targets of one tree: the particles whose time-step level bin[i]
+// (caller order) is <= level, in curve order, compacted on the device.
+// counts[0] = number of active targets, counts[1] = walk groups of `chunk`;
+// n_active (optional) receives counts[0] as int64.
+struct ActiveArrays {
+  const int8_t *bin;
+  int32_t level;
+  uint32_t *flags, *offs, *partial;
+  uint64_t *tkey;
+  uint32_t *tval;
+  uint32_t *counts;           // [0] active, [1] groups, [8..15] walk queues
+  int64_t *n_active;
+};
+void launch_active(const BuildArrays &A, ActiveArrays &T, uint32_t chunk, hipStream_t s);
+size_t scan_partial_words(uint32_t n);
+
 struct WalkArgs {
   const BoxDev *boxes;
   const Topo *topo;
@@ -90,6 +106,7 @@ struct WalkArgs {
   int64_t *nint;
   int pot_override;           // 1: use `pot` (possibly null) instead of the box's
   int ext;                    // some box uses spline softening or the relative criterion
+  const uint32_t *dev_count;  // non-null: n_targets = [0], n_groups = [1], read on the device
   const double *a_old;        // relative criterion: previous accelerations [n][3], caller order
 };
 void launch_walk(const WalkArgs &W, int precision, hipStream_t s);

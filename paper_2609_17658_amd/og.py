@@ -24,6 +24,8 @@ OG_SOFT_PLUMMER, OG_SOFT_SPLINE = 0, 1
 OG_OPEN_BH, OG_OPEN_RELATIVE = 0, 1
 SOFTENINGS = {"plummer": OG_SOFT_PLUMMER, "spline": OG_SOFT_SPLINE, 0: 0, 1: 1}
 CRITERIA = {"bh": OG_OPEN_BH, "relative": OG_OPEN_RELATIVE, 0: 0, 1: 1}
+OG_CURVE_MORTON, OG_CURVE_HILBERT = 0, 1
+CURVES = {"morton": OG_CURVE_MORTON, "hilbert": OG_CURVE_HILBERT, 0: 0, 1: 1}
 
 
 class og_params(ctypes.Structure):
@@ -32,7 +34,8 @@ class og_params(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("periodic", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("group_max", ctypes.c_int32),
                 ("walk_list_cap", ctypes.c_int32), ("softening", ctypes.c_int32),
-                ("criterion", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("criterion", ctypes.c_int32), ("curve", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -61,6 +64,8 @@ _SIGNATURES = {
     "og_tree_force": (ctypes.c_int, [_P, ctypes.POINTER(og_targets), _P, _P]),
     "og_tree_force_ex": (ctypes.c_int, [_P, ctypes.POINTER(og_targets), ctypes.POINTER(og_force_opts),
                                         _P, _P]),
+    "og_tree_force_active": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(og_force_opts), _P, _P,
+                                            _P]),
     "og_tree_status": (ctypes.c_int, [_P]),
     "og_tree_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_size_t)]),
@@ -152,6 +157,8 @@ def make_params(params=None, stream=None, workspace=None, **kw) -> og_params:
             v = SOFTENINGS[v]
         elif k == "criterion":
             v = CRITERIA[v]
+        elif k == "curve":
+            v = CURVES[v]
         setattr(p, k, v)
     p.stream = _stream_handle(stream)
     if workspace is not None:
@@ -201,6 +208,16 @@ def og_tree_force(tree, targets, acc, pot, precision=None, stream=None, n_inter=
                          _stream_handle(stream), _ptr(n_inter), _ptr(a_old))
     _check(load().og_tree_force_ex(tree, ctypes.byref(tg) if tg is not None else None,
                                    ctypes.byref(opts), _ptr(acc), _ptr(pot)))
+
+
+def og_tree_force_active(tree, bin, level, acc, pot, precision=None, stream=None, n_inter=None, a_old=None,
+                         n_active=None):
+    """bin: int8 device tensor [N] (caller order); particles with bin <= level
+    get acc/pot (caller order [N]); others' entries are left unchanged."""
+    opts = og_force_opts(ctypes.sizeof(og_force_opts), -1 if precision is None else PRECISIONS[precision],
+                         _stream_handle(stream), _ptr(n_inter), _ptr(a_old))
+    _check(load().og_tree_force_active(tree, _ptr(bin), int(level), ctypes.byref(opts), _ptr(acc), _ptr(pot),
+                                       _ptr(n_active)))
 
 
 def og_tree_status(tree) -> int:
@@ -330,6 +347,14 @@ class Tree:
                       stream=stream, n_inter=nint, a_old=a_old)
         if with_counts:
             return acc, pot, nint
+        return acc, pot
+
+    def force_active(self, bin, level, acc, pot=None, precision=None, n_inter=None, a_old=None,
+                     n_active=None, stream=None):
+        """Forces on particles with bin <= level into acc/pot (caller order,
+        [N]); other entries are not written."""
+        og_tree_force_active(self.handle, bin, level, acc, pot, precision=precision, stream=stream,
+                             n_inter=n_inter, a_old=a_old, n_active=n_active)
         return acc, pot
 
     def status(self) -> int:
