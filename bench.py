@@ -123,9 +123,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
-    ap.add_argument("--legs", default="batch,serving,zeldovich,variants,hilbert,active",
+    ap.add_argument("--legs", default="batch,serving,zeldovich,variants,hilbert,active,pm",
                     help="extra workloads reported beside the headline: batch, serving, zeldovich, "
-                         "variants, hilbert, active (comma list, or 'none')")
+                         "variants, hilbert, active, pm (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -240,7 +240,7 @@ def main():
     torch.cuda.empty_cache()
     for leg in legs:
         fn = {"batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich,
-              "variants": leg_variants, "hilbert": leg_hilbert, "active": leg_active}[leg]
+              "variants": leg_variants, "hilbert": leg_hilbert, "active": leg_active, "pm": leg_pm}[leg]
         log("leg %s" % leg)
         try:
             out[LEG_NAMES[leg]] = fn(og, torch, synth, args)
@@ -307,7 +307,8 @@ def main():
 
 
 LEG_NAMES = {"batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256",
-             "variants": "variants_mixture2m", "hilbert": "hilbert_mixture2m", "active": "active_mixture2m"}
+             "variants": "variants_mixture2m", "hilbert": "hilbert_mixture2m", "active": "active_mixture2m",
+             "pm": "treepm"}
 
 
 def _oracle_params(oracle, prm):
@@ -654,6 +655,82 @@ def leg_active(og, torch, synth, args):
             "speedup_vs_all_every_substep": full_ms * len(levels) / cycle_ms,
             "workload": "mixture2m resident tree (mixed walk), levels 0..%d from dt = sqrt(2 eta eps/|a|), "
                         "eta 0.025; one cycle of %d substeps" % (kmax, len(levels))}
+
+
+def pm_bytes(n_particles, n_grid):
+    """Algorithmic HBM bytes of one mesh force: deposit 32 B/particle read +
+    8 atomics x 8 B; clear 8, density 8 + 16, three 3-D FFTs of three passes
+    each reading and writing 16 B, Green's function 16 + 32, per cell;
+    interpolation 32 B/particle read, 8 gathers x 32 B, 32 B written."""
+    cells = n_grid ** 3
+    return n_particles * (32 + 64 + 32 + 256 + 32) + cells * (8 + 24 + 9 * 32 + 48)
+
+
+def leg_pm(og, torch, synth, args):
+    """Full TreePM force: tree short-range (mixed walk) + particle-mesh
+    long-range on a mesh of 2 N^(1/3) points per axis (r_s = 1.25 mesh
+    cells), for the headline box and the 256^3 Zel'dovich box."""
+    out = {}
+    for name, make, n_grid, reps in (("mixture2m", lambda: synth.mixture2m(theta=args.theta), 256, 5),
+                                     ("zeldovich256", synth.zeldovich256, 512, 3)):
+        w = make()
+        n = w.pos.shape[0]
+        prm = w.params.as_dict()
+        tp = torch.as_tensor(w.pos, device="cuda")
+        tm = torch.as_tensor(w.mass, device="cuda")
+        stream = torch.cuda.current_stream()
+        mesh = og.PM(n_grid, 1.0, prm["G"], prm["r_s"], stream=stream)
+        wsb = torch.empty(og.og_tree_workspace_bound(n, og.make_params(prm)), dtype=torch.uint8, device="cuda")
+        acc = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        pot = torch.empty(n, dtype=torch.float64, device="cuda")
+        mesh.force(tp, tm, acc, pot)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            mesh.force(tp, tm, acc, pot)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        pm_ms = ev[0].elapsed_time(ev[1]) / reps
+        # one full TreePM step: build + short-range walk + mesh (accumulated)
+        steps = []
+        for _ in range(reps + 1):
+            e3 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e3[0].record(stream)
+            t = og.Tree(tp, tm, 1.0, prm, stream=stream, workspace=wsb)
+            t.force(acc=acc, pot=pot)
+            mesh.force(tp, tm, acc, pot, accumulate=True)
+            e3[1].record(stream)
+            torch.cuda.synchronize()
+            t.close()
+            steps.append(e3[0].elapsed_time(e3[1]))
+        step_ms = float(np.mean(steps[1:]))
+        row = {"N": n, "n_grid": n_grid, "pm_ms": pm_ms, "treepm_ms_per_step": step_ms,
+               "value": n / (step_ms * 1e-3), "unit": "particles/s",
+               "pm_roofline": {"bound": "hbm", "achieved": pm_bytes(n, n_grid) / (pm_ms * 1e-3) / 1e9,
+                               "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                               "frac": pm_bytes(n, n_grid) / (pm_ms * 1e-3) / PEAK_HBM,
+                               "algorithmic_bytes": pm_bytes(n, n_grid)}}
+        if not args.no_oracle and name == "mixture2m":
+            from oracle import pm as opm
+            rng = np.random.default_rng(13)
+            tg = np.sort(rng.choice(n, 4096, replace=False))
+            mesh.force(tp, tm, acc, pot)
+            torch.cuda.synchronize()
+            a_o, p_o = opm.long_range(w.pos, w.mass, 1.0, n_grid, prm["G"], prm["r_s"], targets=tg)
+            a_g = acc.cpu().numpy()[tg]
+            row["pm_error_vs_oracle"] = {
+                "targets": int(tg.size),
+                "max_abs_over_max": float(np.abs(a_g - a_o).max() / np.abs(a_o).max()),
+                "pot_max_abs_over_max": float(np.abs(pot.cpu().numpy()[tg] - p_o).max() / np.abs(p_o).max())}
+        log("  treepm %s: mesh %.3f ms, TreePM step %.3f ms" % (name, pm_ms, step_ms))
+        mesh.close()
+        del tp, tm, wsb, acc, pot
+        torch.cuda.empty_cache()
+        out[name] = row
+    out["workload"] = ("mixture2m (mesh 256^3) and zeldovich256 (mesh 512^3), r_s = 1.25 cells; step = "
+                       "og_tree_build + og_tree_force (mixed) + og_pm_force accumulated")
+    return out
 
 
 def _cpu_model():

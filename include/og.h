@@ -279,6 +279,39 @@ int og_server_release(og_server *s, uint64_t ticket);
 int og_server_stats(const og_server *s, size_t *reserved, int32_t *in_flight, int32_t *pending);
 int og_server_destroy(og_server *s);
 
+/* ------------------------------------------------------- particle mesh --
+ * Long-range part of the TreePM force (paper, "Particle Mesh"): the split
+ * 1/r = erfc(r/2A)/r + erf(r/2A)/r gives the tree the erfc term and the
+ * mesh the erf term.  On an n^3 periodic mesh of a box of side L:
+ *   1. cloud-in-cell assignment of the masses to the nodes j L/n;
+ *   2. FFT of the density rho;
+ *   3. phi_k = -4 pi G exp(-k^2 r_s^2) / k^2 / W(k)^2 rho_k, with W the CIC
+ *      window prod_a sinc^2(pi m_a/n) (assignment and interpolation
+ *      deconvolved) and phi_0 = 0 (periodic, mean density removed);
+ *      a_k = -i k phi_k, the Nyquist wavenumber's derivative set to 0;
+ *   4. inverse FFTs and CIC interpolation at the particles; the potential
+ *      drops the particle's own long-range term, -G m/(sqrt(pi) r_s).
+ * The mesh sum is deterministic (fixed-point deposit).  Positions outside
+ * [0, L) are wrapped. */
+typedef struct og_pm og_pm;
+
+/* Device bytes an n_grid^3 mesh holds (32 n^3 + 256); 0 if n_grid invalid. */
+size_t og_pm_workspace_bound(int32_t n_grid);
+/* n_grid: power of two in 8..1024; box > 0; r_s > 0 (the split scale of
+ * the tree); stream: hipStream_t or NULL.  Allocates the mesh.  Errors:
+ * OG_EINVAL, OG_ENOMEM. */
+int og_pm_create(int32_t n_grid, double box, double G, double r_s, void *stream, og_pm **out);
+/* Long-range acceleration and potential of N particles.
+ *   pos: device [N][3] FP64, mass: device [N] FP64 (caller order)
+ *   acc: device [N][3] FP64, pot: device [N] FP64 or NULL (caller order)
+ *   accumulate: 0 overwrite, 1 add (e.g. onto og_tree_force's short-range
+ *   result, giving the full TreePM force).
+ * Enqueued on the mesh's stream.  Errors: OG_EINVAL, OG_EDEVICE. */
+int og_pm_force(og_pm *pm, const double *pos, const double *mass, int64_t N, double *acc, double *pot,
+                int32_t accumulate);
+/* Waits for the mesh's stream and frees it. */
+int og_pm_free(og_pm *pm);
+
 const char *og_strerror(int code);
 const char *og_last_error(void);
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libog.so")
-SOURCES = ["k_build.hip", "k_walk.hip", "og_api.cpp", "og_server.cpp"]
+SOURCES = ["k_build.hip", "k_walk.hip", "k_pm.hip", "og_api.cpp", "og_server.cpp", "og_pm.cpp"]
 ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,0 +1,307 @@
+// Particle-mesh long-range force for CDNA4 (gfx950).
+//
+// Paper, "Particle Mesh": the particles' mass is assigned to a periodic
+// mesh, the density is Fourier transformed, multiplied by the Green's
+// function of the Poisson equation with the Gaussian filter
+// exp(-k^2 A_smth^2), and transformed back; the tree carries the erfc part
+// of the split, the mesh the erf part.
+//
+// Layout: an n^3 mesh of complex FP64 values (double2), index (x*n + y)*n + z.
+//   1. deposit: cloud-in-cell weights onto the nodes j*L/n, summed with
+//      64-bit fixed-point atomics (a power-of-two scale fitted to N * max m),
+//      so the mesh does not depend on the order of the atomic additions;
+//   2. forward 3-D FFT of the density (three passes of length-n transforms
+//      along z, y and x; each workgroup transforms a tile of neighbouring
+//      lines in LDS, so every pass reads and writes whole cache lines);
+//   3. per wave vector: phi_k = -4 pi G exp(-k^2 r_s^2) / k^2 / W(k)^2 rho_k,
+//      W the CIC window, and a_k = -i k phi_k; the two inverse transforms
+//      carry (a_x + i a_y) and (a_z + i phi), each a pair of real fields;
+//   4. inverse FFTs, then CIC interpolation at the particles.
+#include <cmath>
+
+#include "og_pm.h"
+
+namespace og {
+
+namespace {
+
+constexpr int kPmThreads = 256;
+constexpr int kFftThreads = 256;
+
+__device__ inline void cic(double x, int n, double inv_d, int &i0, double &f) {
+  const double u = x * inv_d;
+  const double fl = floor(u);
+  f = u - fl;
+  long long i = (long long)fl % n;
+  if (i < 0) i += n;
+  i0 = (int)i;
+}
+
+__global__ __launch_bounds__(kPmThreads) void k_fill_u64(unsigned long long *p, uint64_t count) {
+  for (uint64_t i = blockIdx.x * (uint64_t)kPmThreads + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * kPmThreads)
+    p[i] = 0ull;
+}
+
+// Largest mass (positive doubles order like their bit patterns).
+__global__ __launch_bounds__(kPmThreads) void k_mass_max(const double *mass, uint32_t N,
+                                                         unsigned long long *mmax) {
+  __shared__ unsigned long long red[kPmThreads / 64];
+  unsigned long long v = 0ull;
+  for (uint32_t i = blockIdx.x * kPmThreads + threadIdx.x; i < N; i += gridDim.x * kPmThreads) {
+    const double m = mass[i];
+    const unsigned long long b = m > 0.0 ? (unsigned long long)__double_as_longlong(m) : 0ull;
+    v = b > v ? b : v;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kPmThreads / 64; ++w) v = red[w] > v ? red[w] : v;
+    atomicMax(mmax, v);
+  }
+}
+
+// Fixed-point scale: 2^(62 - e) with N * max m < 2^e, so no node overflows.
+__device__ inline double fixed_scale(const unsigned long long *mmax, uint32_t N) {
+  const double m = __longlong_as_double((long long)*mmax);
+  int e = 0;
+  frexp((double)N * m, &e);
+  return ldexp(1.0, 62 - e);
+}
+
+__global__ __launch_bounds__(kPmThreads) void k_deposit(const double *pos, const double *mass, uint32_t N,
+                                                        int n, double inv_d, const unsigned long long *mmax,
+                                                        unsigned long long *acc_mesh) {
+  const uint32_t i = blockIdx.x * kPmThreads + threadIdx.x;
+  if (i >= N) return;
+  const double scale = fixed_scale(mmax, N);
+  int ix, iy, iz;
+  double fx, fy, fz;
+  cic(pos[3ull * i], n, inv_d, ix, fx);
+  cic(pos[3ull * i + 1], n, inv_d, iy, fy);
+  cic(pos[3ull * i + 2], n, inv_d, iz, fz);
+  const double m = mass[i] * scale;
+  const int jx[2] = {ix, ix + 1 == n ? 0 : ix + 1};
+  const int jy[2] = {iy, iy + 1 == n ? 0 : iy + 1};
+  const int jz[2] = {iz, iz + 1 == n ? 0 : iz + 1};
+  const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const unsigned long long q = (unsigned long long)llrint(m * wx[a] * wy[b] * wz[c]);
+        atomicAdd(acc_mesh + ((uint64_t)jx[a] * n + jy[b]) * n + jz[c], q);
+      }
+}
+
+// Fixed point -> density (mass / cell volume), as the real part.
+__global__ __launch_bounds__(kPmThreads) void k_density(const unsigned long long *acc_mesh, uint64_t cells,
+                                                        uint32_t N, const unsigned long long *mmax,
+                                                        double inv_vol, double2 *rho) {
+  const double f = inv_vol / fixed_scale(mmax, N);
+  for (uint64_t i = blockIdx.x * (uint64_t)kPmThreads + threadIdx.x; i < cells;
+       i += (uint64_t)gridDim.x * kPmThreads)
+    rho[i] = make_double2((double)acc_mesh[i] * f, 0.0);
+}
+
+// Length-n transforms along one axis, radix 2, decimation in time (input in
+// bit-reversed order).  kSign = -1: forward e^{-2 pi i jk/n}; +1: inverse
+// without the 1/n.  Lines: axis 2 (z, contiguous) takes `tl` consecutive
+// lines; axes 1 and 0 take `tl` lines with consecutive z, so element j of
+// the tile is `tl` contiguous values.
+template <int kSign>
+__global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *data, int n, int logn, int axis, int tl) {
+  extern __shared__ double2 sm[];
+  double2 *buf = sm;
+  double2 *tw = sm + (size_t)tl * n;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < n / 2; k += kFftThreads) {
+    double s, c;
+    sincospi(2.0 * k / n, &s, &c);
+    tw[k] = make_double2(c, kSign * s);
+  }
+  const uint32_t g = blockIdx.x;
+  const uint32_t per = (uint32_t)(n / tl);
+  const uint32_t a = g / per, z0 = (g % per) * tl;
+  const uint64_t nn = (uint64_t)n;
+  auto addr = [&](int t, int j) -> uint64_t {
+    if (axis == 2) return ((uint64_t)g * tl + t) * nn + j;
+    if (axis == 1) return ((uint64_t)a * nn + j) * nn + z0 + t;
+    return ((uint64_t)j * nn + a) * nn + z0 + t;
+  };
+  const int total = tl * n;
+  for (int idx = tid; idx < total; idx += kFftThreads) {
+    int t, j;
+    if (axis == 2) {
+      t = idx >> logn;
+      j = idx & (n - 1);
+    } else {
+      t = idx % tl;
+      j = idx / tl;
+    }
+    const int jr = (int)(__brev((uint32_t)j) >> (32 - logn));
+    buf[t * n + jr] = data[addr(t, j)];
+  }
+  __syncthreads();
+  for (int s = 1; s <= logn; ++s) {
+    const int half = 1 << (s - 1), len = half << 1, step = n >> s;
+    for (int b = tid; b < total / 2; b += kFftThreads) {
+      const int t = b >> (logn - 1), r = b & (n / 2 - 1);
+      const int pos = r & (half - 1), grp = r >> (s - 1);
+      const int i0 = t * n + grp * len + pos, i1 = i0 + half;
+      const double2 w = tw[pos * step];
+      const double2 u = buf[i0], v0 = buf[i1];
+      const double2 v = make_double2(v0.x * w.x - v0.y * w.y, v0.x * w.y + v0.y * w.x);
+      buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+      buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < total; idx += kFftThreads) {
+    int t, j;
+    if (axis == 2) {
+      t = idx >> logn;
+      j = idx & (n - 1);
+    } else {
+      t = idx % tl;
+      j = idx / tl;
+    }
+    data[addr(t, j)] = buf[t * n + j];
+  }
+}
+
+__device__ inline double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+// Green's function, CIC deconvolution and gradient, per wave vector:
+// B holds rho_k on entry and (a_z + i phi)_k on exit, A gets (a_x + i a_y)_k.
+__global__ __launch_bounds__(kPmThreads) void k_green(double2 *B, double2 *A, int n, double L, double G,
+                                                      double r_s) {
+  const uint64_t cells = (uint64_t)n * n * n;
+  for (uint64_t i = blockIdx.x * (uint64_t)kPmThreads + threadIdx.x; i < cells;
+       i += (uint64_t)gridDim.x * kPmThreads) {
+    const int iz = (int)(i % n), iy = (int)((i / n) % n), ix = (int)(i / ((uint64_t)n * n));
+    const int mx = ix < n / 2 ? ix : ix - n, my = iy < n / 2 ? iy : iy - n, mz = iz < n / 2 ? iz : iz - n;
+    const double kf = 2.0 * M_PI / L;
+    const double kx = kf * mx, ky = kf * my, kz = kf * mz;
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    if (k2 == 0.0) {
+      A[i] = make_double2(0.0, 0.0);
+      B[i] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double w = sinc(M_PI * mx / n) * sinc(M_PI * my / n) * sinc(M_PI * mz / n);
+    const double w2 = w * w;
+    const double g = -4.0 * M_PI * G * exp(-k2 * r_s * r_s) / k2 / (w2 * w2);
+    const double2 rho = B[i];
+    const double pr = g * rho.x, pi = g * rho.y;  // phi_k
+    // derivative wavenumbers, the Nyquist one dropped
+    const double dx = mx == -n / 2 ? 0.0 : kx, dy = my == -n / 2 ? 0.0 : ky, dz = mz == -n / 2 ? 0.0 : kz;
+    // a_k = -i k phi_k = k (phi_i, -phi_r)
+    const double axr = dx * pi, axi = -dx * pr;
+    const double ayr = dy * pi, ayi = -dy * pr;
+    const double azr = dz * pi, azi = -dz * pr;
+    A[i] = make_double2(axr - ayi, axi + ayr);
+    B[i] = make_double2(azr - pi, azi + pr);
+  }
+}
+
+__global__ __launch_bounds__(kPmThreads) void k_interp(const double2 *A, const double2 *B, const double *pos,
+                                                       const double *mass, uint32_t N, int n, double inv_d,
+                                                       double norm, double self, double *acc, double *pot,
+                                                       int accumulate) {
+  const uint32_t i = blockIdx.x * kPmThreads + threadIdx.x;
+  if (i >= N) return;
+  int ix, iy, iz;
+  double fx, fy, fz;
+  cic(pos[3ull * i], n, inv_d, ix, fx);
+  cic(pos[3ull * i + 1], n, inv_d, iy, fy);
+  cic(pos[3ull * i + 2], n, inv_d, iz, fz);
+  const int jx[2] = {ix, ix + 1 == n ? 0 : ix + 1};
+  const int jy[2] = {iy, iy + 1 == n ? 0 : iy + 1};
+  const int jz[2] = {iz, iz + 1 == n ? 0 : iz + 1};
+  const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+  double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const uint64_t k = ((uint64_t)jx[a] * n + jy[b]) * n + jz[c];
+        const double w = wx[a] * wy[b] * wz[c];
+        const double2 u = A[k], v = B[k];
+        ax += w * u.x;
+        ay += w * u.y;
+        az += w * v.x;
+        ph += w * v.y;
+      }
+  ax *= norm;
+  ay *= norm;
+  az *= norm;
+  ph = ph * norm + self * mass[i];
+  if (accumulate) {
+    acc[3ull * i] += ax;
+    acc[3ull * i + 1] += ay;
+    acc[3ull * i + 2] += az;
+    if (pot) pot[i] += ph;
+  } else {
+    acc[3ull * i] = ax;
+    acc[3ull * i + 1] = ay;
+    acc[3ull * i + 2] = az;
+    if (pot) pot[i] = ph;
+  }
+}
+
+inline uint32_t blocks_for(uint64_t work, uint32_t threads, uint32_t cap) {
+  const uint64_t b = (work + threads - 1) / threads;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b, cap));
+}
+
+}  // namespace
+
+// Lines per workgroup: up to 16, at most n, and a tile plus twiddles within 64 KB of LDS.
+int fft_lines_per_block(int n) {
+  int tl = 16;
+  while (tl > 1 && (tl > n || (size_t)tl * n * sizeof(double2) + (size_t)(n / 2) * sizeof(double2) > 65536)) tl >>= 1;
+  return tl;
+}
+
+void launch_fft3(double2 *data, int n, int sign, hipStream_t s) {
+  int logn = 0;
+  while ((1 << logn) < n) ++logn;
+  const int tl = fft_lines_per_block(n);
+  const uint32_t blocks = (uint32_t)((uint64_t)n * n / tl);
+  const size_t lds = ((size_t)tl * n + n / 2) * sizeof(double2);
+  for (int axis = 2; axis >= 0; --axis) {
+    if (sign < 0) k_fft_axis<-1><<<blocks, kFftThreads, lds, s>>>(data, n, logn, axis, tl);
+    else k_fft_axis<1><<<blocks, kFftThreads, lds, s>>>(data, n, logn, axis, tl);
+  }
+}
+
+void launch_pm(const PmArgs &P, hipStream_t s) {
+  const uint64_t cells = (uint64_t)P.n * P.n * P.n;
+  const double d = P.L / P.n, inv_d = P.n / P.L;
+  unsigned long long *fixed = reinterpret_cast<unsigned long long *>(P.A);  // aliases A until k_green
+  k_fill_u64<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells);
+  k_fill_u64<<<1, kPmThreads, 0, s>>>(P.mmax, 1);
+  k_mass_max<<<blocks_for(P.N, kPmThreads, 1024), kPmThreads, 0, s>>>(P.mass, P.N, P.mmax);
+  k_deposit<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(P.pos, P.mass, P.N, P.n, inv_d, P.mmax,
+                                                                         fixed);
+  k_density<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells, P.N, P.mmax,
+                                                                       1.0 / (d * d * d), P.B);
+  launch_fft3(P.B, P.n, -1, s);
+  k_green<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(P.B, P.A, P.n, P.L, P.G, P.r_s);
+  launch_fft3(P.A, P.n, +1, s);
+  launch_fft3(P.B, P.n, +1, s);
+  const double self = P.G / (std::sqrt(M_PI) * P.r_s);
+  k_interp<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(
+      P.A, P.B, P.pos, P.mass, P.N, P.n, inv_d, 1.0 / (double)cells, self, P.acc, P.pot, P.accumulate);
+}
+
+}  // namespace og

@@ -86,6 +86,11 @@ _SIGNATURES = {
     "og_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]),
     "og_server_destroy": (ctypes.c_int, [_P]),
+    "og_pm_workspace_bound": (ctypes.c_size_t, [ctypes.c_int32]),
+    "og_pm_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
+                                    ctypes.POINTER(_P)]),
+    "og_pm_force": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P, ctypes.c_int32]),
+    "og_pm_free": (ctypes.c_int, [_P]),
     "og_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "og_last_error": (ctypes.c_char_p, []),
 }
@@ -476,4 +481,42 @@ class Server:
         try:
             self.close()
         except Exception:  # noqa: BLE001
+            pass
+
+
+# --------------------------------------------------------- particle mesh --
+def og_pm_workspace_bound(n_grid: int) -> int:
+    return int(load().og_pm_workspace_bound(int(n_grid)))
+
+
+class PM:
+    """Long-range (mesh) part of the TreePM force on an n_grid^3 periodic mesh."""
+
+    def __init__(self, n_grid: int, box: float, G: float, r_s: float, stream=None):
+        h = ctypes.c_void_p()
+        _check(load().og_pm_create(int(n_grid), float(box), float(G), float(r_s), _stream_handle(stream),
+                                   ctypes.byref(h)))
+        self.handle = h
+        self.n_grid = int(n_grid)
+
+    def force(self, pos, mass, acc=None, pot=None, accumulate=False, with_pot=True):
+        import torch
+        N = int(pos.shape[0])
+        if acc is None:
+            acc = torch.empty((N, 3), dtype=torch.float64, device=pos.device)
+        if with_pot and pot is None:
+            pot = torch.empty(N, dtype=torch.float64, device=pos.device)
+        _check(load().og_pm_force(self.handle, _ptr(pos), _ptr(mass), N, _ptr(acc), _ptr(pot) if with_pot else None,
+                                  1 if accumulate else 0))
+        return acc, pot
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().og_pm_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
             pass
