@@ -52,6 +52,9 @@ def _load():
         lib.ogo_walk.argtypes = [P, P, I64, P, P, P, P, P, P, P, P, I,
                                  D, D, D, D, D, I, D, I, I, D, P, P, I64, P, P, P]
         lib.ogo_walk.restype = None
+        lib.ogo_walk_groups.argtypes = [P, P, I64, P, P, P, P, P, P, P, P, I,
+                                        D, D, D, D, D, I, D, I, I, D, P, P, P, I64, P, P, P]
+        lib.ogo_walk_groups.restype = None
         lib.ogo_direct.argtypes = [P, P, I64, D, I, D, D, D, D, I, P, I64, P, P, P]
         lib.ogo_direct.restype = None
         _lib = lib
@@ -213,6 +216,61 @@ def walk(tree: Tree, targets=None, params: Params = None, a_old=None):
                  int(p.softening), int(p.criterion), float(p.alpha), _p(aold), _p(tpos), M,
                  _p(acc), _p(pot), _p(nint))
     return acc, pot, nint
+
+
+def curve_groups(tree: Tree, group_size: int, targets=None):
+    """Partition of the targets (caller-order indices, None = all) into
+    groups of `group_size` consecutive targets in the tree's curve order
+    (ties between repeated targets kept in list order).  Returns (order,
+    goff): order[k] is the position in the target list of the k-th target
+    in curve order; group g is order[goff[g]:goff[g+1]]."""
+    n = tree.spos.shape[0]
+    inv = np.empty(n, dtype=np.int64)
+    inv[tree.perm] = np.arange(n)
+    tl = np.arange(n) if targets is None else np.asarray(targets, dtype=np.int64)
+    order = np.argsort(inv[tl], kind="stable")
+    M = len(tl)
+    goff = np.append(np.arange(0, M, group_size), M).astype(np.int64)
+    return order, goff
+
+
+def walk_groups(tree: Tree, group_size: int, targets=None, params: Params = None, a_old=None):
+    """Group-shared walk (R31) over the curve-order partition of
+    `curve_groups`.  Returns (acc, pot, n_interactions) in target order."""
+    lib = _load()
+    p = params or tree.params
+    if p.softening == 1 and not p.eps > 0:
+        raise OracleError("spline softening needs eps > 0")
+    n = tree.spos.shape[0]
+    inv = np.empty(n, dtype=np.uint32)
+    inv[tree.perm] = np.arange(n, dtype=np.uint32)
+    tl = np.arange(n, dtype=np.int64) if targets is None else np.asarray(targets, dtype=np.int64)
+    order, goff = curve_groups(tree, group_size, tl)
+    tsorted = tl[order]
+    tpos = np.ascontiguousarray(inv[tsorted])
+    M = len(tl)
+    if p.criterion == 1:
+        if a_old is None:
+            raise OracleError("the relative criterion needs a_old")
+        aold = np.ascontiguousarray(np.asarray(a_old, dtype=np.float64).reshape(n, 3)[tsorted])
+    else:
+        aold = np.zeros((1, 3))
+    acc = np.empty((M, 3))
+    pot = np.empty(M)
+    nint = np.empty(M, dtype=np.int64)
+    lib.ogo_walk_groups(_p(tree.spos), _p(tree.smass), tree.n_nodes, _p(tree.first), _p(tree.count),
+                        _p(tree.level), _p(tree.skip), _p(tree.centre), _p(tree.side), _p(tree.mass),
+                        _p(tree.com), int(tree.params.leaf_max), float(p.G), float(p.eps), float(p.r_s),
+                        float(p.rcut), float(p.theta), int(p.periodic), float(tree.box),
+                        int(p.softening), int(p.criterion), float(p.alpha), _p(aold), _p(tpos),
+                        _p(goff), len(goff) - 1, _p(acc), _p(pot), _p(nint))
+    out_a = np.empty_like(acc)
+    out_p = np.empty_like(pot)
+    out_n = np.empty_like(nint)
+    out_a[order] = acc
+    out_p[order] = pot
+    out_n[order] = nint
+    return out_a, out_p, out_n
 
 
 def tree_force(pos, mass, box, params: Params, targets=None, a_old=None):

@@ -27,6 +27,12 @@
  *       factors of R2 multiply that softened force and potential.
  *   R25 relative opening criterion (switch): open iff
  *       G M side^2 > alpha |a_old| r^4 (r = |COM - x|), or by R6.
+ *   R31 group-shared interaction lists (separate entry): for a group of
+ *       targets the walk opens a node when any target for which the node is
+ *       not pruned (R4) would open it (R5/R6 or R25); a node pruned for
+ *       every target is skipped; otherwise every target of the group adds
+ *       the node's monopole, or each particle of an opened leaf, subject to
+ *       its own cutoff and self test.
  *   R26 Peano-Hilbert keys (switch): the cell's three 21-bit coordinates
  *       are turned into the transposed Hilbert index of Skilling (2004,
  *       "Programming the Hilbert curve") and interleaved as in R11.  The
@@ -449,4 +455,95 @@ void ogo_walk(const double *spos, const double *smass, int64_t n_nodes,
         if (nint) nint[t] = c;
     }
     free(is_leaf);
+}
+
+/* ------------------------------------------------- group-shared walk --
+ * R31 (paper, "Neighbour search": nearby particles are grouped and served
+ * by one search; "Tree walk" for the per-node rules).  Groups are given as
+ * ranges goff[g]..goff[g+1] of the target list tpos (sorted positions);
+ * every target of a group sees the same node sequence and adds the same
+ * partners in the same order, each with its own cutoff and self test.     */
+void ogo_walk_groups(const double *spos, const double *smass, int64_t n_nodes,
+                     const uint32_t *first, const uint32_t *count, const uint8_t *level,
+                     const uint32_t *skip, const double *centre3, const double *side,
+                     const double *nmass, const double *com3, int leaf_max,
+                     double G, double eps, double r_s, double r_cut, double theta,
+                     int periodic, double box, int softening, int criterion, double alpha,
+                     const double *aold3, const uint32_t *tpos, const int64_t *goff,
+                     int64_t n_groups, double *acc3, double *pot, int64_t *nint)
+{
+    ogo_walk_params p;
+    p.G = G;
+    p.eps2 = eps * eps;
+    p.r_s = r_s;
+    p.cutoff = r_s > 0.0;
+    p.rcut = r_cut;
+    p.rc2 = r_cut * r_cut;
+    p.theta2 = theta * theta;
+    p.periodic = periodic;
+    p.box = box;
+    p.spline = softening == 1;
+    p.h = 2.8 * eps;
+    p.relative = criterion == 1;
+    p.alpha = alpha;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < n_groups; ++g) {
+        const int64_t t0 = goff[g], t1 = goff[g + 1];
+        for (int64_t t = t0; t < t1; ++t) {
+            acc3[3 * t] = acc3[3 * t + 1] = acc3[3 * t + 2] = 0.0;
+            pot[t] = 0.0;
+            nint[t] = 0;
+        }
+        int64_t n = 0;
+        while (n < n_nodes) {
+            const double s = side[n];
+            const int leaf = !((int)count[n] > leaf_max && level[n] < OGO_LEVELS);
+            int any_live = 0, any_open = 0;
+            for (int64_t t = t0; t < t1; ++t) {
+                const double *xi = spos + 3 * (int64_t)tpos[t];
+                double dc[3], d[3];
+                for (int k = 0; k < 3; ++k) dc[k] = ogo_minimg(centre3[3 * n + k] - xi[k], &p);
+                if (p.cutoff) {
+                    double reach = p.rcut + 0.5 * s;
+                    if (fabs(dc[0]) > reach || fabs(dc[1]) > reach || fabs(dc[2]) > reach) continue;
+                }
+                any_live = 1;
+                for (int k = 0; k < 3; ++k) d[k] = ogo_minimg(com3[3 * n + k] - xi[k], &p);
+                double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                double near = 0.6 * s, ao = 0.0;
+                if (p.relative) {
+                    const double *v = aold3 + 3 * t;
+                    ao = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                }
+                int far_open = p.relative ? (p.G * nmass[n] * s * s > p.alpha * ao * r2 * r2)
+                                          : (s * s > p.theta2 * r2);
+                if (far_open || (fabs(dc[0]) < near && fabs(dc[1]) < near && fabs(dc[2]) < near))
+                    any_open = 1;
+            }
+            if (!any_live) {
+                n = skip[n];
+            } else if (!any_open) {
+                for (int64_t t = t0; t < t1; ++t) {
+                    const double *xi = spos + 3 * (int64_t)tpos[t];
+                    double d[3];
+                    for (int k = 0; k < 3; ++k) d[k] = ogo_minimg(com3[3 * n + k] - xi[k], &p);
+                    nint[t] += ogo_pair(d, nmass[n], &p, acc3 + 3 * t, pot + t);
+                }
+                n = skip[n];
+            } else if (!leaf) {
+                n = n + 1;
+            } else {
+                for (uint32_t j = first[n]; j < first[n] + count[n]; ++j) {
+                    for (int64_t t = t0; t < t1; ++t) {
+                        if (j == tpos[t]) continue; /* R14 */
+                        const double *xi = spos + 3 * (int64_t)tpos[t];
+                        double dj[3];
+                        for (int k = 0; k < 3; ++k) dj[k] = ogo_minimg(spos[3 * j + k] - xi[k], &p);
+                        nint[t] += ogo_pair(dj, smass[j], &p, acc3 + 3 * t, pot + t);
+                    }
+                }
+                n = skip[n];
+            }
+        }
+    }
 }
