@@ -123,9 +123,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
-    ap.add_argument("--legs", default="batch,serving,zeldovich,variants,hilbert,active,pm",
+    ap.add_argument("--legs", default="batch,serving,zeldovich,variants,hilbert,active,pm,groups",
                     help="extra workloads reported beside the headline: batch, serving, zeldovich, "
-                         "variants, hilbert, active, pm (comma list, or 'none')")
+                         "variants, hilbert, active, pm, groups (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -240,7 +240,8 @@ def main():
     torch.cuda.empty_cache()
     for leg in legs:
         fn = {"batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich,
-              "variants": leg_variants, "hilbert": leg_hilbert, "active": leg_active, "pm": leg_pm}[leg]
+              "variants": leg_variants, "hilbert": leg_hilbert, "active": leg_active, "pm": leg_pm,
+              "groups": leg_groups}[leg]
         log("leg %s" % leg)
         try:
             out[LEG_NAMES[leg]] = fn(og, torch, synth, args)
@@ -308,7 +309,7 @@ def main():
 
 LEG_NAMES = {"batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256",
              "variants": "variants_mixture2m", "hilbert": "hilbert_mixture2m", "active": "active_mixture2m",
-             "pm": "treepm"}
+             "pm": "treepm", "groups": "group_lists_mixture2m"}
 
 
 def _oracle_params(oracle, prm):
@@ -730,6 +731,57 @@ def leg_pm(og, torch, synth, args):
         out[name] = row
     out["workload"] = ("mixture2m (mesh 256^3) and zeldovich256 (mesh 512^3), r_s = 1.25 cells; step = "
                        "og_tree_build + og_tree_force (mixed) + og_pm_force accumulated")
+    return out
+
+
+def leg_groups(og, torch, synth, args):
+    """The headline box with group-shared interaction lists (one walk per
+    group of consecutive targets in curve order), for two group sizes; the
+    error is against the oracle's group walk over the same partition, on
+    64 whole groups."""
+    w = synth.mixture2m(theta=args.theta)
+    n = w.pos.shape[0]
+    base = w.params.as_dict()
+    tp = torch.as_tensor(w.pos, device="cuda")
+    tm = torch.as_tensor(w.mass, device="cuda")
+    out = {}
+    otree = None
+    if not args.no_oracle:
+        import oracle
+        otree = oracle.build_tree(w.pos, w.mass, 1.0, _oracle_params(oracle, base))
+    for gm in (64, 32):
+        prm = dict(base, lists="group", group_max=gm)
+        wsb = torch.empty(og.og_tree_workspace_bound(n, og.make_params(prm)), dtype=torch.uint8, device="cuda")
+        row = {}
+        for prec, steps in (("mixed", 5), ("fp64", 2)):
+            r = time_steps(og, torch, tp, tm, prm, wsb, prec, steps, 1)
+            for t in r["trees"]:
+                t.close()
+            row[prec] = {"value": n / (r["total_ms"] / steps * 1e-3), "ms_per_step": r["total_ms"] / steps,
+                         "build_ms": float(r["build_ms"].mean()), "walk_ms": float(r["walk_ms"].mean())}
+        t = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream(), workspace=wsb)
+        am, _, nm = t.force(precision="mixed", with_counts=True)
+        ad, _, nd = t.force(precision="fp64", with_counts=True)
+        torch.cuda.synchronize()
+        t.close()
+        row["interactions_per_target"] = float(nm.sum().item()) / n
+        if otree is not None:
+            order, goff = oracle.curve_groups(otree, gm)
+            rng = np.random.default_rng(17)
+            gsel = np.sort(rng.choice(len(goff) - 1, 64, replace=False))
+            members = np.concatenate([order[goff[g]:goff[g + 1]] for g in gsel])
+            a_o, _, n_o = oracle.walk_groups(otree, gm, targets=members)
+            e_m = _rel_err(am.cpu().numpy()[members], a_o)
+            row["error_vs_oracle"] = {
+                "targets": int(members.size), "mixed_median": float(np.median(e_m)),
+                "mixed_p99": float(np.percentile(e_m, 99)),
+                "fp64_max": float(_rel_err(ad.cpu().numpy()[members], a_o).max()),
+                "fp64_counts_equal": bool(np.array_equal(nd.cpu().numpy()[members], n_o))}
+        log("  group lists %d: mixed %.3f ms/step, fp64 %.3f, %.0f interactions/target"
+            % (gm, row["mixed"]["ms_per_step"], row["fp64"]["ms_per_step"], row["interactions_per_target"]))
+        out["group_max_%d" % gm] = row
+        del wsb
+    out["workload"] = "mixture2m as the headline, group-shared lists (OG_LISTS_GROUP)"
     return out
 
 

@@ -96,6 +96,17 @@ enum { OG_OPEN_BH = 0, OG_OPEN_RELATIVE = 1 };
  * the same for both; only their order, hence the summation order, differs. */
 enum { OG_CURVE_MORTON = 0, OG_CURVE_HILBERT = 1 };
 
+/* Interaction lists (paper, "Neighbour search": nearby particles are grouped
+ * and served by one search).  TARGET: every target follows its own walk;
+ * the result does not depend on the grouping.  GROUP: one walk per group of
+ * group_max consecutive targets in curve order; a node is pruned when it is
+ * pruned for every target of the group, accepted for all when none of the
+ * targets that keep it would open it, and opened otherwise; every target
+ * then adds the same monopoles and leaf particles in traversal order, each
+ * with its own cutoff and self test.  The result depends on the grouping
+ * (more nodes opened: more interactions, smaller error). */
+enum { OG_LISTS_TARGET = 0, OG_LISTS_GROUP = 1 };
+
 typedef struct og_params {
     uint32_t struct_size;   /* = sizeof(og_params) (ABI check) */
     double G;               /* gravitational constant (default 1) */
@@ -111,7 +122,8 @@ typedef struct og_params {
                                the result depends on it */
     int32_t precision;      /* OG_PREC_FP64 or OG_PREC_MIXED (default MIXED) */
     int32_t group_max;      /* targets per wavefront group, 1..64, 0 = 64;
-                               the result does not depend on it */
+                               the result does not depend on it (except
+                               with OG_LISTS_GROUP) */
     int32_t walk_list_cap;  /* mixed walk: accepted partners buffered per
                                target before evaluation, 4, 8, 16 or 32; 0 =
                                default (4); the result does not depend on it */
@@ -119,14 +131,15 @@ typedef struct og_params {
                                (needs eps > 0) */
     int32_t criterion;      /* OG_OPEN_BH (default) or OG_OPEN_RELATIVE */
     int32_t curve;          /* OG_CURVE_MORTON (default) or OG_CURVE_HILBERT */
+    int32_t lists;          /* OG_LISTS_TARGET (default) or OG_LISTS_GROUP */
     void *stream;           /* hipStream_t, NULL = default stream */
     void *workspace;        /* optional caller device buffer for the tree */
     size_t workspace_bytes; /* its size; must be >= og_tree_workspace_bound */
 } og_params;
 
 /* Defaults: G 1, eps 0, r_s 0, r_cut 0, theta 0.5, alpha 0, periodic 1,
- * leaf_max 8, MIXED, group_max 0, walk_list_cap 0, PLUMMER, BH, MORTON, no
- * stream, no workspace. */
+ * leaf_max 8, MIXED, group_max 0, walk_list_cap 0, PLUMMER, BH, MORTON,
+ * TARGET lists, no stream, no workspace. */
 void og_params_default(og_params *p);
 
 /* Device bytes one tree over N particles needs (upper bound, independent of
@@ -147,7 +160,7 @@ typedef struct og_tree og_tree;
  * bounds.  Errors: OG_EINVAL (N < 1 or > 2^27-1, box <= 0, eps < 0,
  * theta < 0, leaf_max outside 1..4096, group_max outside 0..64,
  * walk_list_cap not 0, 4, 8, 16 or 32, periodic
- * with r_s <= 0 or r_cut >= box/2, unknown softening, criterion or curve, SPLINE
+ * with r_s <= 0 or r_cut >= box/2, unknown softening, criterion, curve or lists, SPLINE
  * with eps = 0, RELATIVE with alpha <= 0, null pointers, host pointers),
  * OG_ENOMEM, OG_EDEVICE. */
 int og_tree_build(const double *pos, const double *mass, int64_t N, double box,
@@ -232,8 +245,8 @@ typedef struct og_box {
     int64_t N;
     double box;
     og_params params;    /* per box; stream/workspace fields ignored;
-                            precision, group_max and walk_list_cap must
-                            equal box 0's; OG_OPEN_RELATIVE is not
+                            precision, group_max, walk_list_cap and lists
+                            must equal box 0's; OG_OPEN_RELATIVE is not
                             available here (OG_EUNSUPPORTED) */
     double *acc;         /* device [N][3] output, caller order */
     double *pot;         /* device [N] output or NULL */

@@ -703,6 +703,301 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
   }
 }
 
+// ------------------------------------------- group-shared interaction lists --
+// One walk per group of targets (the paper's grouped neighbour search
+// applied to the tree walk): at a visited node every lane applies the
+// per-target pruning and opening tests to its own target; the node is
+// skipped when it is pruned for every lane, accepted for the whole group
+// when no lane that keeps it would open it, and opened when one would.
+// Accepted monopoles and the particles of opened leaves go to one list per
+// wave, and every lane evaluates the whole list for its own target (with
+// its own cutoff and self test), in traversal order.  Evaluation is thus
+// uniform across the wave, at the price of more interactions per target;
+// the result depends on the grouping.
+
+// FP64: the same arithmetic as the per-target FP64 walk, evaluated at the node.
+template <bool kExt>
+__global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
+#pragma clang fp contract(off)
+  const uint32_t lane = threadIdx.x & 63;
+  device_counts(A);
+  GroupQueue Q = make_queue(A);
+  while (true) {
+    const uint32_t g = pop_group(Q, lane);
+    if (g >= A.n_groups) break;
+    const GroupRef gr = group_of(A, g);
+    const BoxDev bx = ld(A.boxes + gr.box);
+    uint32_t p = 0, slot = 0;
+    const bool valid = lane_target(A, gr, bx, lane, p, slot);
+    double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (valid) xi = A.part64[p];
+    double aold = 0.0;
+    const bool relative = kExt && bx.relative;
+    if (valid && relative) {
+      const double *v = A.a_old + 3ull * (A.perm[p] - bx.p_off);
+      aold = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    }
+    const bool periodic = bx.periodic;
+    const double box = bx.box, h = bx.L * 0x1p-21;
+    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+    uint32_t ni = 0;
+    uint32_t n = bx.root;
+    const uint32_t nend = bx.node_end;
+    Topo t = ld(A.topo + n);
+    Mom64 mm = ld(A.mom64 + n);
+    while (n < nend) {
+      const bool leaf = (t.corner & kLeafBit) != 0;
+      const uint32_t ns = leaf ? n + 1 : t.a;
+      const uint32_t n1c = min(n + 1, nend - 1), nsc = min(ns, nend - 1);
+      const Topo t1 = ld(A.topo + n1c);
+      const Mom64 m1 = ld(A.mom64 + n1c);
+      const Topo ts = ld(A.topo + nsc);
+      const Mom64 msk = ld(A.mom64 + nsc);
+      const int lev = (int)(t.b >> kCountBits);
+      const double side = ldexp(bx.L, -lev);
+      const double half = ldexp(1.0, 20 - lev);
+      const double c0 = bx.lo[0] + ((double)(uint32_t)(t.corner & 0x1fffffull) + half) * h;
+      const double c1 = bx.lo[1] + ((double)(uint32_t)((t.corner >> 21) & 0x1fffffull) + half) * h;
+      const double c2 = bx.lo[2] + ((double)(uint32_t)((t.corner >> 42) & 0x1fffffull) + half) * h;
+      bool live = false, open = false;
+      double dx = 0.0, dy = 0.0, dz = 0.0;
+      if (valid) {
+        const double dcx = minimg(c0 - xi.x, periodic, box);
+        const double dcy = minimg(c1 - xi.y, periodic, box);
+        const double dcz = minimg(c2 - xi.z, periodic, box);
+        bool pruned = false;
+        if (bx.cutoff) {
+          const double reach = bx.rcut + 0.5 * side;
+          pruned = fabs(dcx) > reach || fabs(dcy) > reach || fabs(dcz) > reach;
+        }
+        dx = minimg(mm.cx - xi.x, periodic, box);
+        dy = minimg(mm.cy - xi.y, periodic, box);
+        dz = minimg(mm.cz - xi.z, periodic, box);
+        if (!pruned) {
+          live = true;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const double near = 0.6 * side;
+          const bool far_open = relative ? (bx.G * mm.m * side * side > bx.alpha * aold * r2 * r2)
+                                         : (side * side > bx.theta2 * r2);
+          open = far_open || (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
+        }
+      }
+      const uint32_t nskip = ns > n ? ns : n + 1;  // a skip always moves forward
+      uint32_t nn;
+      if (!__ballot(live)) {
+        nn = nskip;
+      } else if (!__ballot(open)) {
+        if (valid) pair64<kExt>(dx, dy, dz, mm.m, bx, ax, ay, az, ph, ni);
+        nn = nskip;
+      } else if (leaf) {
+        const uint32_t f = t.a, cnt = t.b & kCountMask;
+        for (uint32_t base = 0; base < cnt; base += 64) {
+          double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
+          if (base + lane < cnt) q = A.part64[f + base + lane];
+          const uint32_t m = min(64u, cnt - base);
+          for (uint32_t j = 0; j < m; ++j) {
+            const double qx = rdl(q.x, j), qy = rdl(q.y, j), qz = rdl(q.z, j), qm = rdl(q.w, j);
+            if (valid && f + base + j != p) {
+              const double ex = minimg(qx - xi.x, periodic, box);
+              const double ey = minimg(qy - xi.y, periodic, box);
+              const double ez = minimg(qz - xi.z, periodic, box);
+              pair64<kExt>(ex, ey, ez, qm, bx, ax, ay, az, ph, ni);
+            }
+          }
+        }
+        nn = n + 1;
+      } else {
+        nn = n + 1;
+      }
+      const bool first_child = nn == n + 1;
+      t = first_child ? t1 : ts;
+      mm = first_child ? m1 : msk;
+      n = nn;
+    }
+    if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
+  }
+}
+
+// Mixed: list entries hold a node centre (exact half-cells) and an FP32
+// offset from it (centre of mass, or particle), so each lane forms its own
+// offset exactly as the per-target mixed walk does.
+struct __attribute__((aligned(16))) GEntry {
+  int c[3];
+  uint32_t tag;  // bit 31: offsets may need the minimum image; bits 0..30: particle, or kGNoSelf
+  float o[3];
+  float m;
+};
+constexpr uint32_t kGWrap = 0x80000000u, kGNoSelf = 0x7fffffffu;
+constexpr uint32_t kGroupCap = 256;
+
+template <int kMode, bool kExt>
+__global__ __launch_bounds__(kWalk32Threads) void k_walkg32(WalkArgs A) {
+#pragma clang fp contract(fast)
+  __shared__ GEntry list[kGroupCap];
+  const uint32_t lane = threadIdx.x;
+  device_counts(A);
+  GroupQueue Q = make_queue(A);
+  while (true) {
+    const uint32_t g = pop_group(Q, lane);
+    if (g >= A.n_groups) break;
+    const GroupRef gr = group_of(A, g);
+    const BoxDev bx = ld(A.boxes + gr.box);
+    const bool kCut = kMode == 0 ? bx.cutoff != 0 : kMode != 3;
+    const bool kPer = kMode == 0 ? bx.periodic != 0 : kMode == 2;
+    Consts32 k;
+    k.G = bx.Gf;
+    k.eps2 = bx.eps2f;
+    k.inv2rs = bx.inv2rsf;
+    k.rc2 = bx.rc2f;
+    k.theta2 = bx.theta2f;
+    k.h22 = bx.h22f;
+    k.box = bx.Lf;
+    k.half_box = 0.5f * bx.Lf;
+    k.cutoff = kCut;
+    k.periodic = kPer;
+    k.spline = kExt && bx.spline;
+    k.hs2 = bx.hsf * bx.hsf;
+    k.hinv = bx.hinvf;
+    const bool relative = kExt && bx.relative;
+    uint32_t p = 0, slot = 0;
+    const bool valid = lane_target(A, gr, bx, lane, p, slot);
+    float aol = 0.0f;
+    if (relative && valid) {
+      const double *v = A.a_old + 3ull * (A.perm[p] - bx.p_off);
+      aol = (float)(bx.alpha * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / bx.G);
+    }
+    int o0 = 0, o1 = 0, o2 = 0;
+    float xr = 0.0f, yr = 0.0f, zr = 0.0f;
+    if (valid) {
+      uint32_t cc[3];
+      key_cell(A.skeys[p], bx.curve, cc);
+      o0 = 2 * (int)cc[0] + 1;
+      o1 = 2 * (int)cc[1] + 1;
+      o2 = 2 * (int)cc[2] + 1;
+      const double h22 = bx.L * 0x1p-22;
+      const double4 q = A.part64[p];
+      xr = (float)(q.x - (bx.lo[0] + (double)o0 * h22));
+      yr = (float)(q.y - (bx.lo[1] + (double)o1 * h22));
+      zr = (float)(q.z - (bx.lo[2] + (double)o2 * h22));
+    }
+    const int g0 = __builtin_amdgcn_readfirstlane(o0), g1 = __builtin_amdgcn_readfirstlane(o1),
+              g2 = __builtin_amdgcn_readfirstlane(o2);
+    int thr = 0;
+    if (kPer) {
+      const int e = valid ? max(abs(o0 - g0), max(abs(o1 - g1), abs(o2 - g2))) : 0;
+      thr = (1 << 21) - wave_max_i32(e);
+    }
+    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+    uint32_t ni = 0, cnt = 0;
+    // every lane evaluates every entry for its own target, in list order
+    auto flush = [&]() {
+      __syncthreads();
+      for (uint32_t e = 0; e < cnt; ++e) {
+        const GEntry q = list[e];
+        int d0 = q.c[0] - o0, d1 = q.c[1] - o1, d2 = q.c[2] - o2;
+        if (kPer && (abs(q.c[0] - g0) > thr || abs(q.c[1] - g1) > thr || abs(q.c[2] - g2) > thr)) {
+          d0 = wrap_cells(d0);
+          d1 = wrap_cells(d1);
+          d2 = wrap_cells(d2);
+        }
+        float dx = ((float)d0 * k.h22 - xr) + q.o[0];
+        float dy = ((float)d1 * k.h22 - yr) + q.o[1];
+        float dz = ((float)d2 * k.h22 - zr) + q.o[2];
+        if (kPer && (q.tag & kGWrap)) {
+          dx = wrap_box(dx, k);
+          dy = wrap_box(dy, k);
+          dz = wrap_box(dz, k);
+        }
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const bool use = valid && (!kCut || r2 < k.rc2) && (q.tag & kGNoSelf) != p;
+        if (use) {
+          eval32<kExt>(dx, dy, dz, q.m, k, ax, ay, az, ph);
+          ++ni;
+        }
+      }
+      __syncthreads();
+      cnt = 0;
+    };
+    uint32_t n = bx.root;
+    const uint32_t nend = bx.node_end;
+    WNode w = ldw(A.wnode + n);
+    while (n < nend) {
+      const bool leaf = (w.cf & kWLeaf) != 0;
+      const uint32_t ns = leaf ? n + 1 : w.a;
+      const WNode wa = ldw(A.wnode + min(n + 1, nend - 1));
+      const WNode wb = ldw(A.wnode + min(ns, nend - 1));
+      const uint32_t lc = w.cf & kWCount;
+      int d0 = w.c[0] - o0, d1 = w.c[1] - o1, d2 = w.c[2] - o2;
+      if (kPer && (abs(w.c[0] - g0) > thr || abs(w.c[1] - g1) > thr || abs(w.c[2] - g2) > thr)) {
+        d0 = wrap_cells(d0);
+        d1 = wrap_cells(d1);
+        d2 = wrap_cells(d2);
+      }
+      const float dcx = (float)d0 * k.h22 - xr, dcy = (float)d1 * k.h22 - yr, dcz = (float)d2 * k.h22 - zr;
+      const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
+      const bool wrapd = kPer && (w.cf & kWWrap) != 0;
+      float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
+      if (wrapd) {
+        dx = wrap_box(dx, k);
+        dy = wrap_box(dy, k);
+        dz = wrap_box(dz, k);
+      }
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const bool live = valid && !(kCut && mdc > w.reach);
+      const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
+      const bool open = live && (far_open || mdc < w.near);
+      const uint32_t nskip = ns > n ? ns : n + 1;  // a skip always moves forward
+      uint32_t nn;
+      if (!__ballot(live)) {
+        nn = nskip;
+      } else if (!__ballot(open)) {
+        if (cnt == kGroupCap) flush();
+        if (lane == 0) {
+          GEntry q;
+          q.c[0] = w.c[0];
+          q.c[1] = w.c[1];
+          q.c[2] = w.c[2];
+          q.tag = kGNoSelf | (wrapd ? kGWrap : 0u);
+          q.o[0] = w.o[0];
+          q.o[1] = w.o[1];
+          q.o[2] = w.o[2];
+          q.m = w.m;
+          list[cnt] = q;
+        }
+        ++cnt;
+        nn = nskip;
+      } else {
+        if (leaf) {
+          for (uint32_t j0 = 0; j0 < lc; j0 += 64) {
+            const uint32_t m = min(64u, lc - j0);
+            if (cnt + m > kGroupCap) flush();
+            if (lane < m) {
+              const uint32_t j = w.a + j0 + lane;
+              const float4 pq = A.part32[j];
+              GEntry q;
+              q.c[0] = w.c[0];
+              q.c[1] = w.c[1];
+              q.c[2] = w.c[2];
+              q.tag = j | (wrapd ? kGWrap : 0u);
+              q.o[0] = pq.x;
+              q.o[1] = pq.y;
+              q.o[2] = pq.z;
+              q.m = pq.w;
+              list[cnt + lane] = q;
+            }
+            cnt += m;
+          }
+        }
+        nn = n + 1;
+      }
+      w = nn == n + 1 ? wa : wb;
+      n = nn;
+    }
+    flush();
+    if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
+  }
+}
+
 }  // namespace
 
 int walk_list_capacity() {
@@ -719,6 +1014,23 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
   const uint32_t cus = (uint32_t)device_cu_count();
   const uint32_t groups = W.n_groups > 0 ? W.n_groups : 1;
   launch_reset_n(W.counter, kQueues, s);
+  if (W.group_lists) {
+    if (precision == 0) {
+      const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(3u * cus, (groups + 3) / 4));
+      if (W.ext) k_walkg64<true><<<blocks, 256, 0, s>>>(W);
+      else k_walkg64<false><<<blocks, 256, 0, s>>>(W);
+    } else {
+      // one wave per workgroup, 8 KB of list each
+      const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(16u * cus, groups));
+      const int mode = W.box_kind;
+      if (W.ext) k_walkg32<0, true><<<blocks, kWalk32Threads, 0, s>>>(W);
+      else if (mode == 2) k_walkg32<2, false><<<blocks, kWalk32Threads, 0, s>>>(W);
+      else if (mode == 1) k_walkg32<1, false><<<blocks, kWalk32Threads, 0, s>>>(W);
+      else if (mode == 3) k_walkg32<3, false><<<blocks, kWalk32Threads, 0, s>>>(W);
+      else k_walkg32<0, false><<<blocks, kWalk32Threads, 0, s>>>(W);
+    }
+    return;
+  }
   if (precision == 0) {
     // 4 waves per workgroup; this kernel's registers allow 3 waves per SIMD
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(3u * cus, (groups + 3) / 4));

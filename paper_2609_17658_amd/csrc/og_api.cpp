@@ -126,6 +126,8 @@ int check_params(const og_params *p, int64_t N, double box, bool need_stream_fie
   if (p->softening != OG_SOFT_PLUMMER && p->softening != OG_SOFT_SPLINE)
     return fail(OG_EINVAL, "unknown softening %d", p->softening);
   if (p->softening == OG_SOFT_SPLINE && !(p->eps > 0.0)) return fail(OG_EINVAL, "spline softening needs eps > 0");
+  if (p->lists != OG_LISTS_TARGET && p->lists != OG_LISTS_GROUP)
+    return fail(OG_EINVAL, "unknown lists mode %d", p->lists);
   if (p->curve != OG_CURVE_MORTON && p->curve != OG_CURVE_HILBERT)
     return fail(OG_EINVAL, "unknown curve %d", p->curve);
   if (p->criterion != OG_OPEN_BH && p->criterion != OG_OPEN_RELATIVE)
@@ -261,6 +263,7 @@ WalkArgs Forest::walk_args() const {
     if (b.spline || b.relative) W.ext = 1;
   }
   W.counter = &A.scalars[8];
+  W.group_lists = group_lists;
   return W;
 }
 
@@ -436,6 +439,7 @@ int og_tree_build(const double *pos, const double *mass, int64_t N, double box, 
   std::vector<BoxDev> boxes(1);
   fill_box(boxes[0], pos, mass, N, box, *params, 0);
   t->F.list_cap = params->walk_list_cap;
+  t->F.group_lists = params->lists == OG_LISTS_GROUP ? 1 : 0;
   rc = t->F.init(boxes, node_bound((uint64_t)N, params->leaf_max), (hipStream_t)params->stream,
                  params->precision, params->group_max, params->workspace, params->workspace_bytes);
   if (rc == OG_OK) rc = t->F.build();
@@ -626,8 +630,8 @@ int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out)
     if (x.params.criterion == OG_OPEN_RELATIVE)
       return fail(OG_EUNSUPPORTED, "box %d: the relative criterion needs a_old, not available in a batch", b);
     if (x.params.precision != boxes[0].params.precision || x.params.group_max != boxes[0].params.group_max ||
-        x.params.walk_list_cap != boxes[0].params.walk_list_cap)
-      return fail(OG_EINVAL, "box %d: precision, group_max and walk_list_cap must match box 0", b);
+        x.params.walk_list_cap != boxes[0].params.walk_list_cap || x.params.lists != boxes[0].params.lists)
+      return fail(OG_EINVAL, "box %d: precision, group_max, walk_list_cap and lists must match box 0", b);
     if (off + (uint64_t)x.N > kCountMask) return fail(OG_EINVAL, "batch exceeds 2^27-1 particles");
     fill_box(hb[b], x.pos, x.mass, x.N, x.box, x.params, (uint32_t)off);
     hb[b].acc = x.acc;
@@ -639,6 +643,7 @@ int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out)
   if (!bt) return fail(OG_ENOMEM, "host allocation");
   bt->boxes.assign(boxes, boxes + B);
   bt->F.list_cap = boxes[0].params.walk_list_cap;
+  bt->F.group_lists = boxes[0].params.lists == OG_LISTS_GROUP ? 1 : 0;
   int rc = bt->F.init(hb, cap, (hipStream_t)stream, boxes[0].params.precision, boxes[0].params.group_max,
                       nullptr, 0);
   if (rc == OG_OK) rc = bt->F.build();

@@ -31,6 +31,7 @@ struct Forest {
   uint32_t group_max = 64;
   uint32_t n_groups = 0;
   int list_cap = 0;  // mixed walk list capacity (0 = default)
+  int group_lists = 0;  // group-shared interaction lists
   void *mem = nullptr;
   size_t bytes = 0;
   bool own = false;

@@ -107,6 +107,7 @@ struct WalkArgs {
   int pot_override;           // 1: use `pot` (possibly null) instead of the box's
   int ext;                    // some box uses spline softening or the relative criterion
   const uint32_t *dev_count;  // non-null: n_targets = [0], n_groups = [1], read on the device
+  int group_lists;            // 1: group-shared interaction lists, 0: per-target walk
   const double *a_old;        // relative criterion: previous accelerations [n][3], caller order
 };
 void launch_walk(const WalkArgs &W, int precision, hipStream_t s);

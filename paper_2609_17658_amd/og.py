@@ -26,6 +26,8 @@ SOFTENINGS = {"plummer": OG_SOFT_PLUMMER, "spline": OG_SOFT_SPLINE, 0: 0, 1: 1}
 CRITERIA = {"bh": OG_OPEN_BH, "relative": OG_OPEN_RELATIVE, 0: 0, 1: 1}
 OG_CURVE_MORTON, OG_CURVE_HILBERT = 0, 1
 CURVES = {"morton": OG_CURVE_MORTON, "hilbert": OG_CURVE_HILBERT, 0: 0, 1: 1}
+OG_LISTS_TARGET, OG_LISTS_GROUP = 0, 1
+LISTS = {"target": OG_LISTS_TARGET, "group": OG_LISTS_GROUP, 0: 0, 1: 1}
 
 
 class og_params(ctypes.Structure):
@@ -34,7 +36,8 @@ class og_params(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("periodic", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("group_max", ctypes.c_int32),
                 ("walk_list_cap", ctypes.c_int32), ("softening", ctypes.c_int32),
-                ("criterion", ctypes.c_int32), ("curve", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("criterion", ctypes.c_int32), ("curve", ctypes.c_int32), ("lists", ctypes.c_int32),
+                ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
@@ -164,6 +167,8 @@ def make_params(params=None, stream=None, workspace=None, **kw) -> og_params:
             v = CRITERIA[v]
         elif k == "curve":
             v = CURVES[v]
+        elif k == "lists":
+            v = LISTS[v]
         setattr(p, k, v)
     p.stream = _stream_handle(stream)
     if workspace is not None:

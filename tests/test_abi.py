@@ -30,11 +30,12 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_default_and_struct_layout():
     p = og.og_params_default()
-    assert p.struct_size == ctypes.sizeof(og.og_params) == 112
+    assert p.struct_size == ctypes.sizeof(og.og_params) == 120
     assert (p.G, p.eps, p.r_s, p.r_cut, p.theta, p.alpha) == (1.0, 0.0, 0.0, 0.0, 0.5, 0.0)
     assert (p.periodic, p.leaf_max, p.precision, p.group_max, p.walk_list_cap) == (1, 8, og.OG_PREC_MIXED, 0, 0)
     assert (p.softening, p.criterion, p.curve) == (og.OG_SOFT_PLUMMER, og.OG_OPEN_BH, og.OG_CURVE_MORTON)
-    assert ctypes.sizeof(og.og_box) == 8 + 8 + 8 + 8 + 112 + 8 + 8
+    assert ctypes.sizeof(og.og_box) == 8 + 8 + 8 + 8 + 120 + 8 + 8
+    assert p.lists == og.OG_LISTS_TARGET
     assert ctypes.sizeof(og.og_force_opts) == 32
 
 
@@ -54,7 +55,7 @@ def test_workspace_bound_monotone_and_rejects_bad_input():
 @pytest.mark.parametrize("field,value", [
     ("eps", -1.0), ("theta", -0.1), ("leaf_max", 0), ("leaf_max", 5000), ("group_max", 65),
     ("precision", 7), ("r_s", 0.0), ("r_cut", 0.6), ("walk_list_cap", 12),
-    ("softening", 2), ("criterion", 3), ("curve", 2),
+    ("softening", 2), ("criterion", 3), ("curve", 2), ("lists", 2),
     ("softening", 1),   # spline with eps = 0
     ("criterion", 1),   # relative criterion with alpha = 0
 ])
