@@ -436,6 +436,7 @@ __device__ inline F4 ldp(const float4 *p) {
 
 // Spline-softened 1/r^3 (g) and 1/r (w) inside the support, u = r/h < 1.
 __device__ inline void spline32(float u, float hinv, float &g, float &w) {
+#pragma clang fp contract(fast)
   const float u2 = u * u, h3 = hinv * hinv * hinv;
   if (u < 0.5f) {
     g = (32.0f / 3.0f + u2 * (-192.0f / 5.0f + 32.0f * u)) * h3;
@@ -448,10 +449,12 @@ __device__ inline void spline32(float u, float hinv, float &g, float &w) {
   }
 }
 
+// One partner at offset (dx, dy, dz) with r2 = |d|^2, mass m: FP32 pair
+// term, accumulated in FP64.
 template <bool kExt>
-__device__ inline void eval32(float dx, float dy, float dz, float m, const Consts32 &k, double &ax,
+__device__ inline void eval32(float dx, float dy, float dz, float r2, float m, const Consts32 &k, double &ax,
                               double &ay, double &az, double &ph) {
-  const float r2 = dx * dx + dy * dy + dz * dz;
+#pragma clang fp contract(fast)
   float g, wv;  // softened 1/r^3 and 1/r
   if (kExt && k.spline) {
     const float ri = __builtin_amdgcn_rsqf(r2);
@@ -525,12 +528,14 @@ template <int kCap, bool kExt>
 __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], uint32_t lane, uint32_t p,
                              uint32_t &cnt, const Consts32 &k, double &ax, double &ay, double &az, double &ph,
                              uint32_t &ni) {
+#pragma clang fp contract(fast)
   uint32_t e = 0, j = 0;
   while (__ballot(e < cnt)) {
     if (e < cnt) {
       const float4 q = list[e][lane];
       const uint32_t tag = __float_as_uint(q.w);
       float dx = q.x, dy = q.y, dz = q.z, m = q.w;
+      float r2 = dx * dx + dy * dy + dz * dz;
       bool use = true, particle = false;  // monopoles were counted when appended
       if (tag & kTagLeaf) {
         particle = true;
@@ -545,7 +550,7 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
           dz = wrap_box(dz, k);
         }
         m = pq.w;
-        const float r2 = dx * dx + dy * dy + dz * dz;
+        r2 = dx * dx + dy * dy + dz * dz;
         use = (first + j != p) && (!k.cutoff || r2 < k.rc2);
         ++j;
         if (j == n) {
@@ -556,7 +561,7 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
         ++e;
       }
       if (use) {
-        eval32<kExt>(dx, dy, dz, m, k, ax, ay, az, ph);
+        eval32<kExt>(dx, dy, dz, r2, m, k, ax, ay, az, ph);
         ni += particle ? 1u : 0u;
       }
     }
@@ -911,7 +916,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walkg32(WalkArgs A) {
         const float r2 = dx * dx + dy * dy + dz * dz;
         const bool use = valid && (!kCut || r2 < k.rc2) && (q.tag & kGNoSelf) != p;
         if (use) {
-          eval32<kExt>(dx, dy, dz, q.m, k, ax, ay, az, ph);
+          eval32<kExt>(dx, dy, dz, r2, q.m, k, ax, ay, az, ph);
           ++ni;
         }
       }
