@@ -322,6 +322,12 @@ int og_pm_create(int32_t n_grid, double box, double G, double r_s, void *stream,
  * Enqueued on the mesh's stream.  Errors: OG_EINVAL, OG_EDEVICE. */
 int og_pm_force(og_pm *pm, const double *pos, const double *mass, int64_t N, double *acc, double *pot,
                 int32_t accumulate);
+/* As og_pm_force for the particles of a built periodic tree whose box side
+ * equals the mesh's: the mesh is read back in the tree's curve order
+ * (neighbouring threads share cells in cache), and acc/pot (device,
+ * [N][3] and [N] or NULL) are written in caller order.  Ordered after the
+ * tree's build on its stream.  Errors: OG_EINVAL, OG_EDEVICE. */
+int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, int32_t accumulate);
 /* Waits for the mesh's stream and frees it. */
 int og_pm_free(og_pm *pm);
 

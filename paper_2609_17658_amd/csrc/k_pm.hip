@@ -43,13 +43,23 @@ __global__ __launch_bounds__(kPmThreads) void k_fill_u64(unsigned long long *p, 
     p[i] = 0ull;
 }
 
+// Particle i: caller arrays, or a tree's particles in curve order.
+struct PartRef {
+  const double *pos, *mass;
+  const double4 *part;
+  const uint32_t *order;  // with part: visit part[order[i]] (null: part[i])
+  __device__ inline double4 get(uint32_t i) const {
+    if (part) return part[order ? order[i] : i];
+    return make_double4(pos[3ull * i], pos[3ull * i + 1], pos[3ull * i + 2], mass[i]);
+  }
+};
+
 // Largest mass (positive doubles order like their bit patterns).
-__global__ __launch_bounds__(kPmThreads) void k_mass_max(const double *mass, uint32_t N,
-                                                         unsigned long long *mmax) {
+__global__ __launch_bounds__(kPmThreads) void k_mass_max(PartRef P, uint32_t N, unsigned long long *mmax) {
   __shared__ unsigned long long red[kPmThreads / 64];
   unsigned long long v = 0ull;
   for (uint32_t i = blockIdx.x * kPmThreads + threadIdx.x; i < N; i += gridDim.x * kPmThreads) {
-    const double m = mass[i];
+    const double m = P.part ? P.part[i].w : P.mass[i];
     const unsigned long long b = m > 0.0 ? (unsigned long long)__double_as_longlong(m) : 0ull;
     v = b > v ? b : v;
   }
@@ -73,18 +83,19 @@ __device__ inline double fixed_scale(const unsigned long long *mmax, uint32_t N)
   return ldexp(1.0, 62 - e);
 }
 
-__global__ __launch_bounds__(kPmThreads) void k_deposit(const double *pos, const double *mass, uint32_t N,
-                                                        int n, double inv_d, const unsigned long long *mmax,
+__global__ __launch_bounds__(kPmThreads) void k_deposit(PartRef P, uint32_t N, int n, double inv_d,
+                                                        const unsigned long long *mmax,
                                                         unsigned long long *acc_mesh) {
   const uint32_t i = blockIdx.x * kPmThreads + threadIdx.x;
   if (i >= N) return;
   const double scale = fixed_scale(mmax, N);
+  const double4 q = P.get(i);
   int ix, iy, iz;
   double fx, fy, fz;
-  cic(pos[3ull * i], n, inv_d, ix, fx);
-  cic(pos[3ull * i + 1], n, inv_d, iy, fy);
-  cic(pos[3ull * i + 2], n, inv_d, iz, fz);
-  const double m = mass[i] * scale;
+  cic(q.x, n, inv_d, ix, fx);
+  cic(q.y, n, inv_d, iy, fy);
+  cic(q.z, n, inv_d, iz, fz);
+  const double m = q.w * scale;
   const int jx[2] = {ix, ix + 1 == n ? 0 : ix + 1};
   const int jy[2] = {iy, iy + 1 == n ? 0 : iy + 1};
   const int jz[2] = {iz, iz + 1 == n ? 0 : iz + 1};
@@ -211,17 +222,19 @@ __global__ __launch_bounds__(kPmThreads) void k_green(double2 *B, double2 *A, in
   }
 }
 
-__global__ __launch_bounds__(kPmThreads) void k_interp(const double2 *A, const double2 *B, const double *pos,
-                                                       const double *mass, uint32_t N, int n, double inv_d,
+__global__ __launch_bounds__(kPmThreads) void k_interp(const double2 *A, const double2 *B, PartRef P,
+                                                       const uint32_t *perm, uint32_t N, int n, double inv_d,
                                                        double norm, double self, double *acc, double *pot,
                                                        int accumulate) {
-  const uint32_t i = blockIdx.x * kPmThreads + threadIdx.x;
-  if (i >= N) return;
+  const uint32_t t = blockIdx.x * kPmThreads + threadIdx.x;
+  if (t >= N) return;
+  const double4 q = P.get(t);
+  const uint32_t i = perm ? perm[t] : t;  // output slot: caller index
   int ix, iy, iz;
   double fx, fy, fz;
-  cic(pos[3ull * i], n, inv_d, ix, fx);
-  cic(pos[3ull * i + 1], n, inv_d, iy, fy);
-  cic(pos[3ull * i + 2], n, inv_d, iz, fz);
+  cic(q.x, n, inv_d, ix, fx);
+  cic(q.y, n, inv_d, iy, fy);
+  cic(q.z, n, inv_d, iz, fz);
   const int jx[2] = {ix, ix + 1 == n ? 0 : ix + 1};
   const int jy[2] = {iy, iy + 1 == n ? 0 : iy + 1};
   const int jz[2] = {iz, iz + 1 == n ? 0 : iz + 1};
@@ -244,7 +257,7 @@ __global__ __launch_bounds__(kPmThreads) void k_interp(const double2 *A, const d
   ax *= norm;
   ay *= norm;
   az *= norm;
-  ph = ph * norm + self * mass[i];
+  ph = ph * norm + self * q.w;
   if (accumulate) {
     acc[3ull * i] += ax;
     acc[3ull * i + 1] += ay;
@@ -290,9 +303,13 @@ void launch_pm(const PmArgs &P, hipStream_t s) {
   unsigned long long *fixed = reinterpret_cast<unsigned long long *>(P.A);  // aliases A until k_green
   k_fill_u64<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells);
   k_fill_u64<<<1, kPmThreads, 0, s>>>(P.mmax, 1);
-  k_mass_max<<<blocks_for(P.N, kPmThreads, 1024), kPmThreads, 0, s>>>(P.mass, P.N, P.mmax);
-  k_deposit<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(P.pos, P.mass, P.N, P.n, inv_d, P.mmax,
-                                                                         fixed);
+  // Deposits in caller order (neighbouring threads rarely share a cell, so
+  // their atomics do not collide); interpolation in curve order (the eight
+  // nodes of neighbouring threads are shared in cache).
+  const PartRef R{P.pos, P.mass, P.part, nullptr};
+  const PartRef Rd{P.pos, P.mass, P.part, P.part ? P.inv : nullptr};
+  k_mass_max<<<blocks_for(P.N, kPmThreads, 1024), kPmThreads, 0, s>>>(R, P.N, P.mmax);
+  k_deposit<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(Rd, P.N, P.n, inv_d, P.mmax, fixed);
   k_density<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells, P.N, P.mmax,
                                                                        1.0 / (d * d * d), P.B);
   launch_fft3(P.B, P.n, -1, s);
@@ -301,7 +318,8 @@ void launch_pm(const PmArgs &P, hipStream_t s) {
   launch_fft3(P.B, P.n, +1, s);
   const double self = P.G / (std::sqrt(M_PI) * P.r_s);
   k_interp<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(
-      P.A, P.B, P.pos, P.mass, P.N, P.n, inv_d, 1.0 / (double)cells, self, P.acc, P.pot, P.accumulate);
+      P.A, P.B, R, P.part ? P.perm : nullptr, P.N, P.n, inv_d, 1.0 / (double)cells, self, P.acc, P.pot,
+      P.accumulate);
 }
 
 }  // namespace og

@@ -394,9 +394,6 @@ void Forest::release() {
 }  // namespace og
 
 // ================================================================= ABI ==
-struct og_tree {
-  Forest F;
-};
 struct og_batch {
   Forest F;
   std::vector<og_box> boxes;

@@ -11,6 +11,10 @@
 #include "og_kernels.h"
 
 namespace og {
+struct Forest;
+}
+
+namespace og {
 
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
@@ -57,3 +61,8 @@ struct Forest {
 void tree_free_nosync(og_tree *t);
 
 }  // namespace og
+
+// A single tree (og_tree_* entry points): one forest of one box.
+struct og_tree {
+  og::Forest F;
+};

@@ -69,7 +69,7 @@ int og_pm_force(og_pm *pm, const double *pos, const double *mass, int64_t N, dou
   if (N < 1 || N > 0x7fffffffll) return fail(OG_EINVAL, "N = %lld outside [1, 2^31-1]", (long long)N);
   if (!is_device_ptr(pos) || !is_device_ptr(mass) || !is_device_ptr(acc) || (pot && !is_device_ptr(pot)))
     return fail(OG_EINVAL, "pos/mass/acc/pot must be device pointers");
-  PmArgs P;
+  PmArgs P{};
   P.pos = pos;
   P.mass = mass;
   P.N = (uint32_t)N;
@@ -83,6 +83,42 @@ int og_pm_force(og_pm *pm, const double *pos, const double *mass, int64_t N, dou
   P.acc = acc;
   P.pot = pot;
   P.accumulate = accumulate ? 1 : 0;
+  launch_pm(P, pm->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "particle-mesh launch");
+  return OG_OK;
+}
+
+int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, int32_t accumulate) {
+  if (!pm || !tree) return fail(OG_EINVAL, "pm or tree is NULL");
+  const Forest &F = tree->F;
+  const BoxDev &b = F.hboxes[0];
+  if (!b.periodic || b.box != pm->L) return fail(OG_EINVAL, "the tree must be periodic with the mesh's box side");
+  if (!is_device_ptr(acc) || (pot && !is_device_ptr(pot))) return fail(OG_EINVAL, "acc/pot must be device pointers");
+  PmArgs P{};
+  P.part = F.A.part64;
+  P.perm = F.A.perm;
+  P.inv = F.A.inv;
+  P.N = F.N;
+  P.n = pm->n;
+  P.L = pm->L;
+  P.G = pm->G;
+  P.r_s = pm->r_s;
+  P.A = pm->A;
+  P.B = pm->B;
+  P.mmax = pm->mmax;
+  P.acc = acc;
+  P.pot = pot;
+  P.accumulate = accumulate ? 1 : 0;
+  // the tree's particles are ready once its stream has passed the build
+  if (pm->stream != F.stream) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    hipEventRecord(ev, F.stream);
+    hipStreamWaitEvent(pm->stream, ev, 0);
+    hipEventDestroy(ev);
+  }
   launch_pm(P, pm->stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "particle-mesh launch");

@@ -93,6 +93,7 @@ _SIGNATURES = {
     "og_pm_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
                                     ctypes.POINTER(_P)]),
     "og_pm_force": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P, ctypes.c_int32]),
+    "og_pm_force_tree": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32]),
     "og_pm_free": (ctypes.c_int, [_P]),
     "og_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "og_last_error": (ctypes.c_char_p, []),
@@ -513,6 +514,19 @@ class PM:
             pot = torch.empty(N, dtype=torch.float64, device=pos.device)
         _check(load().og_pm_force(self.handle, _ptr(pos), _ptr(mass), N, _ptr(acc), _ptr(pot) if with_pot else None,
                                   1 if accumulate else 0))
+        return acc, pot
+
+    def force_tree(self, tree, acc=None, pot=None, accumulate=False, with_pot=True):
+        """Mesh force on a built periodic tree's particles (read in curve
+        order); acc/pot in caller order."""
+        import torch
+        N = tree.N
+        if acc is None:
+            acc = torch.empty((N, 3), dtype=torch.float64, device=tree.device)
+        if with_pot and pot is None:
+            pot = torch.empty(N, dtype=torch.float64, device=tree.device)
+        _check(load().og_pm_force_tree(self.handle, tree.handle, _ptr(acc), _ptr(pot) if with_pot else None,
+                                       1 if accumulate else 0))
         return acc, pot
 
     def close(self):

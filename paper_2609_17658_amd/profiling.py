@@ -3,6 +3,8 @@
   python paper_2609_17658_amd/profiling.py walk --prec mixed --reps 3
       builds the 2M-particle mixture tree once and runs the force walk
       `reps` times (the build kernels run once, the walk kernel `reps` times);
+  python paper_2609_17658_amd/profiling.py pm --n-grid 256 --reps 3
+      the particle-mesh force of the same mixture on a 256^3 mesh;
   python paper_2609_17658_amd/profiling.py copy --mib 1024 --reps 3
       device-to-device copy of a buffer of known size, the reference for
       scaling FETCH_SIZE / WRITE_SIZE readings to bytes.
@@ -32,6 +34,26 @@ def _walk(prec: str, reps: int, workload: str):
     print("walk %s x%d on %s: done" % (prec, reps, workload), flush=True)
 
 
+def _pm(n_grid: int, reps: int, workload: str):
+    import torch
+
+    from paper_2609_17658_amd import og, synth
+
+    w = synth.WORKLOADS[workload]()
+    dev = torch.device("cuda:0")
+    tp = torch.as_tensor(w.pos, device=dev)
+    tm = torch.as_tensor(w.mass, device=dev)
+    prm = w.params.as_dict()
+    mesh = og.PM(n_grid, w.box, prm["G"], prm["r_s"], stream=torch.cuda.current_stream())
+    acc = torch.empty((tp.shape[0], 3), dtype=torch.float64, device=dev)
+    pot = torch.empty(tp.shape[0], dtype=torch.float64, device=dev)
+    for _ in range(reps):
+        mesh.force(tp, tm, acc, pot)
+    torch.cuda.synchronize()
+    mesh.close()
+    print("pm %d^3 x%d on %s: done" % (n_grid, reps, workload), flush=True)
+
+
 def _copy(mib: int, reps: int):
     import torch
 
@@ -51,12 +73,18 @@ def main(argv=None):
     w.add_argument("--prec", default="mixed")
     w.add_argument("--reps", type=int, default=3)
     w.add_argument("--workload", default="mixture2m")
+    m = sub.add_parser("pm")
+    m.add_argument("--n-grid", type=int, default=256)
+    m.add_argument("--reps", type=int, default=3)
+    m.add_argument("--workload", default="mixture2m")
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=1024)
     c.add_argument("--reps", type=int, default=3)
     a = ap.parse_args(argv)
     if a.cmd == "walk":
         _walk(a.prec, a.reps, a.workload)
+    elif a.cmd == "pm":
+        _pm(a.n_grid, a.reps, a.workload)
     else:
         _copy(a.mib, a.reps)
     return 0

@@ -110,3 +110,28 @@ def test_pm_rejects_bad_arguments(og_mod):
     rc = lib.og_pm_force(m.handle, pos.ctypes.data_as(ctypes.c_void_p), None, 10, None, None, 0)
     assert rc == og_mod.OG_EINVAL
     m.close()
+
+
+def test_pm_from_tree_equals_caller_order(og_mod):
+    """The fixed-point deposit does not depend on the order of particles, so
+    the mesh filled in the tree's curve order is the same, and every
+    particle's interpolation is the same arithmetic: bitwise equal."""
+    pos, mass = _particles(30000, 8)
+    prm = synth.scale_free_params(30000).as_dict()
+    stream = torch.cuda.current_stream()
+    tree = og_mod.Tree(_dev(pos), _dev(mass), 1.0, prm, stream=stream)
+    m = og_mod.PM(64, 1.0, prm["G"], prm["r_s"], stream=stream)
+    a1, p1 = m.force(_dev(pos), _dev(mass))
+    a2, p2 = m.force_tree(tree)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+    # non-periodic tree or another box side: rejected
+    t2 = og_mod.Tree(_dev(pos), _dev(mass), 1.0, dict(G=1.0, eps=0.01, r_s=0.0, theta=0.5, periodic=0, leaf_max=8),
+                     stream=stream)
+    with pytest.raises(og_mod.OgError):
+        m.force_tree(t2)
+    m2 = og_mod.PM(64, 2.0, prm["G"], prm["r_s"], stream=stream)
+    with pytest.raises(og_mod.OgError):
+        m2.force_tree(tree)
+    for x in (tree, t2, m, m2):
+        x.close()
