@@ -50,12 +50,12 @@ def _load():
         lib.ogo_moments.argtypes = [P, P, I64, P, P, P, P, P]
         lib.ogo_moments.restype = None
         lib.ogo_walk.argtypes = [P, P, I64, P, P, P, P, P, P, P, P, I,
-                                 D, D, D, D, D, I, D, I, I, D, P, P, I64, P, P, P]
+                                 D, D, D, D, D, I, D, I, I, D, P, P, P, I64, P, P, P]
         lib.ogo_walk.restype = None
         lib.ogo_walk_groups.argtypes = [P, P, I64, P, P, P, P, P, P, P, P, I,
-                                        D, D, D, D, D, I, D, I, I, D, P, P, P, I64, P, P, P]
+                                        D, D, D, D, D, I, D, I, I, D, P, P, P, P, I64, P, P, P]
         lib.ogo_walk_groups.restype = None
-        lib.ogo_direct.argtypes = [P, P, I64, D, I, D, D, D, D, I, P, I64, P, P, P]
+        lib.ogo_direct.argtypes = [P, P, I64, D, I, D, D, D, D, I, P, P, I64, P, P, P]
         lib.ogo_direct.restype = None
         _lib = lib
     return _lib
@@ -109,6 +109,7 @@ class Tree:
     smass: np.ndarray       # float64 [N], sorted
     box: float
     params: Params
+    seps: np.ndarray = None  # float64 [N], sorted per-particle softening (R32), or None
 
     @property
     def n_nodes(self) -> int:
@@ -147,7 +148,9 @@ def keys(pos, box, periodic=1, curve=0):
     return k
 
 
-def build_tree(pos, mass, box, params: Params) -> Tree:
+def build_tree(pos, mass, box, params: Params, eps=None) -> Tree:
+    """Octree of the particles; `eps` optionally gives every particle's own
+    softening length (caller order, R32)."""
     lib = _load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     mass = np.ascontiguousarray(mass, dtype=np.float64)
@@ -179,8 +182,14 @@ def build_tree(pos, mass, box, params: Params) -> Tree:
     nmass = np.empty(nn)
     com = np.empty((nn, 3))
     lib.ogo_moments(_p(spos), _p(smass), nn, _p(first), _p(count), _p(centre), _p(nmass), _p(com))
+    seps = None
+    if eps is not None:
+        eps = np.asarray(eps, dtype=np.float64)
+        if eps.shape != (n,) or not np.all(eps > 0):
+            raise OracleError("eps must hold one positive length per particle")
+        seps = np.ascontiguousarray(eps[perm])
     return Tree(lo, L, k, perm, skeys, first, count, level, skip, parent, centre, side,
-                nmass, com, spos, smass, float(box), params)
+                nmass, com, spos, smass, float(box), params, seps)
 
 
 def walk(tree: Tree, targets=None, params: Params = None, a_old=None):
@@ -190,7 +199,7 @@ def walk(tree: Tree, targets=None, params: Params = None, a_old=None):
     Returns (acc [M,3], pot [M], n_interactions [M]) in target order."""
     lib = _load()
     p = params or tree.params
-    if p.softening == 1 and not p.eps > 0:
+    if p.softening == 1 and not p.eps > 0 and tree.seps is None:
         raise OracleError("spline softening needs eps > 0")
     n = tree.spos.shape[0]
     inv = np.empty(n, dtype=np.uint32)
@@ -213,7 +222,8 @@ def walk(tree: Tree, targets=None, params: Params = None, a_old=None):
                  _p(tree.level), _p(tree.skip), _p(tree.centre), _p(tree.side), _p(tree.mass),
                  _p(tree.com), int(tree.params.leaf_max), float(p.G), float(p.eps), float(p.r_s),
                  float(p.rcut), float(p.theta), int(p.periodic), float(tree.box),
-                 int(p.softening), int(p.criterion), float(p.alpha), _p(aold), _p(tpos), M,
+                 int(p.softening), int(p.criterion), float(p.alpha), _p(aold),
+                 None if tree.seps is None else _p(tree.seps), _p(tpos), M,
                  _p(acc), _p(pot), _p(nint))
     return acc, pot, nint
 
@@ -239,7 +249,7 @@ def walk_groups(tree: Tree, group_size: int, targets=None, params: Params = None
     `curve_groups`.  Returns (acc, pot, n_interactions) in target order."""
     lib = _load()
     p = params or tree.params
-    if p.softening == 1 and not p.eps > 0:
+    if p.softening == 1 and not p.eps > 0 and tree.seps is None:
         raise OracleError("spline softening needs eps > 0")
     n = tree.spos.shape[0]
     inv = np.empty(n, dtype=np.uint32)
@@ -262,7 +272,8 @@ def walk_groups(tree: Tree, group_size: int, targets=None, params: Params = None
                         _p(tree.level), _p(tree.skip), _p(tree.centre), _p(tree.side), _p(tree.mass),
                         _p(tree.com), int(tree.params.leaf_max), float(p.G), float(p.eps), float(p.r_s),
                         float(p.rcut), float(p.theta), int(p.periodic), float(tree.box),
-                        int(p.softening), int(p.criterion), float(p.alpha), _p(aold), _p(tpos),
+                        int(p.softening), int(p.criterion), float(p.alpha), _p(aold),
+                        None if tree.seps is None else _p(tree.seps), _p(tpos),
                         _p(goff), len(goff) - 1, _p(acc), _p(pot), _p(nint))
     out_a = np.empty_like(acc)
     out_p = np.empty_like(pot)
@@ -273,12 +284,12 @@ def walk_groups(tree: Tree, group_size: int, targets=None, params: Params = None
     return out_a, out_p, out_n
 
 
-def tree_force(pos, mass, box, params: Params, targets=None, a_old=None):
+def tree_force(pos, mass, box, params: Params, targets=None, a_old=None, eps=None):
     """Build + walk.  Returns (acc, pot, n_interactions) in target order."""
-    return walk(build_tree(pos, mass, box, params), targets, params, a_old)
+    return walk(build_tree(pos, mass, box, params, eps=eps), targets, params, a_old)
 
 
-def direct(pos, mass, box, params: Params, targets=None):
+def direct(pos, mass, box, params: Params, targets=None, eps=None):
     """Brute-force direct sum (exact short-range force).  Returns
     (acc [M,3], pot [M], n_interactions [M]) in target order."""
     lib = _load()
@@ -292,9 +303,15 @@ def direct(pos, mass, box, params: Params, targets=None):
     acc = np.empty((M, 3))
     pot = np.empty(M)
     nint = np.empty(M, dtype=np.int64)
-    if params.softening == 1 and not params.eps > 0:
+    if params.softening == 1 and not params.eps > 0 and eps is None:
         raise OracleError("spline softening needs eps > 0")
+    peps = None
+    if eps is not None:
+        peps = np.ascontiguousarray(eps, dtype=np.float64)
+        if peps.shape != (n,) or not np.all(peps > 0):
+            raise OracleError("eps must hold one positive length per particle")
     lib.ogo_direct(_p(pos), _p(mass), n, float(box), int(params.periodic), float(params.G),
                    float(params.eps), float(params.r_s), float(params.rcut),
-                   int(params.softening), _p(targets), M, _p(acc), _p(pot), _p(nint))
+                   int(params.softening), None if peps is None else _p(peps), _p(targets), M,
+                   _p(acc), _p(pot), _p(nint))
     return acc, pot, nint

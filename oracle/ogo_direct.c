@@ -19,6 +19,8 @@
  * q(r/h)/r + t(r/h)/h, where q is the spline's enclosed mass fraction and
  * t(u) = 32 int_u^1 s f(s) ds its outer shells' potential (f the profile
  * 1 - 6s^2 + 6s^3 below 1/2 and 2(1-s)^3 above, 32 = 4 pi * 8/pi).
+ * With per-particle softening lengths (peps, caller order) a pair uses the
+ * larger of its two lengths in place of eps.
  */
 #include <math.h>
 #include <stdint.h>
@@ -42,12 +44,11 @@ static void ogo_spline_shells(double u, double *q, double *t)
 
 void ogo_direct(const double *pos, const double *mass, int64_t n, double box,
                 int periodic, double G, double eps, double r_s, double r_cut,
-                int softening, const int64_t *targets, int64_t M, double *acc3,
-                double *pot, int64_t *nint)
+                int softening, const double *peps, const int64_t *targets, int64_t M,
+                double *acc3, double *pot, int64_t *nint)
 {
-    const double hs = 2.8 * eps;
     const int cut = r_s > 0.0;
-    const double half = 0.5 * box, e2 = eps * eps, rc2 = r_cut * r_cut;
+    const double half = 0.5 * box, rc2 = r_cut * r_cut;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < M; ++t) {
         int64_t i = targets[t];
@@ -71,6 +72,9 @@ void ogo_direct(const double *pos, const double *mass, int64_t n, double box,
                 wp = erfc(u);
                 w = wp + 2.0 * u / sqrt(M_PI) * exp(-u * u);
             }
+            double el = eps;
+            if (peps) el = peps[i] > peps[j] ? peps[i] : peps[j];
+            const double hs = 2.8 * el;
             double f3, f1; /* softened 1/r^3 and 1/r */
             if (softening == 1 && rr < hs * hs) {
                 double r = sqrt(rr), qm, tm;
@@ -81,7 +85,7 @@ void ogo_direct(const double *pos, const double *mass, int64_t n, double box,
                 f1 = 1.0 / sqrt(rr);
                 f3 = f1 * f1 * f1;
             } else {
-                double q = 1.0 / sqrt(rr + e2);
+                double q = 1.0 / sqrt(rr + el * el);
                 f3 = q * q * q;
                 f1 = q;
             }

@@ -33,6 +33,12 @@
  *       every target is skipped; otherwise every target of the group adds
  *       the node's monopole, or each particle of an opened leaf, subject to
  *       its own cutoff and self test.
+ *   R32 per-particle softening (optional array): a pair is softened with
+ *       the larger of its two lengths, a node's monopole with the larger of
+ *       the target's and the node's largest; the mixed-softening check
+ *       opens a node that holds different softenings, whose largest exceeds
+ *       the target's, when the target lies within 2.8 times that largest
+ *       length of the node's centre of mass.
  *   R26 Peano-Hilbert keys (switch): the cell's three 21-bit coordinates
  *       are turned into the transposed Hilbert index of Skilling (2004,
  *       "Programming the Hilbert curve") and interleaved as in R11.  The
@@ -282,6 +288,8 @@ typedef struct {
     double h;        /* spline support, 2.8 eps */
     int relative;    /* R25: 0 Barnes-Hut (R5), 1 relative criterion */
     double alpha;    /* relative criterion tolerance */
+    double eps;      /* softening length when no per-particle lengths */
+    const double *seps, *emax, *emin; /* R32: per-particle (sorted) and per-node */
 } ogo_walk_params;
 
 static double ogo_minimg(double d, const ogo_walk_params *p)
@@ -327,16 +335,17 @@ static void ogo_spline(double r, double h, double *g, double *w)
     }
 }
 
-static int ogo_pair(const double d[3], double m, const ogo_walk_params *p,
+/* Pair term with softening length e (the pair's, R32; else the global one). */
+static int ogo_pair(const double d[3], double m, double e, const ogo_walk_params *p,
                     double acc[3], double *pot)
 {
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (p->cutoff && !(r2 < p->rc2)) return 0;
     double g, w; /* softened 1/r^3 and 1/r */
     if (p->spline) {
-        ogo_spline(sqrt(r2), p->h, &g, &w);
+        ogo_spline(sqrt(r2), 2.8 * e, &g, &w);
     } else {
-        double rinv = 1.0 / sqrt(r2 + p->eps2);
+        double rinv = 1.0 / sqrt(r2 + e * e);
         g = rinv * rinv * rinv;
         w = rinv;
     }
@@ -356,6 +365,30 @@ static int ogo_pair(const double d[3], double m, const ogo_walk_params *p,
     return 1;
 }
 
+/* R32: largest and smallest softening length of every node's particles
+ * (written into one allocation, returned for freeing; NULL without
+ * per-particle lengths).                                                   */
+static double *ogo_node_eps(const double *seps, int64_t n_nodes, const uint32_t *first,
+                            const uint32_t *count, ogo_walk_params *p)
+{
+    p->seps = seps;
+    p->emax = p->emin = NULL;
+    if (!seps) return NULL;
+    double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)(n_nodes > 0 ? n_nodes : 1));
+    for (int64_t r = 0; r < n_nodes; ++r) {
+        double hi = seps[first[r]], lo = hi;
+        for (uint32_t j = first[r]; j < first[r] + count[r]; ++j) {
+            if (seps[j] > hi) hi = seps[j];
+            if (seps[j] < lo) lo = seps[j];
+        }
+        buf[r] = hi;
+        buf[n_nodes + r] = lo;
+    }
+    p->emax = buf;
+    p->emin = buf + n_nodes;
+    return buf;
+}
+
 /* Per-target tree walk (paper, "Tree walk"): one target per invocation,
  * starting at the root, moving to the first child (index + 1 in pre-order)
  * when a node is opened and to `skip` when it is accepted or pruned.      */
@@ -368,6 +401,7 @@ static int64_t ogo_walk_one(uint32_t ps, const double *spos, const double *smass
                             double aold, double acc[3], double *pot)
 {
     const double *xi = spos + 3 * (int64_t)ps;
+    const double ei = p->seps ? p->seps[ps] : p->eps;
     int64_t nint = 0;
     int64_t n = 0;
     acc[0] = acc[1] = acc[2] = 0.0;
@@ -389,8 +423,14 @@ static int64_t ogo_walk_one(uint32_t ps, const double *spos, const double *smass
                                    : (s * s > p->theta2 * r2);
         int open = far_open ||
                    (fabs(dc[0]) < near && fabs(dc[1]) < near && fabs(dc[2]) < near);
+        if (p->seps && p->emin[n] < p->emax[n] && p->emax[n] > ei) {
+            /* R32: mixed-softening check */
+            double hm = 2.8 * p->emax[n];
+            if (r2 < hm * hm) open = 1;
+        }
         if (!open) {
-            nint += ogo_pair(d, nmass[n], p, acc, pot);
+            double e = p->seps ? (ei > p->emax[n] ? ei : p->emax[n]) : p->eps;
+            nint += ogo_pair(d, nmass[n], e, p, acc, pot);
             n = skip[n];
         } else if (!is_leaf[n]) {
             n = n + 1;
@@ -399,7 +439,8 @@ static int64_t ogo_walk_one(uint32_t ps, const double *spos, const double *smass
                 if (j == ps) continue; /* R14 */
                 double dj[3];
                 for (int k = 0; k < 3; ++k) dj[k] = ogo_minimg(spos[3 * j + k] - xi[k], p);
-                nint += ogo_pair(dj, smass[j], p, acc, pot);
+                double e = p->seps ? (ei > p->seps[j] ? ei : p->seps[j]) : p->eps;
+                nint += ogo_pair(dj, smass[j], e, p, acc, pot);
             }
             n = skip[n];
         }
@@ -419,7 +460,7 @@ void ogo_walk(const double *spos, const double *smass, int64_t n_nodes,
               const double *nmass, const double *com3, int leaf_max,
               double G, double eps, double r_s, double r_cut, double theta,
               int periodic, double box, int softening, int criterion, double alpha,
-              const double *aold3, const uint32_t *tpos, int64_t M,
+              const double *aold3, const double *seps, const uint32_t *tpos, int64_t M,
               double *acc3, double *pot, int64_t *nint)
 {
     ogo_walk_params p;
@@ -436,6 +477,8 @@ void ogo_walk(const double *spos, const double *smass, int64_t n_nodes,
     p.h = 2.8 * eps;
     p.relative = criterion == 1;
     p.alpha = alpha;
+    p.eps = eps;
+    double *eminmax = ogo_node_eps(seps, n_nodes, first, count, &p);
     uint8_t *is_leaf = (uint8_t *)malloc((size_t)(n_nodes > 0 ? n_nodes : 1));
     for (int64_t r = 0; r < n_nodes; ++r)
         is_leaf[r] = !((int)count[r] > leaf_max && level[r] < OGO_LEVELS);
@@ -454,6 +497,7 @@ void ogo_walk(const double *spos, const double *smass, int64_t n_nodes,
         pot[t] = ph;
         if (nint) nint[t] = c;
     }
+    free(eminmax);
     free(is_leaf);
 }
 
@@ -469,8 +513,9 @@ void ogo_walk_groups(const double *spos, const double *smass, int64_t n_nodes,
                      const double *nmass, const double *com3, int leaf_max,
                      double G, double eps, double r_s, double r_cut, double theta,
                      int periodic, double box, int softening, int criterion, double alpha,
-                     const double *aold3, const uint32_t *tpos, const int64_t *goff,
-                     int64_t n_groups, double *acc3, double *pot, int64_t *nint)
+                     const double *aold3, const double *seps, const uint32_t *tpos,
+                     const int64_t *goff, int64_t n_groups, double *acc3, double *pot,
+                     int64_t *nint)
 {
     ogo_walk_params p;
     p.G = G;
@@ -486,6 +531,8 @@ void ogo_walk_groups(const double *spos, const double *smass, int64_t n_nodes,
     p.h = 2.8 * eps;
     p.relative = criterion == 1;
     p.alpha = alpha;
+    p.eps = eps;
+    double *eminmax = ogo_node_eps(seps, n_nodes, first, count, &p);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t g = 0; g < n_groups; ++g) {
         const int64_t t0 = goff[g], t1 = goff[g + 1];
@@ -519,6 +566,10 @@ void ogo_walk_groups(const double *spos, const double *smass, int64_t n_nodes,
                                           : (s * s > p.theta2 * r2);
                 if (far_open || (fabs(dc[0]) < near && fabs(dc[1]) < near && fabs(dc[2]) < near))
                     any_open = 1;
+                if (p.seps) { /* R32 */
+                    double ei = p.seps[tpos[t]], hm = 2.8 * p.emax[n];
+                    if (p.emin[n] < p.emax[n] && p.emax[n] > ei && r2 < hm * hm) any_open = 1;
+                }
             }
             if (!any_live) {
                 n = skip[n];
@@ -527,7 +578,9 @@ void ogo_walk_groups(const double *spos, const double *smass, int64_t n_nodes,
                     const double *xi = spos + 3 * (int64_t)tpos[t];
                     double d[3];
                     for (int k = 0; k < 3; ++k) d[k] = ogo_minimg(com3[3 * n + k] - xi[k], &p);
-                    nint[t] += ogo_pair(d, nmass[n], &p, acc3 + 3 * t, pot + t);
+                    double ei = p.seps ? p.seps[tpos[t]] : p.eps;
+                    double e = p.seps ? (ei > p.emax[n] ? ei : p.emax[n]) : p.eps;
+                    nint[t] += ogo_pair(d, nmass[n], e, &p, acc3 + 3 * t, pot + t);
                 }
                 n = skip[n];
             } else if (!leaf) {
@@ -539,11 +592,14 @@ void ogo_walk_groups(const double *spos, const double *smass, int64_t n_nodes,
                         const double *xi = spos + 3 * (int64_t)tpos[t];
                         double dj[3];
                         for (int k = 0; k < 3; ++k) dj[k] = ogo_minimg(spos[3 * j + k] - xi[k], &p);
-                        nint[t] += ogo_pair(dj, smass[j], &p, acc3 + 3 * t, pot + t);
+                        double ei = p.seps ? p.seps[tpos[t]] : p.eps;
+                        double e = p.seps ? (ei > p.seps[j] ? ei : p.seps[j]) : p.eps;
+                        nint[t] += ogo_pair(dj, smass[j], e, &p, acc3 + 3 * t, pot + t);
                     }
                 }
                 n = skip[n];
             }
         }
     }
+    free(eminmax);
 }
