@@ -495,7 +495,15 @@ VARIANT_LEGS = (
     ("spline", dict(softening="spline")),
     ("relative", dict(criterion="relative", alpha=0.0025)),
     ("spline_relative", dict(softening="spline", criterion="relative", alpha=0.0025)),
+    ("particle_lengths", dict(softening="spline", lengths=True)),
 )
+
+
+def particle_lengths(n, eps, seed=21):
+    """Per-particle softening lengths: 30 % of the particles at 5x eps, the
+    rest at eps, each scattered by a factor in [0.8, 1.2]."""
+    rng = np.random.default_rng(seed)
+    return eps * np.where(rng.random(n) < 0.3, 5.0, 1.0) * rng.uniform(0.8, 1.2, n)
 
 
 def leg_variants(og, torch, synth, args):
@@ -524,8 +532,16 @@ def leg_variants(og, torch, synth, args):
         a_bh, _, _ = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, base), targets=tg)
         a_old_o = np.zeros((n, 3))
         a_old_o[tg] = a_bh
+    eps_np = particle_lengths(n, base["eps"])
+    eps_t = torch.as_tensor(eps_np, device="cuda")
+    wsb = torch.empty(og.og_tree_workspace_bound(n, og.make_params(dict(base, eps_particle=eps_t))),
+                      dtype=torch.uint8, device="cuda")
     for name, extra in VARIANT_LEGS:
+        extra = dict(extra)
+        lengths = extra.pop("lengths", False)
         prm = dict(base, **extra)
+        if lengths:
+            prm["eps_particle"] = eps_t
         rel = prm.get("criterion") == "relative"
         row = {}
         for prec, steps in (("mixed", 5), ("fp64", 2)):
@@ -548,7 +564,8 @@ def leg_variants(og, torch, synth, args):
                                                           "leaf_max")},
                                   "softening": 1 if prm.get("softening") == "spline" else 0,
                                   "criterion": 1 if rel else 0, "alpha": prm.get("alpha", 0.0)})
-            a_o, _, n_o = oracle.tree_force(w.pos, w.mass, 1.0, op, targets=tg, a_old=a_old_o)
+            a_o, _, n_o = oracle.tree_force(w.pos, w.mass, 1.0, op, targets=tg, a_old=a_old_o,
+                                            eps=eps_np if lengths else None)
             e_m = _rel_err(am.cpu().numpy(), a_o)
             row["error_vs_oracle"] = {
                 "targets": int(tg.size), "mixed_median": float(np.median(e_m)),
@@ -558,8 +575,8 @@ def leg_variants(og, torch, synth, args):
         t.close()
         log("  %s: mixed %.3f ms/step, fp64 %.3f" % (name, row["mixed"]["ms_per_step"], row["fp64"]["ms_per_step"]))
         out[name] = row
-    out["workload"] = "mixture2m as the headline; variants: %s" % ", ".join(
-        "%s=%s" % (k, v) for k, v in VARIANT_LEGS)
+    out["workload"] = ("mixture2m as the headline; variants: %s; particle_lengths: 30%% of the particles at "
+                       "5x eps, the rest at eps, x U(0.8, 1.2), seed 21" % ", ".join("%s=%s" % (k, v) for k, v in VARIANT_LEGS))
     return out
 
 

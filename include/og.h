@@ -132,6 +132,19 @@ typedef struct og_params {
     int32_t criterion;      /* OG_OPEN_BH (default) or OG_OPEN_RELATIVE */
     int32_t curve;          /* OG_CURVE_MORTON (default) or OG_CURVE_HILBERT */
     int32_t lists;          /* OG_LISTS_TARGET (default) or OG_LISTS_GROUP */
+    const double *eps_particle; /* device [N] FP64, caller order: every
+                               particle's own (Plummer-equivalent) softening
+                               length, or NULL (all use eps).  A pair uses
+                               the larger of its two lengths; a node's
+                               monopole the larger of the target's and the
+                               node's largest; a node holding different
+                               lengths whose largest, e_max, exceeds the
+                               target's is opened when the target lies
+                               within 2.8 e_max of its centre of mass (the
+                               paper's mixed-softening check, "Tree walk").
+                               A length <= 0 or not finite gives OG_ERANGE
+                               from og_tree_status.  Not with
+                               OG_LISTS_GROUP (OG_EUNSUPPORTED). */
     void *stream;           /* hipStream_t, NULL = default stream */
     void *workspace;        /* optional caller device buffer for the tree */
     size_t workspace_bytes; /* its size; must be >= og_tree_workspace_bound */

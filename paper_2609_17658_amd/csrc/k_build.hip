@@ -363,7 +363,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *keys_
 // -------------------------------------------------------------- gather --
 __global__ __launch_bounds__(kThreads) void k_gather(const BoxDev *boxes, int B, uint32_t n,
                                                      const uint32_t *vals, uint32_t *perm,
-                                                     uint32_t *inv, double4 *part64) {
+                                                     uint32_t *inv, double4 *part64, double *seps,
+                                                     uint32_t *status) {
   uint32_t p = blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
   uint32_t g = vals[p];
@@ -373,6 +374,11 @@ __global__ __launch_bounds__(kThreads) void k_gather(const BoxDev *boxes, int B,
   part64[p] = make_double4(x[0], x[1], x[2], bx.mass[i]);
   perm[p] = g;
   inv[g] = p;
+  if (seps) {
+    const double e = bx.epsp ? bx.epsp[i] : bx.eps;
+    if (!(e > 0.0 && e < INFINITY)) atomicOr(status, kStatusRange);
+    seps[p] = e;
+  }
 }
 
 // ------------------------------------------------------------ topology --
@@ -548,10 +554,12 @@ __device__ inline void node_centre(const BoxDev &bx, uint64_t corner, int level,
 // each level, deepest first, sums its children in child order.  Every
 // node is summed once in a fixed order, so the result is deterministic, and
 // levels are separated by kernel boundaries only.
+// With per-particle softening lengths (seps non-null) every node also gets
+// the largest and smallest length of its particles (semax, semin).
 __global__ __launch_bounds__(kThreads) void k_leaves_and_buckets(
     const BoxDev *boxes, int B, const Topo *topo, const double4 *part64, float4 *part32, Mom64 *mom64,
     Mom32 *mom32, const uint32_t *scalars, uint32_t node_cap, const uint32_t *lvl_cnt, uint32_t *lvl_fill,
-    uint32_t *lvl_nodes) {
+    uint32_t *lvl_nodes, const double *seps, double *semax, double *semin) {
   __shared__ uint32_t base[kLevels + 1], lcount[kLevels + 1], lres[kLevels + 1];
   if (threadIdx.x <= kLevels) {
     uint32_t o = 0;
@@ -587,6 +595,15 @@ __global__ __launch_bounds__(kThreads) void k_leaves_and_buckets(
         const double com[3] = {c[0] + s0 / M, c[1] + s1 / M, c[2] + s2 / M};
         mom64[r] = Mom64{com[0], com[1], com[2], M};
         mom32[r] = Mom32{(float)(com[0] - c[0]), (float)(com[1] - c[1]), (float)(com[2] - c[2]), (float)M};
+        if (seps) {
+          double hi = seps[f], lo = hi;
+          for (uint32_t j = f + 1; j < f + cnt; ++j) {
+            hi = seps[j] > hi ? seps[j] : hi;
+            lo = seps[j] < lo ? seps[j] : lo;
+          }
+          semax[r] = hi;
+          semin[r] = lo;
+        }
       } else {
         lvl = (int)(t.b >> kCountBits);
         slot = atomicAdd(&lcount[lvl], 1u);
@@ -605,7 +622,8 @@ __global__ __launch_bounds__(kThreads) void k_moments_level(const BoxDev *boxes,
                                                             const Topo *topo, const uint32_t *first,
                                                             const uint32_t *skip, const uint32_t *lvl_cnt,
                                                             const uint32_t *lvl_nodes, const uint32_t *scalars,
-                                                            uint32_t node_cap, Mom64 *mom64, Mom32 *mom32) {
+                                                            uint32_t node_cap, Mom64 *mom64, Mom32 *mom32,
+                                                            double *semax, double *semin) {
   uint32_t o = 0;
   for (int l = 0; l < level; ++l) o += lvl_cnt[l];
   const uint32_t cnt = lvl_cnt[level];
@@ -617,6 +635,7 @@ __global__ __launch_bounds__(kThreads) void k_moments_level(const BoxDev *boxes,
     double cp[3];
     node_centre(bx, tp.corner, level, cp);
     double Mp = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    double hi = 0.0, lo = INFINITY;
     const uint32_t pend = min(tp.a, tot);
     for (uint32_t ch = par + 1; ch < pend;) {
       const Mom64 m = mom64[ch];
@@ -624,6 +643,10 @@ __global__ __launch_bounds__(kThreads) void k_moments_level(const BoxDev *boxes,
       q0 += m.m * (m.cx - cp[0]);
       q1 += m.m * (m.cy - cp[1]);
       q2 += m.m * (m.cz - cp[2]);
+      if (semax) {
+        hi = semax[ch] > hi ? semax[ch] : hi;
+        lo = semin[ch] < lo ? semin[ch] : lo;
+      }
       const uint32_t nx = skip[ch];
       if (nx <= ch) break;  // never taken for a well-formed tree
       ch = nx;
@@ -631,6 +654,10 @@ __global__ __launch_bounds__(kThreads) void k_moments_level(const BoxDev *boxes,
     const double cm[3] = {cp[0] + q0 / Mp, cp[1] + q1 / Mp, cp[2] + q2 / Mp};
     mom64[par] = Mom64{cm[0], cm[1], cm[2], Mp};
     mom32[par] = Mom32{(float)(cm[0] - cp[0]), (float)(cm[1] - cp[1]), (float)(cm[2] - cp[2]), (float)Mp};
+    if (semax) {
+      semax[par] = hi;
+      semin[par] = lo;
+    }
   }
 }
 
@@ -776,7 +803,7 @@ void launch_build(BuildArrays &A, hipStream_t s) {
   k_keys<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, k0, v0, &A.scalars[0]);
   radix_sort(k0, v0, k1, v1, n, 0, 8, box_passes, A.boxes, A.B, A.hist, A.digit_tot, s);
   const uint64_t *skeys = A.keys_a;
-  k_gather<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.vals_a, A.perm, A.inv, A.part64);
+  k_gather<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.vals_a, A.perm, A.inv, A.part64, A.seps, &A.scalars[0]);
   k_lcp_depth<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.nstart);
   scan_u32(A.nstart, A.S, &A.scalars[4], n, A.scan_partial, s);
   k_box_nodes<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.S, n, A.node_cap, A.scalars);
@@ -788,12 +815,13 @@ void launch_build(BuildArrays &A, hipStream_t s) {
   k_roots<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.parent);
   k_leaves_and_buckets<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.part64, A.part32, A.mom64,
                                                    A.mom32, A.scalars, A.node_cap, A.lvl_cnt, A.lvl_fill,
-                                                   A.lvl_nodes);
+                                                   A.lvl_nodes, A.seps, A.semax, A.semin);
   // internal nodes at level L number at most n / (leaf_max + 1) <= n / 2
   const uint32_t glev = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(n / 2 + 1, kThreads), 2048));
   for (int L = kLevels - 1; L >= 0; --L)
     k_moments_level<<<glev, kThreads, 0, s>>>(A.boxes, A.B, L, A.topo, A.first, A.skip, A.lvl_cnt,
-                                              A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32);
+                                              A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32, A.semax,
+                                              A.semin);
   k_wnodes<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.mom32, A.first, A.scalars, A.node_cap,
                                        A.wnode);
 }

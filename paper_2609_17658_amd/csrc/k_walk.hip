@@ -101,6 +101,8 @@ __device__ inline BoxDev ld(const BoxDev *p) {
   b.hsf = q->hsf;
   b.hinvf = q->hinvf;
   b.curve = q->curve;
+  b.epsp = q->epsp;
+  b.eps = q->eps;
   return b;
 }
 
@@ -237,17 +239,19 @@ __device__ inline void spline64(double r, double h, double &g, double &w) {
   }
 }
 
+// e: the pair's softening length (used by the kExt variants; the others
+// take the box's).
 template <bool kExt>
-__device__ inline void pair64(double dx, double dy, double dz, double m, const BoxDev &bx, double &ax,
-                              double &ay, double &az, double &ph, uint32_t &ni) {
+__device__ inline void pair64(double dx, double dy, double dz, double m, double e, const BoxDev &bx,
+                              double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(off)
   const double r2 = dx * dx + dy * dy + dz * dz;
   if (bx.cutoff && !(r2 < bx.rc2)) return;
   double g, w;  // softened 1/r^3 and 1/r
   if (kExt && bx.spline) {
-    spline64(sqrt(r2), bx.hs, g, w);
+    spline64(sqrt(r2), 2.8 * e, g, w);
   } else {
-    const double rinv = 1.0 / sqrt(r2 + bx.eps2);
+    const double rinv = 1.0 / sqrt(r2 + (kExt ? e * e : bx.eps2));
     g = rinv * rinv * rinv;
     w = rinv;
   }
@@ -292,6 +296,9 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
       const double *v = A.a_old + 3ull * (A.perm[p] - bx.p_off);
       aold = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     }
+    // softening: the target's own length (per-particle lengths) or the box's
+    const bool soft = kExt && A.seps != nullptr && bx.epsp != nullptr;
+    const double ei = soft && valid ? A.seps[p] : bx.eps;
     const bool periodic = bx.periodic;
     const double box = bx.box, h = bx.L * 0x1p-21;
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
@@ -335,9 +342,19 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
           const double near = 0.6 * side;
           const bool far_open = relative ? (bx.G * mm.m * side * side > bx.alpha * aold * r2 * r2)
                                             : (side * side > bx.theta2 * r2);
-          const bool open = far_open || (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
+          bool open = far_open || (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
+          double e = bx.eps;
+          if (soft) {
+            // the node's softening range; mixed-softening check
+            const double emax = *cptr(A.semax + n), emin = *cptr(A.semin + n);
+            if (emin < emax && emax > ei) {
+              const double hm = 2.8 * emax;
+              if (r2 < hm * hm) open = true;
+            }
+            e = ei > emax ? ei : emax;
+          }
           if (!open) {
-            pair64<kExt>(dx, dy, dz, mm.m, bx, ax, ay, az, ph, ni);
+            pair64<kExt>(dx, dy, dz, mm.m, e, bx, ax, ay, az, ph, ni);
             next = ns;
           } else if (!leaf) {
             open_int = true;
@@ -354,15 +371,20 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
           const uint32_t f = t.a, cnt = t.b & kCountMask;
           for (uint32_t base = 0; base < cnt; base += 64) {
             double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (base + lane < cnt) q = A.part64[f + base + lane];
+            double qe = bx.eps;
+            if (base + lane < cnt) {
+              q = A.part64[f + base + lane];
+              if (soft) qe = A.seps[f + base + lane];
+            }
             const uint32_t m = min(64u, cnt - base);
             for (uint32_t j = 0; j < m; ++j) {
               const double qx = rdl(q.x, j), qy = rdl(q.y, j), qz = rdl(q.z, j), qm = rdl(q.w, j);
+              const double ej = soft ? rdl(qe, j) : bx.eps;
               if (open_leaf && f + base + j != p) {
                 const double dx = minimg(qx - xi.x, periodic, box);
                 const double dy = minimg(qy - xi.y, periodic, box);
                 const double dz = minimg(qz - xi.z, periodic, box);
-                pair64<kExt>(dx, dy, dz, qm, bx, ax, ay, az, ph, ni);
+                pair64<kExt>(dx, dy, dz, qm, soft ? (ei > ej ? ei : ej) : bx.eps, bx, ax, ay, az, ph, ni);
               }
             }
           }
@@ -405,6 +427,7 @@ struct Consts32 {
   float G, eps2, inv2rs, rc2, theta2, h22, half_box, box;
   float hs2, hinv;  // spline support squared and inverse
   bool cutoff, periodic, spline;
+  bool soft;        // per-particle softening lengths: each pair brings its own
 };
 
 struct F4 {
@@ -451,22 +474,29 @@ __device__ inline void spline32(float u, float hinv, float &g, float &w) {
 
 // One partner at offset (dx, dy, dz) with r2 = |d|^2, mass m: FP32 pair
 // term, accumulated in FP64.
+// e: the pair's softening length when k.soft (kExt variants only).
 template <bool kExt>
 __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, const Consts32 &k, double &ax,
-                              double &ay, double &az, double &ph) {
+                              double &ay, double &az, double &ph, float e = 0.0f) {
 #pragma clang fp contract(fast)
   float g, wv;  // softened 1/r^3 and 1/r
   if (kExt && k.spline) {
+    float hs2 = k.hs2, hinv = k.hinv;
+    if (k.soft) {
+      const float h = 2.8f * e;
+      hs2 = h * h;
+      hinv = __builtin_amdgcn_rcpf(h);
+    }
     const float ri = __builtin_amdgcn_rsqf(r2);
-    if (r2 < k.hs2) {
+    if (r2 < hs2) {
       const float r = r2 > 0.0f ? r2 * ri : 0.0f;
-      spline32(r * k.hinv, k.hinv, g, wv);
+      spline32(r * hinv, hinv, g, wv);
     } else {
       g = ri * ri * ri;
       wv = ri;
     }
   } else {
-    const float rinv = __builtin_amdgcn_rsqf(r2 + k.eps2);
+    const float rinv = __builtin_amdgcn_rsqf(r2 + (kExt && k.soft ? e * e : k.eps2));
     g = rinv * rinv * rinv;
     wv = rinv;
   }
@@ -524,10 +554,10 @@ __device__ inline float leaf_tag(uint32_t first, uint32_t n, bool wrap) {
 // Evaluate and empty every lane's list, lane-parallel: each step every lane
 // takes the next partner of its own list (a monopole, or the next particle
 // of a leaf entry, read with a per-lane load), in list order.
-template <int kCap, bool kExt>
-__device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], uint32_t lane, uint32_t p,
-                             uint32_t &cnt, const Consts32 &k, double &ax, double &ay, double &az, double &ph,
-                             uint32_t &ni) {
+template <int kCap, bool kExt, bool kSoft>
+__device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], float (*lsoft)[kWalk32Threads],
+                             float eif, uint32_t lane, uint32_t p, uint32_t &cnt, const Consts32 &k, double &ax,
+                             double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(fast)
   uint32_t e = 0, j = 0;
   while (__ballot(e < cnt)) {
@@ -537,6 +567,8 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
       float dx = q.x, dy = q.y, dz = q.z, m = q.w;
       float r2 = dx * dx + dy * dy + dz * dz;
       bool use = true, particle = false;  // monopoles were counted when appended
+      float es = 0.0f;                    // the pair's softening length (k.soft)
+      if (kSoft && k.soft && !(tag & kTagLeaf)) es = lsoft[e][lane];
       if (tag & kTagLeaf) {
         particle = true;
         const uint32_t first = tag & kTagFirst, n = ((tag >> 27) & 7u) + 1u;
@@ -552,6 +584,10 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
         m = pq.w;
         r2 = dx * dx + dy * dy + dz * dz;
         use = (first + j != p) && (!k.cutoff || r2 < k.rc2);
+        if (kSoft && k.soft) {
+          const float ej = (float)A.seps[first + j];
+          es = eif > ej ? eif : ej;
+        }
         ++j;
         if (j == n) {
           j = 0;
@@ -561,7 +597,7 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
         ++e;
       }
       if (use) {
-        eval32<kExt>(dx, dy, dz, r2, m, k, ax, ay, az, ph);
+        eval32<kExt>(dx, dy, dz, r2, m, k, ax, ay, az, ph, es);
         ni += particle ? 1u : 0u;
       }
     }
@@ -572,11 +608,12 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
 // kMode: 0 = cutoff and periodicity read from each box; 1 = cutoff, open
 // boundaries; 2 = cutoff, periodic; 3 = plain Newtonian, open boundaries.
 // kExt: the spline softening and the relative criterion are read from each
-// box (only with kMode 0).
-template <int kCap, int kMode, bool kExt>  // list entries per lane; box kind; variants
+// box (only with kMode 0); kSoft (with kExt): per-particle softening lengths.
+template <int kCap, int kMode, bool kExt, bool kSoft = false>
 __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ float4 list[kCap][kWalk32Threads];
+  __shared__ float lsoft[kSoft ? kCap : 1][kWalk32Threads];  // monopoles' softening lengths
   const uint32_t lane = threadIdx.x;
   device_counts(A);
   GroupQueue Q = make_queue(A);
@@ -601,9 +638,11 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
     k.spline = kExt && bx.spline;
     k.hs2 = bx.hsf * bx.hsf;
     k.hinv = bx.hinvf;
+    k.soft = kSoft && A.seps != nullptr && bx.epsp != nullptr;  // this box has per-particle lengths
     const bool relative = kExt && bx.relative;
     uint32_t p = 0, slot = 0;
     const bool valid = lane_target(A, gr, bx, lane, p, slot);
+    const float eif = k.soft && valid ? (float)A.seps[p] : 0.0f;  // the target's softening length
     // relative criterion: open iff M side^2 > (alpha |a_old| / G) r^4
     float aol = 0.0f;
     if (relative && valid) {
@@ -649,7 +688,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       const uint32_t lc = w.cf & kWCount;
       // room for this visit's entry (a leaf of more than 8 particles makes
       // room entry by entry below)
-      if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
+      if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
       int d0 = w.c[0] - o0, d1 = w.c[1] - o1, d2 = w.c[2] - o2;
       if (kPer && (abs(w.c[0] - g0) > thr || abs(w.c[1] - g1) > thr || abs(w.c[2] - g2) > thr)) {
         d0 = wrap_cells(d0);
@@ -669,17 +708,25 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       const bool act = next == n;
       const bool live = act && !(kCut && mdc > w.reach);
       const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
-      const bool open = far_open || (mdc < w.near);
+      bool open = far_open || (mdc < w.near);
+      float emono = 0.0f;  // the monopole's softening length (k.soft)
+      if (kSoft && k.soft) {
+        const float emax = (float)*cptr(A.semax + n), emin = (float)*cptr(A.semin + n);
+        const float hm = 2.8f * emax;
+        if (emin < emax && emax > eif && r2 < hm * hm) open = true;
+        emono = eif > emax ? eif : emax;
+      }
       const bool contrib = live && !open && (!kCut || r2 < k.rc2);
       const bool open_here = live && open;
       if (leaf && lc > 8u) {
         // a leaf of more than 8 particles: an opening lane appends one entry
         // per 8 particles, an accepting lane its monopole once
         for (uint32_t j0 = 0; j0 < lc; j0 += 8) {
-          if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
+          if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
           if (open_here || (contrib && j0 == 0)) {
             list[cnt][lane] = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a + j0, min(8u, lc - j0), wrapd))
                                         : make_float4(dx, dy, dz, w.m);
+            if (kSoft) lsoft[cnt][lane] = emono;
             ++cnt;
           }
         }
@@ -689,6 +736,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
         const float4 entry = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a, lc, wrapd))
                                        : make_float4(dx, dy, dz, w.m);
         list[cnt][lane] = entry;
+        if (kSoft) lsoft[cnt][lane] = emono;
         const bool add = contrib || (leaf && open_here);
         cnt += add ? 1u : 0u;
         ni += contrib ? 1u : 0u;
@@ -703,7 +751,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       w = nn == n + 1 ? wa : wb;
       n = nn;
     }
-    flush<kCap, kExt>(A, list, lane, p, cnt, k, ax, ay, az, ph, ni);
+    flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
@@ -792,7 +840,7 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
       if (!__ballot(live)) {
         nn = nskip;
       } else if (!__ballot(open)) {
-        if (valid) pair64<kExt>(dx, dy, dz, mm.m, bx, ax, ay, az, ph, ni);
+        if (valid) pair64<kExt>(dx, dy, dz, mm.m, bx.eps, bx, ax, ay, az, ph, ni);
         nn = nskip;
       } else if (leaf) {
         const uint32_t f = t.a, cnt = t.b & kCountMask;
@@ -806,7 +854,7 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
               const double ex = minimg(qx - xi.x, periodic, box);
               const double ey = minimg(qy - xi.y, periodic, box);
               const double ez = minimg(qz - xi.z, periodic, box);
-              pair64<kExt>(ex, ey, ez, qm, bx, ax, ay, az, ph, ni);
+              pair64<kExt>(ex, ey, ez, qm, bx.eps, bx, ax, ay, az, ph, ni);
             }
           }
         }
@@ -863,6 +911,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walkg32(WalkArgs A) {
     k.spline = kExt && bx.spline;
     k.hs2 = bx.hsf * bx.hsf;
     k.hinv = bx.hinvf;
+    k.soft = false;  // per-particle softening is not offered with group lists
     const bool relative = kExt && bx.relative;
     uint32_t p = 0, slot = 0;
     const bool valid = lane_target(A, gr, bx, lane, p, slot);
@@ -1049,7 +1098,8 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
     const int mode = W.box_kind;
 #define OG_WALK32(C)                                                                 \
   do {                                                                               \
-    if (W.ext) k_walk32<C, 0, true><<<blocks, kWalk32Threads, 0, s>>>(W);            \
+    if (W.seps) k_walk32<C, 0, true, true><<<blocks, kWalk32Threads, 0, s>>>(W);     \
+    else if (W.ext) k_walk32<C, 0, true><<<blocks, kWalk32Threads, 0, s>>>(W);       \
     else if (mode == 2) k_walk32<C, 2, false><<<blocks, kWalk32Threads, 0, s>>>(W);  \
     else if (mode == 1) k_walk32<C, 1, false><<<blocks, kWalk32Threads, 0, s>>>(W);  \
     else if (mode == 3) k_walk32<C, 3, false><<<blocks, kWalk32Threads, 0, s>>>(W);  \

@@ -63,7 +63,7 @@ struct Carver {
   }
 };
 
-void carve(Carver &c, BuildArrays &A, uint32_t n, uint32_t node_cap, int B) {
+void carve(Carver &c, BuildArrays &A, uint32_t n, uint32_t node_cap, int B, bool soft) {
   A.boxes = c.take<BoxDev>(B);
   A.minmax = c.take<uint64_t>(6ull * B);
   A.keys_a = c.take<uint64_t>(n);
@@ -93,15 +93,20 @@ void carve(Carver &c, BuildArrays &A, uint32_t n, uint32_t node_cap, int B) {
   A.lvl_fill = c.take<uint32_t>(32);
   A.lvl_nodes = c.take<uint32_t>(node_cap);
   A.scalars = c.take<uint32_t>(32);
+  if (soft) {
+    A.seps = c.take<double>(n);
+    A.semax = c.take<double>(node_cap);
+    A.semin = c.take<double>(node_cap);
+  }
 }
 }  // namespace
 
 uint64_t node_bound(uint64_t n, int leaf_max) { return n + 21ull * (n / (uint64_t)(leaf_max + 1)) + 1ull; }
 
-size_t forest_bytes(uint32_t n, uint32_t node_cap, int B) {
+size_t forest_bytes(uint32_t n, uint32_t node_cap, int B, bool soft) {
   Carver c;
   BuildArrays A{};
-  carve(c, A, n, node_cap, B);
+  carve(c, A, n, node_cap, B, soft);
   return c.off + 256;
 }
 
@@ -125,9 +130,14 @@ int check_params(const og_params *p, int64_t N, double box, bool need_stream_fie
     return fail(OG_EINVAL, "unknown precision %d", p->precision);
   if (p->softening != OG_SOFT_PLUMMER && p->softening != OG_SOFT_SPLINE)
     return fail(OG_EINVAL, "unknown softening %d", p->softening);
-  if (p->softening == OG_SOFT_SPLINE && !(p->eps > 0.0)) return fail(OG_EINVAL, "spline softening needs eps > 0");
+  if (p->softening == OG_SOFT_SPLINE && !(p->eps > 0.0) && !p->eps_particle)
+    return fail(OG_EINVAL, "spline softening needs eps > 0");
   if (p->lists != OG_LISTS_TARGET && p->lists != OG_LISTS_GROUP)
     return fail(OG_EINVAL, "unknown lists mode %d", p->lists);
+  if (p->eps_particle && !is_device_ptr(p->eps_particle))
+    return fail(OG_EINVAL, "eps_particle must be a device pointer");
+  if (p->eps_particle && p->lists == OG_LISTS_GROUP)
+    return fail(OG_EUNSUPPORTED, "per-particle softening with group-shared lists is not available");
   if (p->curve != OG_CURVE_MORTON && p->curve != OG_CURVE_HILBERT)
     return fail(OG_EINVAL, "unknown curve %d", p->curve);
   if (p->criterion != OG_OPEN_BH && p->criterion != OG_OPEN_RELATIVE)
@@ -176,6 +186,8 @@ void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, doubl
   b.hsf = (float)b.hs;
   b.hinvf = b.spline ? (float)(1.0 / b.hs) : 0.0f;
   b.curve = p.curve == OG_CURVE_HILBERT ? 1 : 0;
+  b.epsp = p.eps_particle;
+  b.eps = p.eps;
   if (b.periodic) {
     b.lo[0] = b.lo[1] = b.lo[2] = 0.0;
     b.L = box;
@@ -208,7 +220,9 @@ int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream
     gtot += (b.n + group_max - 1) / group_max;
   }
   n_groups = (uint32_t)gtot;
-  bytes = forest_bytes(N, node_cap, B);
+  bool soft = false;
+  for (auto &b : hboxes) soft |= b.epsp != nullptr;
+  bytes = forest_bytes(N, node_cap, B, soft);
   if (workspace) {
     if (!is_device_ptr(workspace)) return fail(OG_EINVAL, "workspace is not device memory");
     if (ws_bytes < bytes) return fail(OG_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, bytes);
@@ -224,7 +238,7 @@ int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream
   }
   Carver c;
   c.base = static_cast<char *>(mem);
-  carve(c, A, N, node_cap, B);
+  carve(c, A, N, node_cap, B, soft);
   A.B = B;
   A.n = N;
   A.node_cap = node_cap;
@@ -264,6 +278,10 @@ WalkArgs Forest::walk_args() const {
   }
   W.counter = &A.scalars[8];
   W.group_lists = group_lists;
+  W.seps = A.seps;
+  W.semax = A.semax;
+  W.semin = A.semin;
+  if (A.seps) W.ext = 1;
   return W;
 }
 
@@ -422,7 +440,7 @@ size_t og_tree_workspace_bound(int64_t N, const og_params *p) {
   if (!p || p->struct_size != sizeof(og_params) || N < 1 || N > (int64_t)kCountMask || p->leaf_max < 1 ||
       p->leaf_max > 4096)
     return 0;
-  return forest_bytes((uint32_t)N, (uint32_t)node_bound((uint64_t)N, p->leaf_max), 1);
+  return forest_bytes((uint32_t)N, (uint32_t)node_bound((uint64_t)N, p->leaf_max), 1, p->eps_particle != nullptr);
 }
 
 int og_tree_build(const double *pos, const double *mass, int64_t N, double box, const og_params *params,

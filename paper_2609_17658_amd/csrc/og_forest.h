@@ -23,7 +23,7 @@ int check_params(const og_params *p, int64_t N, double box, bool need_stream_fie
 void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, double box, const og_params &p,
               uint32_t p_off);
 uint64_t node_bound(uint64_t n, int leaf_max);
-size_t forest_bytes(uint32_t n, uint32_t node_cap, int B);
+size_t forest_bytes(uint32_t n, uint32_t node_cap, int B, bool soft);
 
 struct Forest {
   int B = 0;

@@ -42,6 +42,8 @@ struct BoxDev {
   double hs, alpha;          // spline support 2.8 eps; relative tolerance
   float hsf, hinvf;          // FP32 support and its inverse
   int32_t curve;             // 0 Morton, 1 Peano-Hilbert keys
+  const double *epsp;        // caller [n] per-particle softening lengths, or null
+  double eps;                // softening length of particles without their own
 };
 
 // Walk-order node record, 16 bytes.

@@ -46,6 +46,8 @@ struct BuildArrays {
   uint32_t *scalars;          // [0] status [3] n_nodes [4] n [8..15] walk queues
                               // [5] deepest level (stats)
   int any_open;               // some box has periodic = 0
+  double *seps;               // sorted per-particle softening lengths (null: none given)
+  double *semax, *semin;      // per node: largest and smallest of its particles' lengths
 };
 
 void launch_build(BuildArrays &A, hipStream_t s);
@@ -107,6 +109,7 @@ struct WalkArgs {
   int pot_override;           // 1: use `pot` (possibly null) instead of the box's
   int ext;                    // some box uses spline softening or the relative criterion
   const uint32_t *dev_count;  // non-null: n_targets = [0], n_groups = [1], read on the device
+  const double *seps, *semax, *semin;  // per-particle softening (null: the boxes' eps)
   int group_lists;            // 1: group-shared interaction lists, 0: per-target walk
   const double *a_old;        // relative criterion: previous accelerations [n][3], caller order
 };

@@ -37,7 +37,7 @@ class og_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("group_max", ctypes.c_int32),
                 ("walk_list_cap", ctypes.c_int32), ("softening", ctypes.c_int32),
                 ("criterion", ctypes.c_int32), ("curve", ctypes.c_int32), ("lists", ctypes.c_int32),
-                ("stream", ctypes.c_void_p),
+                ("eps_particle", ctypes.c_void_p), ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
@@ -170,6 +170,8 @@ def make_params(params=None, stream=None, workspace=None, **kw) -> og_params:
             v = CURVES[v]
         elif k == "lists":
             v = LISTS[v]
+        elif k == "eps_particle":
+            v = None if v is None else (v if isinstance(v, int) else v.data_ptr())
         setattr(p, k, v)
     p.stream = _stream_handle(stream)
     if workspace is not None:
@@ -342,7 +344,10 @@ class Tree:
         self.N = int(pos.shape[0])
         self.device = pos.device
         self.params = make_params(params, stream=stream, workspace=workspace, **kw)
-        self._keep = (pos, mass, workspace)
+        eps_t = kw.get("eps_particle")
+        if eps_t is None and isinstance(params, dict):
+            eps_t = params.get("eps_particle")
+        self._keep = (pos, mass, workspace, eps_t)
         self.handle = og_tree_build(pos, mass, self.N, box, self.params)
 
     def force(self, targets=None, precision=None, with_pot=True, with_counts=False, stream=None,

@@ -30,11 +30,12 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_default_and_struct_layout():
     p = og.og_params_default()
-    assert p.struct_size == ctypes.sizeof(og.og_params) == 120
+    assert p.struct_size == ctypes.sizeof(og.og_params) == 128
     assert (p.G, p.eps, p.r_s, p.r_cut, p.theta, p.alpha) == (1.0, 0.0, 0.0, 0.0, 0.5, 0.0)
     assert (p.periodic, p.leaf_max, p.precision, p.group_max, p.walk_list_cap) == (1, 8, og.OG_PREC_MIXED, 0, 0)
     assert (p.softening, p.criterion, p.curve) == (og.OG_SOFT_PLUMMER, og.OG_OPEN_BH, og.OG_CURVE_MORTON)
-    assert ctypes.sizeof(og.og_box) == 8 + 8 + 8 + 8 + 120 + 8 + 8
+    assert ctypes.sizeof(og.og_box) == 8 + 8 + 8 + 8 + 128 + 8 + 8
+    assert p.eps_particle is None
     assert p.lists == og.OG_LISTS_TARGET
     assert ctypes.sizeof(og.og_force_opts) == 32
 
@@ -113,3 +114,12 @@ def test_header_layout_matches_binding(tmp_path):
         assert int(got[st]) == ctypes.sizeof(cls), st
         for f in fs:
             assert int(got["%s.%s" % (st, f)]) == getattr(cls, f).offset, (st, f)
+
+
+def test_build_rejects_host_softening_lengths():
+    import numpy as np
+    lib = og.load()
+    eps = np.full(100, 0.01)
+    p = og.make_params(r_s=0.01, eps_particle=eps.ctypes.data)
+    h = ctypes.c_void_p()
+    assert lib.og_tree_build(None, None, 100, 1.0, ctypes.byref(p), ctypes.byref(h)) == og.OG_EINVAL
