@@ -14,8 +14,10 @@
 // n + 1 when any lane opened n (ballot), otherwise to skip(n).  A lane
 // therefore sees exactly the node sequence of its own walk, in the same
 // order, so its result does not depend on the group it was placed in.
-// Node records are wave-uniform: they are read with scalar loads, and the
-// records of both possible successors are requested before the decision.
+// Node records are wave-uniform: they are read with scalar loads, one per
+// visit, once the wave has chosen the node (requesting both possible
+// successors ahead of the decision costs more vector work to select between
+// them than the load latency it hides).
 #include <cstdlib>
 
 #include "og_kernels.h"
@@ -306,16 +308,11 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
     uint32_t n = bx.root;
     const uint32_t nend = bx.node_end;
     uint32_t next = valid ? n : nend;
-    Topo t = ld(A.topo + n);
-    Mom64 mm = ld(A.mom64 + n);
     while (n < nend) {
+      const Topo t = ld(A.topo + n);
+      const Mom64 mm = ld(A.mom64 + n);
       const bool leaf = (t.corner & kLeafBit) != 0;
       const uint32_t ns = leaf ? n + 1 : t.a;
-      const uint32_t n1c = min(n + 1, nend - 1), nsc = min(ns, nend - 1);
-      const Topo t1 = ld(A.topo + n1c);
-      const Mom64 m1 = ld(A.mom64 + n1c);
-      const Topo ts = ld(A.topo + nsc);
-      const Mom64 msk = ld(A.mom64 + nsc);
       const int lev = (int)(t.b >> kCountBits);
       const double side = ldexp(bx.L, -lev);
       const double half = ldexp(1.0, 20 - lev);
@@ -393,9 +390,6 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
       } else {
         nn = (__ballot(open_int) || t.a <= n) ? n + 1 : t.a;
       }
-      const bool first_child = nn == n + 1;
-      t = first_child ? t1 : ts;
-      mm = first_child ? m1 : msk;
       n = nn;
     }
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
@@ -679,12 +673,12 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
     uint32_t n = bx.root;
     const uint32_t nend = bx.node_end;
     uint32_t next = valid ? n : nend;
-    WNode w = ldw(A.wnode + n);
+    // the next node's record is read after the decision (the wave's other
+    // work and the other waves on the SIMD cover the scalar load)
     while (n < nend) {
+      const WNode w = ldw(A.wnode + n);
       const bool leaf = (w.cf & kWLeaf) != 0;
       const uint32_t ns = leaf ? n + 1 : w.a;
-      const WNode wa = ldw(A.wnode + min(n + 1, nend - 1));
-      const WNode wb = ldw(A.wnode + min(ns, nend - 1));
       const uint32_t lc = w.cf & kWCount;
       // room for this visit's entry (a leaf of more than 8 particles makes
       // room entry by entry below)
@@ -748,7 +742,6 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       } else {
         nn = (__ballot(open_here) || ns <= n) ? n + 1 : ns;
       }
-      w = nn == n + 1 ? wa : wb;
       n = nn;
     }
     flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
@@ -796,16 +789,11 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
     uint32_t ni = 0;
     uint32_t n = bx.root;
     const uint32_t nend = bx.node_end;
-    Topo t = ld(A.topo + n);
-    Mom64 mm = ld(A.mom64 + n);
     while (n < nend) {
+      const Topo t = ld(A.topo + n);
+      const Mom64 mm = ld(A.mom64 + n);
       const bool leaf = (t.corner & kLeafBit) != 0;
       const uint32_t ns = leaf ? n + 1 : t.a;
-      const uint32_t n1c = min(n + 1, nend - 1), nsc = min(ns, nend - 1);
-      const Topo t1 = ld(A.topo + n1c);
-      const Mom64 m1 = ld(A.mom64 + n1c);
-      const Topo ts = ld(A.topo + nsc);
-      const Mom64 msk = ld(A.mom64 + nsc);
       const int lev = (int)(t.b >> kCountBits);
       const double side = ldexp(bx.L, -lev);
       const double half = ldexp(1.0, 20 - lev);
@@ -862,9 +850,6 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
       } else {
         nn = n + 1;
       }
-      const bool first_child = nn == n + 1;
-      t = first_child ? t1 : ts;
-      mm = first_child ? m1 : msk;
       n = nn;
     }
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
@@ -974,12 +959,10 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walkg32(WalkArgs A) {
     };
     uint32_t n = bx.root;
     const uint32_t nend = bx.node_end;
-    WNode w = ldw(A.wnode + n);
     while (n < nend) {
+      const WNode w = ldw(A.wnode + n);
       const bool leaf = (w.cf & kWLeaf) != 0;
       const uint32_t ns = leaf ? n + 1 : w.a;
-      const WNode wa = ldw(A.wnode + min(n + 1, nend - 1));
-      const WNode wb = ldw(A.wnode + min(ns, nend - 1));
       const uint32_t lc = w.cf & kWCount;
       int d0 = w.c[0] - o0, d1 = w.c[1] - o1, d2 = w.c[2] - o2;
       if (kPer && (abs(w.c[0] - g0) > thr || abs(w.c[1] - g1) > thr || abs(w.c[2] - g2) > thr)) {
@@ -1044,7 +1027,6 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walkg32(WalkArgs A) {
         }
         nn = n + 1;
       }
-      w = nn == n + 1 ? wa : wb;
       n = nn;
     }
     flush();
