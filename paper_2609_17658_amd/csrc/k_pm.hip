@@ -17,6 +17,7 @@
 //      W the CIC window, and a_k = -i k phi_k; the two inverse transforms
 //      carry (a_x + i a_y) and (a_z + i phi), each a pair of real fields;
 //   4. inverse FFTs, then CIC interpolation at the particles.
+#include <climits>
 #include <cmath>
 
 #include "og_pm.h"
@@ -109,6 +110,99 @@ __global__ __launch_bounds__(kPmThreads) void k_deposit(PartRef P, uint32_t N, i
         const unsigned long long q = (unsigned long long)llrint(m * wx[a] * wy[b] * wz[c]);
         atomicAdd(acc_mesh + ((uint64_t)jx[a] * n + jy[b]) * n + jz[c], q);
       }
+}
+
+// Deposit of particles in curve order: the 256 particles of a workgroup
+// are neighbours in space, so their 8 x 256 node weights are first summed in
+// an LDS tile spanning the workgroup's box of nodes, then the tile is added
+// to the mesh (one global atomic per touched node).  Integer sums: the
+// result is the same as adding every weight to the mesh directly, which is
+// what a workgroup whose box exceeds the tile (straddling the periodic edge,
+// or spread out) does.
+constexpr int kDepositTile = 4096;  // nodes (32 KB)
+
+__global__ __launch_bounds__(kPmThreads) void k_deposit_tiled(PartRef P, uint32_t N, int n, double inv_d,
+                                                              const unsigned long long *mmax,
+                                                              unsigned long long *acc_mesh) {
+  __shared__ unsigned long long tile[kDepositTile];
+  __shared__ int red[6][kPmThreads / 64];
+  const uint32_t i = blockIdx.x * kPmThreads + threadIdx.x;
+  const bool ok = i < N;
+  const double scale = fixed_scale(mmax, N);
+  int ix = 0, iy = 0, iz = 0;
+  double fx = 0.0, fy = 0.0, fz = 0.0, m = 0.0;
+  if (ok) {
+    const double4 q = P.get(i);
+    cic(q.x, n, inv_d, ix, fx);
+    cic(q.y, n, inv_d, iy, fy);
+    cic(q.z, n, inv_d, iz, fz);
+    m = q.w * scale;
+  }
+  // the workgroup's box of lower nodes (the upper node is +1, unwrapped)
+  int v[6] = {ok ? ix : INT_MAX, ok ? iy : INT_MAX, ok ? iz : INT_MAX,
+              ok ? ix : INT_MIN, ok ? iy : INT_MIN, ok ? iz : INT_MIN};
+  for (int off = 32; off > 0; off >>= 1)
+    for (int a = 0; a < 6; ++a) {
+      const int o = __shfl_xor(v[a], off, 64);
+      v[a] = a < 3 ? min(v[a], o) : max(v[a], o);
+    }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int a = 0; a < 6; ++a) red[a][wv] = v[a];
+  __syncthreads();
+  int lo[3], ext[3];
+  for (int a = 0; a < 3; ++a) {
+    int l = red[a][0], h = red[a + 3][0];
+    for (int w = 1; w < kPmThreads / 64; ++w) {
+      l = min(l, red[a][w]);
+      h = max(h, red[a + 3][w]);
+    }
+    lo[a] = l;
+    ext[a] = h - l + 2;  // nodes lo .. h + 1
+  }
+  const long long vol = (long long)ext[0] * ext[1] * ext[2];
+  const int wx[2] = {0, 1};
+  const double wgt[3][2] = {{1.0 - fx, fx}, {1.0 - fy, fy}, {1.0 - fz, fz}};
+  if (vol <= kDepositTile) {
+    for (int c = threadIdx.x; c < (int)vol; c += kPmThreads) tile[c] = 0ull;
+    __syncthreads();
+    if (ok) {
+      const int rx = ix - lo[0], ry = iy - lo[1], rz = iz - lo[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const unsigned long long qv = (unsigned long long)llrint(m * wgt[0][a] * wgt[1][b] * wgt[2][c]);
+            atomicAdd(&tile[((rx + wx[a]) * ext[1] + ry + wx[b]) * ext[2] + rz + wx[c]], qv);
+          }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < (int)vol; c += kPmThreads) {
+      const unsigned long long qv = tile[c];
+      if (!qv) continue;
+      const int cz = c % ext[2], cy = (c / ext[2]) % ext[1], cx = c / (ext[2] * ext[1]);
+      int gx = lo[0] + cx, gy = lo[1] + cy, gz = lo[2] + cz;
+      gx = gx >= n ? gx - n : gx;
+      gy = gy >= n ? gy - n : gy;
+      gz = gz >= n ? gz - n : gz;
+      atomicAdd(acc_mesh + ((uint64_t)gx * n + gy) * n + gz, qv);
+    }
+  } else if (ok) {
+    const int jx[2] = {ix, ix + 1 == n ? 0 : ix + 1};
+    const int jy[2] = {iy, iy + 1 == n ? 0 : iy + 1};
+    const int jz[2] = {iz, iz + 1 == n ? 0 : iz + 1};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const unsigned long long qv = (unsigned long long)llrint(m * wgt[0][a] * wgt[1][b] * wgt[2][c]);
+          atomicAdd(acc_mesh + ((uint64_t)jx[a] * n + jy[b]) * n + jz[c], qv);
+        }
+  }
 }
 
 // Fixed point -> density (mass / cell volume), as the real part.
@@ -303,13 +397,16 @@ void launch_pm(const PmArgs &P, hipStream_t s) {
   unsigned long long *fixed = reinterpret_cast<unsigned long long *>(P.A);  // aliases A until k_green
   k_fill_u64<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells);
   k_fill_u64<<<1, kPmThreads, 0, s>>>(P.mmax, 1);
-  // Deposits in caller order (neighbouring threads rarely share a cell, so
-  // their atomics do not collide); interpolation in curve order (the eight
-  // nodes of neighbouring threads are shared in cache).
+  // Caller order: direct atomics (neighbouring threads rarely share a node).
+  // Curve order (a tree's particles): LDS tiles per workgroup.  Interpolation
+  // in curve order shares the eight nodes of neighbouring threads in cache.
   const PartRef R{P.pos, P.mass, P.part, nullptr};
-  const PartRef Rd{P.pos, P.mass, P.part, P.part ? P.inv : nullptr};
   k_mass_max<<<blocks_for(P.N, kPmThreads, 1024), kPmThreads, 0, s>>>(R, P.N, P.mmax);
-  k_deposit<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(Rd, P.N, P.n, inv_d, P.mmax, fixed);
+  if (P.part)
+    k_deposit_tiled<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(R, P.N, P.n, inv_d, P.mmax,
+                                                                                 fixed);
+  else
+    k_deposit<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(R, P.N, P.n, inv_d, P.mmax, fixed);
   k_density<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells, P.N, P.mmax,
                                                                        1.0 / (d * d * d), P.B);
   launch_fft3(P.B, P.n, -1, s);
