@@ -130,7 +130,7 @@ __device__ inline double ord2d(uint64_t u) {
   return __longlong_as_double((long long)u);
 }
 
-__global__ __launch_bounds__(kThreads) void k_frame_init(BoxDev *boxes, int B, uint64_t *minmax) {
+__global__ __launch_bounds__(kThreads) void k_frame_init(int B, uint64_t *minmax) {
   int i = blockIdx.x * kThreads + threadIdx.x;
   if (i < 6 * B) minmax[i] = (i % 6) < 3 ? ~0ull : 0ull;
 }
@@ -738,7 +738,7 @@ int g_cu = 0;
 int device_cu_count() {
   if (g_cu == 0) {
     int dev = 0;
-    hipGetDevice(&dev);
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
       cu = 256;
@@ -791,7 +791,7 @@ void launch_build(BuildArrays &A, hipStream_t s) {
   k_reset<<<1, 1, 0, s>>>(&A.scalars[0]);
   k_set<<<1, 1, 0, s>>>(&A.scalars[4], n);
   if (A.any_open) {
-    k_frame_init<<<cdiv(6 * (uint64_t)A.B, kThreads), kThreads, 0, s>>>(A.boxes, A.B, A.minmax);
+    k_frame_init<<<cdiv(6 * (uint64_t)A.B, kThreads), kThreads, 0, s>>>(A.B, A.minmax);
     k_frame_reduce<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.minmax, &A.scalars[0]);
     k_frame_finalize<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.minmax);
   }

@@ -48,9 +48,8 @@ __global__ __launch_bounds__(kPmThreads) void k_fill_u64(unsigned long long *p, 
 struct PartRef {
   const double *pos, *mass;
   const double4 *part;
-  const uint32_t *order;  // with part: visit part[order[i]] (null: part[i])
   __device__ inline double4 get(uint32_t i) const {
-    if (part) return part[order ? order[i] : i];
+    if (part) return part[i];
     return make_double4(pos[3ull * i], pos[3ull * i + 1], pos[3ull * i + 2], mass[i]);
   }
 };
@@ -400,7 +399,7 @@ void launch_pm(const PmArgs &P, hipStream_t s) {
   // Caller order: direct atomics (neighbouring threads rarely share a node).
   // Curve order (a tree's particles): LDS tiles per workgroup.  Interpolation
   // in curve order shares the eight nodes of neighbouring threads in cache.
-  const PartRef R{P.pos, P.mass, P.part, nullptr};
+  const PartRef R{P.pos, P.mass, P.part};
   k_mass_max<<<blocks_for(P.N, kPmThreads, 1024), kPmThreads, 0, s>>>(R, P.N, P.mmax);
   if (P.part)
     k_deposit_tiled<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(R, P.N, P.n, inv_d, P.mmax,

@@ -53,10 +53,6 @@ __device__ inline Topo ld(const Topo *p) {
   t.b = q->b;
   return t;
 }
-__device__ inline Mom32 ld(const Mom32 *p) {
-  const auto q = cptr(p);
-  return Mom32{q->ox, q->oy, q->oz, q->m};
-}
 __device__ inline Mom64 ld(const Mom64 *p) {
   const auto q = cptr(p);
   return Mom64{q->cx, q->cy, q->cz, q->m};
@@ -108,9 +104,6 @@ __device__ inline BoxDev ld(const BoxDev *p) {
   return b;
 }
 
-__device__ inline float rdl(float v, uint32_t j) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)j));
-}
 __device__ inline double rdl(double v, uint32_t j) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), (int)j);
@@ -424,10 +417,6 @@ struct Consts32 {
   bool soft;        // per-particle softening lengths: each pair brings its own
 };
 
-struct F4 {
-  float x, y, z, w;
-};
-
 __device__ inline WNode ldw(const WNode *p) {
   const auto q = cptr(p);
   WNode w;
@@ -444,11 +433,6 @@ __device__ inline WNode ldw(const WNode *p) {
   w.a = q->a;
   w.cf = q->cf;
   return w;
-}
-
-__device__ inline F4 ldp(const float4 *p) {
-  const auto q = cptr(reinterpret_cast<const F4 *>(p));
-  return F4{q->x, q->y, q->z, q->w};
 }
 
 // Spline-softened 1/r^3 (g) and 1/r (w) inside the support, u = r/h < 1.
@@ -523,11 +507,6 @@ __device__ inline float wrap_box(float d, const Consts32 &k) {
   return d < -k.half_box ? d + k.box : hi;
 }
 
-__device__ inline int wave_min_i32(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-  return __builtin_amdgcn_readfirstlane(v);
-}
 __device__ inline int wave_max_i32(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));

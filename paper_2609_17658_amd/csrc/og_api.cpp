@@ -396,16 +396,29 @@ int Forest::read_status(hipStream_t s) {
   return OG_OK;
 }
 
+int order_after(hipStream_t waiter, hipStream_t producer) {
+  if (waiter == producer) return OG_OK;
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  e = hipEventRecord(ev, producer);
+  if (e == hipSuccess) e = hipStreamWaitEvent(waiter, ev, 0);
+  (void)hipEventDestroy(ev);  // released once the wait is satisfied
+  if (e != hipSuccess) return hip_fail(e, "stream ordering");
+  return OG_OK;
+}
+
+// Release paths ignore HIP errors: there is nothing left to report them to.
 void Forest::release() {
   if (gexec) {
-    hipGraphExecDestroy(gexec);
+    (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
   }
   if (own_stream) {
-    hipStreamDestroy(own_stream);
+    (void)hipStreamDestroy(own_stream);
     own_stream = nullptr;
   }
-  if (mem && own) hipFree(mem);
+  if (mem && own) (void)hipFree(mem);
   mem = nullptr;
 }
 
@@ -496,14 +509,9 @@ int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_fo
   }
   if (!is_device_ptr(acc)) return fail(OG_EINVAL, "acc must be a device pointer");
   if (pot && !is_device_ptr(pot)) return fail(OG_EINVAL, "pot must be a device pointer");
-  if (s != F.stream) {
-    // order after the build on the tree's stream
-    hipEvent_t ev;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    hipEventRecord(ev, F.stream);
-    hipStreamWaitEvent(s, ev, 0);
-    hipEventDestroy(ev);
+  {
+    const int rc = order_after(s, F.stream);  // after the build on the tree's stream
+    if (rc != OG_OK) return rc;
   }
   if (!targets || !targets->idx) {
     if (targets && targets->M != (int64_t)F.N)
@@ -550,13 +558,9 @@ int og_tree_force_active(const og_tree *tree, const int8_t *bin, int32_t level, 
   } else {
     a_old = nullptr;
   }
-  if (s != F.stream) {
-    hipEvent_t ev;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    hipEventRecord(ev, F.stream);
-    hipStreamWaitEvent(s, ev, 0);
-    hipEventDestroy(ev);
+  {
+    const int rc = order_after(s, F.stream);
+    if (rc != OG_OK) return rc;
   }
   return F.walk_active(prec, s, bin, level, acc, pot, nint, a_old, n_active);
 }
@@ -623,7 +627,7 @@ int og_tree_export(const og_tree *tree, uint64_t *keys, uint32_t *perm, uint32_t
 
 int og_tree_free(og_tree *tree) {
   if (!tree) return OG_OK;
-  hipStreamSynchronize(tree->F.stream);
+  (void)hipStreamSynchronize(tree->F.stream);
   tree->F.release();
   delete tree;
   return OG_OK;
@@ -699,29 +703,25 @@ int og_batch_graph_replay(og_batch *b) {
     F.stream = keep;
     e = hipStreamEndCapture(cs, &g);
     if (rc1 || rc2) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc1 ? rc1 : rc2;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&F.gexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       F.gexec = nullptr;
       return hip_fail(e, "hipGraphInstantiate");
     }
   }
   if (cs != F.stream) {  // order the private stream after the caller's stream and back
-    hipEvent_t ev;
-    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-    hipEventRecord(ev, F.stream);
-    hipStreamWaitEvent(cs, ev, 0);
+    int rc = order_after(cs, F.stream);
+    if (rc != OG_OK) return rc;
     e = hipGraphLaunch(F.gexec, cs);
-    hipEventRecord(ev, cs);
-    hipStreamWaitEvent(F.stream, ev, 0);
-    hipEventDestroy(ev);
-  } else {
-    e = hipGraphLaunch(F.gexec, cs);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return order_after(F.stream, cs);
   }
+  e = hipGraphLaunch(F.gexec, cs);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return OG_OK;
 }
@@ -738,8 +738,8 @@ int og_batch_status(const og_batch *b) {
 
 int og_batch_free(og_batch *b) {
   if (!b) return OG_OK;
-  hipStreamSynchronize(b->F.stream);
-  if (b->F.own_stream) hipStreamSynchronize(b->F.own_stream);
+  (void)hipStreamSynchronize(b->F.stream);
+  if (b->F.own_stream) (void)hipStreamSynchronize(b->F.own_stream);
   b->F.release();
   delete b;
   return OG_OK;

@@ -18,6 +18,9 @@ namespace og {
 
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
+// Make `waiter` wait for the work enqueued so far on `producer` (no-op when
+// they are the same stream).  OG_OK or OG_EDEVICE.
+int order_after(hipStream_t waiter, hipStream_t producer);
 bool is_device_ptr(const void *p);
 int check_params(const og_params *p, int64_t N, double box, bool need_stream_fields);
 void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, double box, const og_params &p,

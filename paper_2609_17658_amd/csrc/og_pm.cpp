@@ -98,7 +98,6 @@ int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, i
   PmArgs P{};
   P.part = F.A.part64;
   P.perm = F.A.perm;
-  P.inv = F.A.inv;
   P.N = F.N;
   P.n = pm->n;
   P.L = pm->L;
@@ -111,14 +110,8 @@ int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, i
   P.pot = pot;
   P.accumulate = accumulate ? 1 : 0;
   // the tree's particles are ready once its stream has passed the build
-  if (pm->stream != F.stream) {
-    hipEvent_t ev;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    hipEventRecord(ev, F.stream);
-    hipStreamWaitEvent(pm->stream, ev, 0);
-    hipEventDestroy(ev);
-  }
+  const int rc = order_after(pm->stream, F.stream);
+  if (rc != OG_OK) return rc;
   launch_pm(P, pm->stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "particle-mesh launch");
@@ -127,8 +120,8 @@ int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, i
 
 int og_pm_free(og_pm *pm) {
   if (!pm) return OG_OK;
-  hipStreamSynchronize(pm->stream);
-  if (pm->mem) hipFree(pm->mem);
+  (void)hipStreamSynchronize(pm->stream);
+  if (pm->mem) (void)hipFree(pm->mem);
   delete pm;
   return OG_OK;
 }

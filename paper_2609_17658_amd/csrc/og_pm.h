@@ -12,7 +12,6 @@ struct PmArgs {
   const double *mass;  // caller [N]
   const double4 *part; // or: a tree's particles in curve order, (x, y, z, m)
   const uint32_t *perm;  // with part: curve position -> caller index
-  const uint32_t *inv;   // with part: caller index -> curve position
   uint32_t N;
   int n;               // mesh points per axis, power of two, 8..1024
   double L, G, r_s;

@@ -189,8 +189,8 @@ int og_server_create(size_t hbm_budget_bytes, int32_t max_slots, og_server **out
   for (int i = 0; i < max_slots; ++i) {
     e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
     if (e != hipSuccess) {
-      for (int j = 0; j < i; ++j) hipStreamDestroy(s->streams[j]);
-      hipFree(s->mem);
+      for (int j = 0; j < i; ++j) (void)hipStreamDestroy(s->streams[j]);
+      (void)hipFree(s->mem);
       delete s;
       return hip_fail(e, "hipStreamCreate");
     }
@@ -294,7 +294,7 @@ int og_server_release(og_server *s, uint64_t ticket) {
   if (it == s->reqs.end()) return fail(OG_ENOTFOUND, "unknown ticket");
   Request &r = it->second;
   if (r.state == kRunning) {
-    hipEventSynchronize(r.ev);
+    (void)hipEventSynchronize(r.ev);
     s->retire_locked();
   }
   if (r.state == kPending) {
@@ -310,7 +310,7 @@ int og_server_release(og_server *s, uint64_t ticket) {
       s->reserved -= (r.bytes + 255) & ~(size_t)255;
     }
   }
-  if (r.ev) hipEventDestroy(r.ev);
+  if (r.ev) (void)hipEventDestroy(r.ev);
   s->reqs.erase(it);
   s->admit_locked();
   return OG_OK;
@@ -328,13 +328,13 @@ int og_server_stats(const og_server *cs, size_t *reserved, int32_t *in_flight, i
 
 int og_server_destroy(og_server *s) {
   if (!s) return OG_OK;
-  for (auto st : s->streams) hipStreamSynchronize(st);
+  for (auto st : s->streams) (void)hipStreamSynchronize(st);
   for (auto &kv : s->reqs) {
     if (kv.second.tree) og::tree_free_nosync(kv.second.tree);
-    if (kv.second.ev) hipEventDestroy(kv.second.ev);
+    if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
   }
-  for (auto st : s->streams) hipStreamDestroy(st);
-  if (s->mem) hipFree(s->mem);
+  for (auto st : s->streams) (void)hipStreamDestroy(st);
+  if (s->mem) (void)hipFree(s->mem);
   delete s;
   return OG_OK;
 }
