@@ -702,9 +702,10 @@ __global__ __launch_bounds__(kThreads) void k_wnodes(const BoxDev *boxes, int B,
     w.m = m.m;
     w.reach = bx.rcutf + 0.5f * side;
     w.near = 0.6f * side;
-    w.a = t.a;
-    w.cf = (t.b & kCountMask) | (leaf ? kWLeaf : 0u) |
-           ((bx.periodic && bx.rcutf + side >= 0.5f * bx.Lf) ? kWWrap : 0u);
+    const uint32_t count = t.b & kCountMask;
+    const bool wrap = bx.periodic && bx.rcutf + side >= 0.5f * bx.Lf;
+    w.a = leaf ? leaf_tag_bits(t.a, min(count, 8u), wrap) : t.a;
+    w.cf = count | (leaf && count > 8u ? kWBig : 0u) | (leaf ? kWLeaf : 0u) | (wrap ? kWWrap : 0u);
     wn[r] = w;
   }
 }

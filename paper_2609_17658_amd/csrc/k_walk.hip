@@ -19,6 +19,7 @@
 // successors ahead of the decision costs more vector work to select between
 // them than the load latency it hides).
 #include <cstdlib>
+#include <type_traits>
 
 #include "og_kernels.h"
 
@@ -514,14 +515,10 @@ __device__ inline int wave_max_i32(int v) {
 }
 
 // List entries (float4).  A monopole: (offset, mass), mass >= 0, already
-// known to pass the cutoff.  A leaf: (offset of the leaf centre, tag) with
-// the sign bit of the tag set, bits 0..26 the leaf's first particle, bits
-// 27..29 the number of particles minus one (at most 8 per entry) and bit 30
-// set when particle offsets may need the minimum image.
-constexpr uint32_t kTagLeaf = 0x80000000u, kTagWrap = 0x40000000u, kTagFirst = (1u << 27) - 1u;
-
+// known to pass the cutoff.  A leaf: (offset of the leaf centre, tag), the
+// tag's bits as laid out by leaf_tag_bits.
 __device__ inline float leaf_tag(uint32_t first, uint32_t n, bool wrap) {
-  return __uint_as_float(kTagLeaf | (wrap ? kTagWrap : 0u) | ((n - 1u) << 27) | first);
+  return __uint_as_float(leaf_tag_bits(first, n, wrap));
 }
 
 // Evaluate and empty every lane's list, lane-parallel: each step every lane
@@ -538,12 +535,11 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
       const float4 q = list[e][lane];
       const uint32_t tag = __float_as_uint(q.w);
       float dx = q.x, dy = q.y, dz = q.z, m = q.w;
-      float r2 = dx * dx + dy * dy + dz * dz;
-      bool use = true, particle = false;  // monopoles were counted when appended
+      float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
+      bool use = true;
       float es = 0.0f;                    // the pair's softening length (k.soft)
       if (kSoft && k.soft && !(tag & kTagLeaf)) es = lsoft[e][lane];
       if (tag & kTagLeaf) {
-        particle = true;
         const uint32_t first = tag & kTagFirst, n = ((tag >> 27) & 7u) + 1u;
         const float4 pq = A.part32[first + j];
         dx += pq.x;
@@ -555,7 +551,7 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
           dz = wrap_box(dz, k);
         }
         m = pq.w;
-        r2 = dx * dx + dy * dy + dz * dz;
+        r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         use = (first + j != p) && (!k.cutoff || r2 < k.rc2);
         if (kSoft && k.soft) {
           const float ej = (float)A.seps[first + j];
@@ -571,7 +567,7 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
       }
       if (use) {
         eval32<kExt>(dx, dy, dz, r2, m, k, ax, ay, az, ph, es);
-        ni += particle ? 1u : 0u;
+        ++ni;
       }
     }
   }
@@ -637,92 +633,147 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
       yr = (float)(q.y - (bx.lo[1] + (double)o1 * h22));
       zr = (float)(q.z - (bx.lo[2] + (double)o2 * h22));
     }
-    // Minimum image test: with g the first lane's origin and e the largest
-    // |o - g| over the group's lanes, a node centre c with |c - g| <= 2^21 - e
-    // on every axis is within half a box of every lane's origin.
-    int g0 = __builtin_amdgcn_readfirstlane(o0), g1 = __builtin_amdgcn_readfirstlane(o1),
-        g2 = __builtin_amdgcn_readfirstlane(o2);
-    int thr = 0;
+    // Offsets between a lane's origin o and a node centre c, in half-cells.
+    // Periodic box (2^22 half-cells): with g the first lane's origin and
+    // E = max |o - g| over the group's lanes, the scalar unit reduces c - g
+    // modulo 2^22 into [-2^21, 2^21) once per node, and each lane subtracts
+    // its o - g.  For the root (centre at half the box) that is c - o
+    // itself.  For every other node (at most half a box wide) it is the
+    // minimum image whenever the node is within reach of the lane, as long
+    // as r_cut + E stays below a quarter of the box; a node out of reach is
+    // pruned in either image.  Wider groups (also those that straddle the
+    // box boundary) take the minimum image per lane.
+    const int g0 = __builtin_amdgcn_readfirstlane(o0), g1 = __builtin_amdgcn_readfirstlane(o1),
+              g2 = __builtin_amdgcn_readfirstlane(o2);
+    constexpr int kHalf = 1 << 21, kMask = (1 << 22) - 1;
+    const int gq0 = g0 - kHalf, gq1 = g1 - kHalf, gq2 = g2 - kHalf;
+    // per-lane term subtracted from the reduced node centre: (o - g) + 2^21
+    const int q0 = o0 - gq0, q1 = o1 - gq1, q2 = o2 - gq2;
+    bool lane_wrap = false;
     if (kPer) {
       const int e = valid ? max(abs(o0 - g0), max(abs(o1 - g1), abs(o2 - g2))) : 0;
-      thr = (1 << 21) - wave_max_i32(e);
+      const float rc_cells = sqrtf(k.rc2) / k.h22;
+      lane_wrap = !((float)wave_max_i32(e) + rc_cells < (float)((1 << 20) - (1 << 16)));
     }
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
     uint32_t ni = 0, cnt = 0;
-    uint32_t n = bx.root;
     const uint32_t nend = bx.node_end;
-    uint32_t next = valid ? n : nend;
-    // the next node's record is read after the decision (the wave's other
-    // work and the other waves on the SIMD cover the scalar load)
-    while (n < nend) {
-      const WNode w = ldw(A.wnode + n);
-      const bool leaf = (w.cf & kWLeaf) != 0;
-      const uint32_t ns = leaf ? n + 1 : w.a;
-      const uint32_t lc = w.cf & kWCount;
-      // room for this visit's entry (a leaf of more than 8 particles makes
-      // room entry by entry below)
-      if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
-      int d0 = w.c[0] - o0, d1 = w.c[1] - o1, d2 = w.c[2] - o2;
-      if (kPer && (abs(w.c[0] - g0) > thr || abs(w.c[1] - g1) > thr || abs(w.c[2] - g2) > thr)) {
-        d0 = wrap_cells(d0);
-        d1 = wrap_cells(d1);
-        d2 = wrap_cells(d2);
-      }
-      const float dcx = (float)d0 * k.h22 - xr, dcy = (float)d1 * k.h22 - yr, dcz = (float)d2 * k.h22 - zr;
-      const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
-      const bool wrapd = kPer && (w.cf & kWWrap) != 0;
-      float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
-      if (wrapd) {
-        dx = wrap_box(dx, k);
-        dy = wrap_box(dy, k);
-        dz = wrap_box(dz, k);
-      }
-      const float r2 = dx * dx + dy * dy + dz * dz;
-      const bool act = next == n;
-      const bool live = act && !(kCut && mdc > w.reach);
-      const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
-      bool open = far_open || (mdc < w.near);
-      float emono = 0.0f;  // the monopole's softening length (k.soft)
-      if (kSoft && k.soft) {
-        const float emax = (float)*cptr(A.semax + n), emin = (float)*cptr(A.semin + n);
-        const float hm = 2.8f * emax;
-        if (emin < emax && emax > eif && r2 < hm * hm) open = true;
-        emono = eif > emax ? eif : emax;
-      }
-      const bool contrib = live && !open && (!kCut || r2 < k.rc2);
-      const bool open_here = live && open;
-      if (leaf && lc > 8u) {
-        // a leaf of more than 8 particles: an opening lane appends one entry
-        // per 8 particles, an accepting lane its monopole once
-        for (uint32_t j0 = 0; j0 < lc; j0 += 8) {
-          if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
-          if (open_here || (contrib && j0 == 0)) {
-            list[cnt][lane] = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a + j0, min(8u, lc - j0), wrapd))
-                                        : make_float4(dx, dy, dz, w.m);
-            if (kSoft) lsoft[cnt][lane] = emono;
-            ++cnt;
-          }
+    // A lane is active at node n while next <= n: an opening lane keeps its
+    // value and so stays active in the subtree; a lane that prunes or accepts
+    // n moves next to skip(n).
+    uint32_t next = valid ? bx.root : nend;
+    auto walk = [&](auto lane_wrap_t) {
+      constexpr bool kLaneWrap = decltype(lane_wrap_t)::value;
+      // A leaf of more than 8 particles takes one list entry per 8 of its
+      // particles: the wave stays on it (pend = the next particle offset)
+      // until the lanes that opened it (bigopen) have appended every entry.
+      uint32_t pend = 0, bigopen = 0;
+      // the next node's record is read after the decision (the wave's other
+      // work and the other waves on the SIMD cover the scalar load)
+      for (uint32_t n = bx.root; n < nend;) {
+        const WNode w = ldw(A.wnode + n);
+        const uint32_t cf = w.cf;
+        // room for this visit's entry
+        if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
+        int d0, d1, d2;
+        if (kPer && !kLaneWrap) {
+          d0 = ((w.c[0] - gq0) & kMask) - q0;
+          d1 = ((w.c[1] - gq1) & kMask) - q1;
+          d2 = ((w.c[2] - gq2) & kMask) - q2;
+        } else if (kPer) {
+          d0 = wrap_cells(w.c[0] - o0);
+          d1 = wrap_cells(w.c[1] - o1);
+          d2 = wrap_cells(w.c[2] - o2);
+        } else {
+          d0 = w.c[0] - o0;
+          d1 = w.c[1] - o1;
+          d2 = w.c[2] - o2;
         }
-        ni += contrib ? 1u : 0u;
-      } else {
-        // one entry: the monopole, or the opened leaf
-        const float4 entry = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a, lc, wrapd))
+        const float dcx = (float)d0 * k.h22 - xr, dcy = (float)d1 * k.h22 - yr, dcz = (float)d2 * k.h22 - zr;
+        const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
+        const uint32_t ns = (cf & kWLeaf) ? n + 1 : w.a;
+        // the rare cases (a big leaf, offsets that may need the minimum
+        // image) take the general path; the common visit below has no
+        // branch of its own
+        if (pend | (cf & (kWBig | (kPer ? kWWrap : 0u)))) {
+          const uint32_t lc = cf & kWCount;
+          const bool wrapd = kPer && (cf & kWWrap) != 0;
+          if (pend) {
+            if (bigopen) {
+              list[cnt][lane] = make_float4(dcx, dcy, dcz, leaf_tag((w.a & kTagFirst) + pend, min(8u, lc - pend), wrapd));
+              ++cnt;
+            }
+            pend += 8;
+            if (pend >= lc) {
+              pend = 0;
+              ++n;
+            }
+            continue;
+          }
+          float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
+          if (wrapd) {
+            dx = wrap_box(dx, k);
+            dy = wrap_box(dy, k);
+            dz = wrap_box(dz, k);
+          }
+          const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
+          const bool act = next <= n;
+          const bool live = act && !(kCut && mdc > w.reach);
+          const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
+          bool open = far_open || (mdc < w.near);
+          float emono = 0.0f;
+          if (kSoft && k.soft) {
+            const float emax = (float)*cptr(A.semax + n), emin = (float)*cptr(A.semin + n);
+            const float hm = 2.8f * emax;
+            if (emin < emax && emax > eif && r2 < hm * hm) open = true;
+            emono = eif > emax ? eif : emax;
+          }
+          const bool contrib = live && !open && (!kCut || r2 < k.rc2);
+          const bool open_here = live && open;
+          list[cnt][lane] = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a & kTagFirst, min(8u, lc), wrapd))
+                                      : make_float4(dx, dy, dz, w.m);
+          if (kSoft) lsoft[cnt][lane] = emono;
+          cnt += contrib ? 1u : (open_here ? (cf >> 30) & 1u : 0u);
+          if (act && !open_here) next = ns;
+          const bool opened = __ballot(open_here) != 0;
+          if ((cf & kWBig) && opened) {
+            pend = 8;
+            bigopen = open_here ? 1u : 0u;
+          } else {
+            n = opened ? n + 1 : max(ns, n + 1);
+          }
+          continue;
+        }
+        const float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
+        const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
+        const bool act = next <= n;
+        const bool live = act && !(kCut && mdc > w.reach);
+        const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
+        bool open = far_open || (mdc < w.near);
+        float emono = 0.0f;  // the monopole's softening length (k.soft)
+        if (kSoft && k.soft) {
+          const float emax = (float)*cptr(A.semax + n), emin = (float)*cptr(A.semin + n);
+          const float hm = 2.8f * emax;
+          if (emin < emax && emax > eif && r2 < hm * hm) open = true;
+          emono = eif > emax ? eif : emax;
+        }
+        const bool contrib = live && !open && (!kCut || r2 < k.rc2);
+        const bool open_here = live && open;
+        // one entry: the accepted monopole or, at a leaf, the opened leaf.
+        // Every lane writes its next slot; only a real entry advances it.
+        const float4 entry = open_here ? make_float4(dcx, dcy, dcz, __uint_as_float(w.a))
                                        : make_float4(dx, dy, dz, w.m);
         list[cnt][lane] = entry;
         if (kSoft) lsoft[cnt][lane] = emono;
-        const bool add = contrib || (leaf && open_here);
-        cnt += add ? 1u : 0u;
-        ni += contrib ? 1u : 0u;
+        cnt += contrib ? 1u : (open_here ? (cf >> 30) & 1u : 0u);
+        if (act && !open_here) next = ns;
+        // the lanes that opened n are those still at or before n; a leaf's
+        // skip is n + 1; a skip always moves forward
+        n = __ballot(next <= n) ? n + 1 : max(ns, n + 1);
       }
-      next = act ? (open_here ? n + 1 : ns) : next;
-      uint32_t nn;
-      if (leaf) {
-        nn = n + 1;
-      } else {
-        nn = (__ballot(open_here) || ns <= n) ? n + 1 : ns;
-      }
-      n = nn;
-    }
+    };
+    if (kPer && lane_wrap) walk(std::true_type{});
+    else walk(std::false_type{});
     flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
@@ -988,7 +1039,7 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walkg32(WalkArgs A) {
             const uint32_t m = min(64u, lc - j0);
             if (cnt + m > kGroupCap) flush();
             if (lane < m) {
-              const uint32_t j = w.a + j0 + lane;
+              const uint32_t j = (w.a & kTagFirst) + j0 + lane;
               const float4 pq = A.part32[j];
               GEntry q;
               q.c[0] = w.c[0];

@@ -70,10 +70,21 @@ struct __attribute__((aligned(16))) Mom32 {
 //   c[3]:   cube centre in half-cells of the level-21 grid (exact integers)
 //   side2:  side^2;  reach: r_cut + side/2;  near: 0.6 side
 //   o[3]:   centre of mass minus cube centre;  m: mass
-//   a:      leaf ? first particle : skip (the next node after the subtree)
-//   cf:     particle count | kWLeaf | kWWrap (offsets inside the node may
-//           need the minimum image)
-constexpr uint32_t kWLeaf = 1u << 30, kWWrap = 1u << 31, kWCount = (1u << 30) - 1u;
+//   a:      internal node: skip (the next node after the subtree);
+//           leaf: its interaction-list tag (below), whose low bits hold
+//           the leaf's first particle
+//   cf:     particle count | kWBig (a leaf of more than 8 particles) |
+//           kWLeaf | kWWrap (offsets inside the node may need the minimum
+//           image)
+constexpr uint32_t kWBig = 1u << 29, kWLeaf = 1u << 30, kWWrap = 1u << 31, kWCount = kCountMask;
+// Leaf tag, as stored in interaction lists (the float bits of the entry's
+// fourth component): sign bit set, bits 0..26 the first particle, bits
+// 27..29 the number of particles minus one (at most 8 per entry), bit 30
+// set when particle offsets may need the minimum image.
+constexpr uint32_t kTagLeaf = 0x80000000u, kTagWrap = 0x40000000u, kTagFirst = (1u << 27) - 1u;
+__host__ __device__ inline uint32_t leaf_tag_bits(uint32_t first, uint32_t n, bool wrap) {
+  return kTagLeaf | (wrap ? kTagWrap : 0u) | ((n - 1u) << 27) | first;
+}
 struct __attribute__((aligned(16))) WNode {
   int32_t c[3];
   float side2;

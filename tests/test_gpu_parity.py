@@ -287,3 +287,33 @@ def test_full_size_mixture2m_sampled(og_mod, oracle_mod, theta):
             assert np.median(e) <= 1e-3 and np.percentile(e, 99) <= 1e-2
     assert tree.status() == 0
     tree.close()
+
+
+def test_mixed_walk_groups_across_the_periodic_boundary(og_mod, oracle_mod):
+    """Every target of the walk groups (64 consecutive particles in curve
+    order) whose members lie on both sides of a periodic face, N = 128^3
+    mixture (r_cut = 0.022 of the box): such groups need the minimum image
+    per lane, which a group-wide reference cannot give them.  Worst target
+    within the p99 bound of the mixed form."""
+    w = synth.mixture2m()
+    _note("mixture2m: groups across the periodic boundary")
+    tp, tm = _dev(w.pos), _dev(w.mass)
+    tree = og_mod.Tree(tp, tm, 1.0, w.params, stream=torch.cuda.current_stream())
+    perm = tree.export()["perm"].astype(np.int64)
+    n_full = (perm.shape[0] // 64) * 64
+    groups = perm[:n_full].reshape(-1, 64)
+    xs = w.pos[groups]
+    wide = (xs.max(axis=1) - xs.min(axis=1) > 0.5).any(axis=1)
+    tg = np.sort(groups[wide].ravel())
+    _note("  %d groups, %d targets" % (int(wide.sum()), tg.shape[0]))
+    assert tg.shape[0] >= 64
+    a, p, n = tree.force(precision="mixed", with_counts=True)
+    torch.cuda.synchronize()
+    assert tree.status() == 0
+    tree.close()
+    op = oracle_params(oracle_mod, w.params)
+    ot = oracle_mod.build_tree(w.pos, w.mass, 1.0, op)
+    acc, pot, nint = oracle_mod.walk(ot, targets=tg)
+    e = rel_err(a.cpu().numpy()[tg], acc)
+    _note("  median %.3g max %.3g" % (np.median(e), e.max()))
+    assert e.max() <= 1e-2
