@@ -481,7 +481,8 @@ __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, c
   }
   float S = 1.0f, pf = 1.0f;
   if (k.cutoff) {
-    const float r = r2 > 0.0f ? r2 * __builtin_amdgcn_rsqf(r2) : 0.0f;
+    // r2 = 0 (coincident partners) gives r = 0
+    const float r = r2 * __builtin_amdgcn_rsqf(r2 + 0x1p-126f);
     const float u = r * k.inv2rs;
     const float e = __expf(-u * u);
     const float t = __builtin_amdgcn_rcpf(1.0f + kAsP * u);
@@ -490,10 +491,10 @@ __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, c
     pf = ec;
   }
   const float gm = k.G * m;
-  const float f = gm * g * S;
-  ax += (double)(f * dx);
-  ay += (double)(f * dy);
-  az += (double)(f * dz);
+  const double f = (double)(gm * g * S);
+  ax = fma(f, (double)dx, ax);
+  ay = fma(f, (double)dy, ay);
+  az = fma(f, (double)dz, az);
   ph -= (double)(gm * wv * pf);
 }
 
