@@ -235,6 +235,35 @@ __device__ inline void spline64(double r, double h, double &g, double &w) {
   }
 }
 
+// erfc(u) = exp(-u^2) erfcx(u).  erfcx on 0 <= u <= 3 (r < 6 r_s) is a
+// polynomial of degree 25 in t = 2u/3 - 1 (coefficients from
+// gen_erfcx64.py, relative error below 1e-15), so the pair term needs one
+// exponential; larger u falls back to the library erfc.
+__constant__ double kErfcx64[26] = {
+    -1.9285526545026629e-09, 5.7920154915414246e-09, -4.6119752723685525e-09,
+    1.2374418534053267e-08, -6.8302916092557606e-08, 1.8960282584894505e-07,
+    -4.5725982227457081e-07, 1.2076614734008636e-06, -3.1901620317342984e-06,
+    8.1102004120020287e-06, -2.0126549072150048e-05, 4.8905112127983934e-05,
+    -0.00011601010087456714, 0.00026818449435352847, -0.00060331955090763077,
+    0.0013184708553075387, -0.0027932530866193999, 0.0057231897175237054,
+    -0.011309695741544485, 0.021484255075844793, -0.039077115130126794,
+    0.06772278857525682, -0.11114180538602185, 0.17133983967481778,
+    -0.2454343765988401, 0.32158541645431754,
+};
+__device__ inline double erfcx64(double u) {
+  // The coefficients are read with scalar loads at each use: kept in
+  // registers across the walk they would cost 52 of them and halve the
+  // number of resident waves.
+  const double *c = kErfcx64;
+  asm volatile("" : "+s"(c));
+  const auto q = cptr(c);
+  const double t = fma(u, 2.0 / 3.0, -1.0);
+  double y = q[0];
+#pragma unroll
+  for (int i = 1; i < 26; ++i) y = fma(y, t, q[i]);
+  return y;
+}
+
 // e: the pair's softening length (used by the kExt variants; the others
 // take the box's).
 template <bool kExt>
@@ -255,8 +284,9 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, double 
   if (bx.cutoff) {
     const double r = sqrt(r2);
     const double u = r / (2.0 * bx.r_s);
-    const double e = erfc(u);
-    S = e + kTwoOverSqrtPi * u * exp(-u * u);
+    const double eu = exp(-u * u);
+    const double e = u <= 3.0 ? eu * erfcx64(u) : erfc(u);
+    S = e + kTwoOverSqrtPi * u * eu;
     pf = e;
   }
   const double f = bx.G * m * g * S;
@@ -269,12 +299,73 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, double 
 
 // Plain FP64 walk: every quantity in double precision, with the same
 // expressions (and no contraction) as a direct reading of the walk rules.
+// The decisions are taken at the node; an accepted monopole (FP64 offset and
+// mass) or an opened leaf (its particle range) goes to the lane's own list
+// in LDS, and the lists are evaluated lane-parallel when one is full and at
+// the end of the walk.  Each target still sums its partners in traversal
+// order, but the costly FP64 pair terms run with the lanes of many nodes at
+// once instead of only the lanes that accepted or opened the current node.
 // kExt: the spline softening and the relative criterion are read from each
 // box.
+constexpr int kWalk64Waves = 4;  // waves per workgroup
+constexpr int kWalk64Cap = 4;    // list entries per lane
+
+// Evaluate and empty every lane's list.  A monopole entry is (offset, mass),
+// mass >= 0; a leaf entry has w = -1 and, in the bits of x, its first
+// particle (bits 0..31), count (32..62) and whether its particles' offsets
+// need the minimum image (bit 63).
 template <bool kExt>
-__global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
+__device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*lsoft)[64], uint32_t lane,
+                               uint32_t p, const double4 &xi, double ei, bool soft, const BoxDev &bx,
+                               uint32_t &cnt, double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(off)
-  const uint32_t lane = threadIdx.x & 63;
+  uint32_t e = 0, j = 0;
+  while (__ballot(e < cnt)) {
+    if (e < cnt) {
+      const double4 q = list[e][lane];
+      // the partner: the monopole itself, or the leaf's j-th particle
+      double dx = q.x, dy = q.y, dz = q.z, m = q.w, es = bx.eps;
+      bool use = true;
+      if (q.w >= 0.0) {
+        if (soft) es = lsoft[e][lane];
+        ++e;
+      } else {
+        const uint64_t bits = (uint64_t)__double_as_longlong(q.x);
+        const uint32_t first = (uint32_t)bits, count = (uint32_t)(bits >> 32) & 0x7fffffffu;
+        const bool wrap = (bits >> 63) != 0;
+        const uint32_t i = first + j;
+        use = i != p;
+        const double4 s = A.part64[i];
+        dx = minimg(s.x - xi.x, wrap, bx.box);
+        dy = minimg(s.y - xi.y, wrap, bx.box);
+        dz = minimg(s.z - xi.z, wrap, bx.box);
+        m = s.w;
+        if (soft) {
+          const double ej = A.seps[i];
+          es = ei > ej ? ei : ej;
+        }
+        if (++j == count) {
+          j = 0;
+          ++e;
+        }
+      }
+      // one evaluation site, shared by both kinds of partner
+      if (use) pair64<kExt>(dx, dy, dz, m, es, bx, ax, ay, az, ph, ni);
+    }
+  }
+  cnt = 0;
+}
+
+// Four waves per SIMD (a few registers spill to scratch) run faster than
+// the three the registers would otherwise allow.
+template <bool kExt>
+__global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk64(WalkArgs A) {
+#pragma clang fp contract(off)
+  __shared__ double4 lists[kWalk64Waves][kWalk64Cap][64];
+  __shared__ double lsofts[kExt ? kWalk64Waves : 1][kExt ? kWalk64Cap : 1][64];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double4(*list)[64] = lists[wv];
+  double(*lsoft)[64] = lsofts[kExt ? wv : 0];
   device_counts(A);
   GroupQueue Q = make_queue(A);
   while (true) {
@@ -297,27 +388,45 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
     const double ei = soft && valid ? A.seps[p] : bx.eps;
     const bool periodic = bx.periodic;
     const double box = bx.box, h = bx.L * 0x1p-21;
+    // A group whose targets all lie farther than r_cut from every face of
+    // the periodic box (r_cut below a quarter of the box) needs no minimum
+    // image below level 1: a node of side <= box/4 within reach of such a
+    // target is within half a box of it, and so are its centre of mass and
+    // particles, while any other node is pruned in either image.  The
+    // offsets, and so every decision and term, are those of the minimum
+    // image.
+    bool interior = false;
+    if (periodic) {
+      const double m = bx.rcut + 0x1p-40 * box;
+      const bool inside = !valid || (xi.x >= m && xi.x <= box - m && xi.y >= m && xi.y <= box - m &&
+                                     xi.z >= m && xi.z <= box - m);
+      interior = bx.rcut <= 0.24 * box && __ballot(!inside) == 0;
+    }
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
-    uint32_t ni = 0;
+    uint32_t ni = 0, cnt = 0;
     uint32_t n = bx.root;
     const uint32_t nend = bx.node_end;
     uint32_t next = valid ? n : nend;
     while (n < nend) {
+      // room for this visit's entry
+      if (__ballot(cnt >= (uint32_t)kWalk64Cap))
+        flush64<kExt>(A, list, lsoft, lane, p, xi, ei, soft, bx, cnt, ax, ay, az, ph, ni);
       const Topo t = ld(A.topo + n);
       const Mom64 mm = ld(A.mom64 + n);
       const bool leaf = (t.corner & kLeafBit) != 0;
       const uint32_t ns = leaf ? n + 1 : t.a;
       const int lev = (int)(t.b >> kCountBits);
+      const bool wrap = periodic && !(interior && lev >= 2);
       const double side = ldexp(bx.L, -lev);
       const double half = ldexp(1.0, 20 - lev);
       const double c0 = bx.lo[0] + ((double)(uint32_t)(t.corner & 0x1fffffull) + half) * h;
       const double c1 = bx.lo[1] + ((double)(uint32_t)((t.corner >> 21) & 0x1fffffull) + half) * h;
       const double c2 = bx.lo[2] + ((double)(uint32_t)((t.corner >> 42) & 0x1fffffull) + half) * h;
-      bool open_int = false, open_leaf = false;
+      bool open_int = false;
       if (next == n) {
-        const double dcx = minimg(c0 - xi.x, periodic, box);
-        const double dcy = minimg(c1 - xi.y, periodic, box);
-        const double dcz = minimg(c2 - xi.z, periodic, box);
+        const double dcx = minimg(c0 - xi.x, wrap, box);
+        const double dcy = minimg(c1 - xi.y, wrap, box);
+        const double dcz = minimg(c2 - xi.z, wrap, box);
         bool pruned = false;
         if (bx.cutoff) {
           const double reach = bx.rcut + 0.5 * side;
@@ -326,9 +435,9 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
         if (pruned) {
           next = ns;
         } else {
-          const double dx = minimg(mm.cx - xi.x, periodic, box);
-          const double dy = minimg(mm.cy - xi.y, periodic, box);
-          const double dz = minimg(mm.cz - xi.z, periodic, box);
+          const double dx = minimg(mm.cx - xi.x, wrap, box);
+          const double dy = minimg(mm.cy - xi.y, wrap, box);
+          const double dz = minimg(mm.cz - xi.z, wrap, box);
           const double r2 = dx * dx + dy * dy + dz * dz;
           const double near = 0.6 * side;
           const bool far_open = relative ? (bx.G * mm.m * side * side > bx.alpha * aold * r2 * r2)
@@ -345,47 +454,28 @@ __global__ __launch_bounds__(256) void k_walk64(WalkArgs A) {
             e = ei > emax ? ei : emax;
           }
           if (!open) {
-            pair64<kExt>(dx, dy, dz, mm.m, e, bx, ax, ay, az, ph, ni);
+            // the monopole, if within the cutoff (the test the pair term makes)
+            if (!bx.cutoff || r2 < bx.rc2) {
+              list[cnt][lane] = make_double4(dx, dy, dz, mm.m);
+              if (kExt) lsoft[cnt][lane] = e;
+              ++cnt;
+            }
             next = ns;
           } else if (!leaf) {
             open_int = true;
             next = n + 1;
           } else {
-            open_leaf = true;
+            const uint64_t range = (uint64_t)t.a | ((uint64_t)(t.b & kCountMask) << 32) | ((uint64_t)wrap << 63);
+            list[cnt][lane] = make_double4(__longlong_as_double((long long)range), 0.0, 0.0, -1.0);
+            ++cnt;
             next = n + 1;
           }
         }
       }
-      uint32_t nn;
-      if (leaf) {
-        if (__ballot(open_leaf)) {
-          const uint32_t f = t.a, cnt = t.b & kCountMask;
-          for (uint32_t base = 0; base < cnt; base += 64) {
-            double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
-            double qe = bx.eps;
-            if (base + lane < cnt) {
-              q = A.part64[f + base + lane];
-              if (soft) qe = A.seps[f + base + lane];
-            }
-            const uint32_t m = min(64u, cnt - base);
-            for (uint32_t j = 0; j < m; ++j) {
-              const double qx = rdl(q.x, j), qy = rdl(q.y, j), qz = rdl(q.z, j), qm = rdl(q.w, j);
-              const double ej = soft ? rdl(qe, j) : bx.eps;
-              if (open_leaf && f + base + j != p) {
-                const double dx = minimg(qx - xi.x, periodic, box);
-                const double dy = minimg(qy - xi.y, periodic, box);
-                const double dz = minimg(qz - xi.z, periodic, box);
-                pair64<kExt>(dx, dy, dz, qm, soft ? (ei > ej ? ei : ej) : bx.eps, bx, ax, ay, az, ph, ni);
-              }
-            }
-          }
-        }
-        nn = n + 1;
-      } else {
-        nn = (__ballot(open_int) || t.a <= n) ? n + 1 : t.a;
-      }
-      n = nn;
+      // a leaf's skip is n + 1; a skip always moves forward
+      n = (leaf || __ballot(open_int) || t.a <= n) ? n + 1 : t.a;
     }
+    flush64<kExt>(A, list, lsoft, lane, p, xi, ei, soft, bx, cnt, ax, ay, az, ph, ni);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
@@ -1099,10 +1189,10 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
     return;
   }
   if (precision == 0) {
-    // 4 waves per workgroup; this kernel's registers allow 3 waves per SIMD
-    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(3u * cus, (groups + 3) / 4));
-    if (W.ext) k_walk64<true><<<blocks, 256, 0, s>>>(W);
-    else k_walk64<false><<<blocks, 256, 0, s>>>(W);
+    // 4 waves per workgroup, 4 waves per SIMD
+    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(4u * cus, (groups + 3) / 4));
+    if (W.ext) k_walk64<true><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
+    else k_walk64<false><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
   } else {
     // one wave per workgroup; LDS per wave = cap x 1 KB of lists
     const int cap = W.list_cap > 0 ? W.list_cap : walk_list_capacity();
