@@ -47,9 +47,11 @@ def build_bytes(n, n_nodes, n_groups_bound=None):
     return per_particle * n + per_node * n_nodes
 
 
-def walk_traffic_bytes():
-    """HBM bytes per walk launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
-    scaled by a 1 GiB copy), valid only while the walk source is unchanged."""
+def walk_profile():
+    """The walk's rocprofv3 record (profiles/k_walk32_mixture2m_traffic.txt):
+    HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy) and
+    vector / scalar instruction counts per launch; empty once the walk source
+    differs from the profiled one."""
     import hashlib
     try:
         rec = {}
@@ -61,10 +63,30 @@ def walk_traffic_bytes():
         with open(os.path.join(ROOT, "paper_2609_17658_amd", "csrc", "k_walk.hip"), "rb") as f:
             h = hashlib.sha256(f.read()).hexdigest()
         if rec.get("source_sha256") != h:
-            return None
-        return float(rec["walk_traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+            return {}
+        return rec
+    except OSError:
+        return {}
+
+
+def walk_traffic_bytes():
+    try:
+        return float(walk_profile()["walk_traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
         return None
+
+
+def walk_issue(walk_ms):
+    """Vector issue of the walk: a wave64 VALU instruction holds a 16-lane SIMD
+    for 4 cycles; 1024 SIMDs at 2.4 GHz.  From the profiled instruction count
+    and this run's walk time."""
+    try:
+        valu = float(walk_profile()["walk_valu_insts_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    busy = valu * 4 / (1024 * walk_ms * 1e-3 * 2.4e9)
+    return {"valu_insts_per_launch": valu, "valu_busy_frac": busy,
+            "note": "SIMD cycles issuing vector instructions / all SIMD cycles of the launch"}
 
 
 def git_hash():
@@ -226,6 +248,7 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
             "peak_unpacked_fp32": 78.6,
             "flop_per_interaction": FLOP_PER_INTERACTION, "interactions": inter_m,
+            "issue": walk_issue(walk_ms),
         },
         "roofline_build": {
             "bound": "hbm", "achieved": build_gbs / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
