@@ -588,6 +588,9 @@ __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, c
   ph -= (double)(gm * wv * pf);
 }
 
+// 2^23 + a as a float, exactly, for 0 <= a < 2^23.
+__device__ inline float biased(int a) { return __int_as_float(0x4B000000 | a); }
+
 __device__ inline int wrap_cells(int d) {
   // the periodic box is 2^22 half-cells long
   const int hi = d > (1 << 21) ? d - (1 << 22) : d;
@@ -670,7 +673,11 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
 // kExt: the spline softening and the relative criterion are read from each
 // box (only with kMode 0); kSoft (with kExt): per-particle softening lengths.
 template <int kCap, int kMode, bool kExt, bool kSoft = false>
-__global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
+// The plain variants with 4-deep lists fit 8 waves per SIMD (64 vector and
+// at most 96 scalar registers), which hides more latency than the 7 that
+// the scalar registers would otherwise allow.
+__global__ __launch_bounds__(kWalk32Threads)
+__attribute__((amdgpu_waves_per_eu(kCap == 4 && !kExt ? 8 : 1, 8))) void k_walk32(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ float4 list[kCap][kWalk32Threads];
   __shared__ float lsoft[kSoft ? kCap : 1][kWalk32Threads];  // monopoles' softening lengths
@@ -740,6 +747,11 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
     const int gq0 = g0 - kHalf, gq1 = g1 - kHalf, gq2 = g2 - kHalf;
     // per-lane term subtracted from the reduced node centre: (o - g) + 2^21
     const int q0 = o0 - gq0, q1 = o1 - gq1, q2 = o2 - gq2;
+    // Offsets in half-cells become floats exactly without a per-lane
+    // conversion: for 0 <= a, b < 2^23 the float with bit pattern
+    // 0x4B000000 | a is 2^23 + a, and (2^23 + a) - (2^23 + b) = a - b
+    // exactly.  The node's term is a scalar OR, the lane's is fixed.
+    const float qb0 = biased(kPer ? q0 : o0), qb1 = biased(kPer ? q1 : o1), qb2 = biased(kPer ? q2 : o2);
     bool lane_wrap = false;
     if (kPer) {
       const int e = valid ? max(abs(o0 - g0), max(abs(o1 - g1), abs(o2 - g2))) : 0;
@@ -766,21 +778,21 @@ __global__ __launch_bounds__(kWalk32Threads) void k_walk32(WalkArgs A) {
         const uint32_t cf = w.cf;
         // room for this visit's entry
         if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
-        int d0, d1, d2;
+        float f0, f1, f2;  // node centre minus lane origin, in half-cells (exact)
         if (kPer && !kLaneWrap) {
-          d0 = ((w.c[0] - gq0) & kMask) - q0;
-          d1 = ((w.c[1] - gq1) & kMask) - q1;
-          d2 = ((w.c[2] - gq2) & kMask) - q2;
+          f0 = biased((w.c[0] - gq0) & kMask) - qb0;
+          f1 = biased((w.c[1] - gq1) & kMask) - qb1;
+          f2 = biased((w.c[2] - gq2) & kMask) - qb2;
         } else if (kPer) {
-          d0 = wrap_cells(w.c[0] - o0);
-          d1 = wrap_cells(w.c[1] - o1);
-          d2 = wrap_cells(w.c[2] - o2);
+          f0 = (float)wrap_cells(w.c[0] - o0);
+          f1 = (float)wrap_cells(w.c[1] - o1);
+          f2 = (float)wrap_cells(w.c[2] - o2);
         } else {
-          d0 = w.c[0] - o0;
-          d1 = w.c[1] - o1;
-          d2 = w.c[2] - o2;
+          f0 = biased(w.c[0]) - qb0;
+          f1 = biased(w.c[1]) - qb1;
+          f2 = biased(w.c[2]) - qb2;
         }
-        const float dcx = (float)d0 * k.h22 - xr, dcy = (float)d1 * k.h22 - yr, dcz = (float)d2 * k.h22 - zr;
+        const float dcx = f0 * k.h22 - xr, dcy = f1 * k.h22 - yr, dcz = f2 * k.h22 - zr;
         const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
         const uint32_t ns = (cf & kWLeaf) ? n + 1 : w.a;
         // the rare cases (a big leaf, offsets that may need the minimum
