@@ -96,6 +96,11 @@ def _cases():
     pos[500:1000, 1] = np.nextafter(3.0, 0.0)
     cases.append(("box3_faces", pos, np.full(6000, 1 / 6000), 3.0,
                   dict(G=1.0, eps=0.002, r_s=0.05, r_cut=0.25, theta=0.7, periodic=1, leaf_max=8)))
+    # cutoff at 8 r_s: pair terms with u = r/(2 r_s) up to 4, past the range
+    # of the FP64 walk's erfcx polynomial (u <= 3)
+    pos = synth.wrap(np.concatenate([rng.random((2500, 3)), 0.6 + 0.03 * rng.standard_normal((2500, 3))]))
+    cases.append(("rcut8rs5000", pos, np.full(5000, 1 / 5000), 1.0,
+                  dict(G=1.0, eps=0.001, r_s=0.02, r_cut=0.16, theta=0.5, periodic=1, leaf_max=8)))
     return cases
 
 
