@@ -999,10 +999,12 @@ struct __attribute__((aligned(16))) GEntry {
   float m;
 };
 constexpr uint32_t kGWrap = 0x80000000u, kGNoSelf = 0x7fffffffu;
-constexpr uint32_t kGroupCap = 256;
+constexpr uint32_t kGroupCap = 128;
 
+// 128 entries (4 KB of LDS per wave) leave room for 8 waves per SIMD, which
+// pays for the extra flushes.
 template <int kMode, bool kExt>
-__global__ __launch_bounds__(kWalk32Threads) void k_walkg32(WalkArgs A) {
+__global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kExt ? 1 : 8, 8))) void k_walkg32(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ GEntry list[kGroupCap];
   const uint32_t lane = threadIdx.x;
@@ -1189,8 +1191,8 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
       if (W.ext) k_walkg64<true><<<blocks, 256, 0, s>>>(W);
       else k_walkg64<false><<<blocks, 256, 0, s>>>(W);
     } else {
-      // one wave per workgroup, 8 KB of list each
-      const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(16u * cus, groups));
+      // one wave per workgroup, 4 KB of list each, 8 waves per SIMD
+      const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(32u * cus, groups));
       const int mode = W.box_kind;
       if (W.ext) k_walkg32<0, true><<<blocks, kWalk32Threads, 0, s>>>(W);
       else if (mode == 2) k_walkg32<2, false><<<blocks, kWalk32Threads, 0, s>>>(W);
