@@ -673,11 +673,11 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
 // kExt: the spline softening and the relative criterion are read from each
 // box (only with kMode 0); kSoft (with kExt): per-particle softening lengths.
 template <int kCap, int kMode, bool kExt, bool kSoft = false>
-// The plain variants with 4-deep lists fit 8 waves per SIMD (64 vector and
-// at most 96 scalar registers), which hides more latency than the 7 that
-// the scalar registers would otherwise allow.
+// With 4-deep lists every variant fits 8 waves per SIMD (64 vector and at
+// most 96 scalar registers, no spills), which hides more latency than the
+// 7 that the scalar registers would otherwise allow.
 __global__ __launch_bounds__(kWalk32Threads)
-__attribute__((amdgpu_waves_per_eu(kCap == 4 && !kExt ? 8 : 1, 8))) void k_walk32(WalkArgs A) {
+__attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ float4 list[kCap][kWalk32Threads];
   __shared__ float lsoft[kSoft ? kCap : 1][kWalk32Threads];  // monopoles' softening lengths
