@@ -86,7 +86,8 @@ def walk_issue(walk_ms):
         return None
     busy = valu * 4 / (1024 * walk_ms * 1e-3 * 2.4e9)
     return {"valu_insts_per_launch": valu, "valu_busy_frac": busy,
-            "note": "SIMD cycles issuing vector instructions / all SIMD cycles of the launch"}
+            "note": "vector instructions x 4 cycles / SIMD cycles of the launch; 1 = vector issue saturated "
+                    "(an estimate: it assumes every wave64 vector instruction holds its SIMD for 4 cycles)"}
 
 
 def git_hash():
