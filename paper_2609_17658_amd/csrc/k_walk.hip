@@ -484,21 +484,22 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
 // Every lane works in FP32 offsets from its own origin, the centre of the
 // level-21 cell holding its target.  Cell indices (in half-cells, < 2^23)
 // are exact, so a node centre relative to a lane's origin is one exact
-// integer difference times the half-cell size; the periodic minimum image is
-// applied to that exact difference, and skipped for a node when a scalar
-// test shows that no lane of the group can need it.  A node's centre of
-// mass is its centre plus the node's FP32 offset, a particle is its leaf's
-// centre plus its FP32 offset (both offsets formed in FP64 at build time),
-// and the target is FP64 (x - origin) rounded once.  Node data comes from
-// 64-byte walk records (one scalar load each).
+// integer difference times the half-cell size; in a periodic box that
+// difference is the minimum image (reduced once per node on the scalar unit
+// for compact groups, per lane otherwise).  A node's centre of mass is its
+// centre plus the node's FP32 offset, a particle is its leaf's centre plus
+// its FP32 offset (both offsets formed in FP64 at build time), and the
+// target is FP64 (x - origin) rounded once.  Node data comes from 48-byte
+// walk records read with scalar loads.
 //
 // Accepted partners are not evaluated at the node: each lane appends
 // (offset, mass) to its own list in LDS, in traversal order, and the lists
 // are evaluated lane-parallel when one of them is full and at the end of
 // the walk.  The per-target summation order is thus the traversal order,
 // and a lane evaluates only its own partners, so the interaction arithmetic
-// runs with (nearly) all lanes busy even though the lanes' decisions at a
-// node differ.  The per-lane decisions are computed without branches.
+// runs with the lanes of many nodes at once even though the lanes'
+// decisions at a node differ.  The per-lane decisions are computed without
+// branches.
 constexpr int kWalk32Threads = 64;       // one wavefront per workgroup
 
 struct Consts32 {
