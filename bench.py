@@ -152,8 +152,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(each box is independent; see the sharding notes in the design document).",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent boxes would be spread over GPUs; one large box would be split "
+              "into curve segments with a one-step ghost exchange).",
               file=sys.stderr)
         sys.exit(2)
 
