@@ -58,7 +58,7 @@ enum {
     OG_ENOMEM = -3,       /* device allocation failed or workspace too small */
     OG_EDEVICE = -4,      /* a HIP runtime error */
     OG_EBUSY = -5,        /* server: over budget and queue full */
-    OG_EUNSUPPORTED = -6, /* valid request this build does not handle */
+    OG_EUNSUPPORTED = -6, /* valid request the library does not handle */
     OG_ENOTFOUND = -7     /* server: unknown ticket */
 };
 
