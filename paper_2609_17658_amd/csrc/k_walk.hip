@@ -276,14 +276,14 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, double 
   if (kExt && bx.spline) {
     spline64(sqrt(r2), 2.8 * e, g, w);
   } else {
-    const double rinv = 1.0 / sqrt(r2 + (kExt ? e * e : bx.eps2));
+    const double rinv = rsqrt(r2 + (kExt ? e * e : bx.eps2));  // within an ulp or two of 1/sqrt
     g = rinv * rinv * rinv;
     w = rinv;
   }
   double S = 1.0, pf = 1.0;
   if (bx.cutoff) {
     const double r = sqrt(r2);
-    const double u = r / (2.0 * bx.r_s);
+    const double u = r * (0.5 / bx.r_s);
     const double eu = exp(-u * u);
     const double e = u <= 3.0 ? eu * erfcx64(u) : erfc(u);
     S = e + kTwoOverSqrtPi * u * eu;
