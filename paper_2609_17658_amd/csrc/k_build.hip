@@ -234,7 +234,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint64_t *keys, co
 #pragma unroll 4
   for (int r = 0; r < kSortItems; ++r) {
     uint32_t e = base + r * kThreads + threadIdx.x;
-    if (e < n) atomicAdd(&h[sort_digit(keys[e], vals[e], pass, boxes, B)], 1u);
+    // the key passes need no value
+    if (e < n) atomicAdd(&h[sort_digit(keys[e], pass < 8 ? 0u : vals[e], pass, boxes, B)], 1u);
   }
   __syncthreads();
   hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
