@@ -253,17 +253,40 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *data, int n, 
     buf[t * n + jr] = data[addr(t, j)];
   }
   __syncthreads();
-  for (int s = 1; s <= logn; ++s) {
-    const int half = 1 << (s - 1), len = half << 1, step = n >> s;
+  int s = 1;
+  if (logn & 1) {
+    // one radix-2 stage (len 2, twiddle 1) when log2 n is odd
     for (int b = tid; b < total / 2; b += kFftThreads) {
-      const int t = b >> (logn - 1), r = b & (n / 2 - 1);
-      const int pos = r & (half - 1), grp = r >> (s - 1);
-      const int i0 = t * n + grp * len + pos, i1 = i0 + half;
-      const double2 w = tw[pos * step];
-      const double2 u = buf[i0], v0 = buf[i1];
-      const double2 v = make_double2(v0.x * w.x - v0.y * w.y, v0.x * w.y + v0.y * w.x);
+      const int i0 = 2 * b;
+      const double2 u = buf[i0], v = buf[i0 + 1];
       buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-      buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+      buf[i0 + 1] = make_double2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+    s = 2;
+  }
+  // two radix-2 stages (s and s + 1) per pass over the LDS lines: each
+  // thread takes the four elements i0 + {0, h, 2h, 3h} of one group of 4h
+  for (; s < logn; s += 2) {
+    const int h = 1 << (s - 1), step1 = n >> s, step2 = n >> (s + 1);
+    for (int b = tid; b < total / 4; b += kFftThreads) {
+      const int t = b >> (logn - 2), r = b & (n / 4 - 1);
+      const int pos = r & (h - 1), grp = r >> (s - 1);
+      const int i0 = t * n + grp * 4 * h + pos;
+      const double2 w1 = tw[pos * step1], w2 = tw[pos * step2];
+      // the second stage's twiddle for the odd pair is w2 exp(sign i pi/2)
+      const double2 w3 = make_double2(-kSign * w2.y, kSign * w2.x);
+      const double2 a = buf[i0], b0 = buf[i0 + h], c = buf[i0 + 2 * h], d0 = buf[i0 + 3 * h];
+      const double2 vb = make_double2(b0.x * w1.x - b0.y * w1.y, b0.x * w1.y + b0.y * w1.x);
+      const double2 vd = make_double2(d0.x * w1.x - d0.y * w1.y, d0.x * w1.y + d0.y * w1.x);
+      const double2 a1 = make_double2(a.x + vb.x, a.y + vb.y), b1 = make_double2(a.x - vb.x, a.y - vb.y);
+      const double2 c1 = make_double2(c.x + vd.x, c.y + vd.y), d1 = make_double2(c.x - vd.x, c.y - vd.y);
+      const double2 vc = make_double2(c1.x * w2.x - c1.y * w2.y, c1.x * w2.y + c1.y * w2.x);
+      const double2 ve = make_double2(d1.x * w3.x - d1.y * w3.y, d1.x * w3.y + d1.y * w3.x);
+      buf[i0] = make_double2(a1.x + vc.x, a1.y + vc.y);
+      buf[i0 + 2 * h] = make_double2(a1.x - vc.x, a1.y - vc.y);
+      buf[i0 + h] = make_double2(b1.x + ve.x, b1.y + ve.y);
+      buf[i0 + 3 * h] = make_double2(b1.x - ve.x, b1.y - ve.y);
     }
     __syncthreads();
   }
