@@ -33,9 +33,9 @@ __device__ inline void cic(double x, int n, double inv_d, int &i0, double &f) {
   const double u = x * inv_d;
   const double fl = floor(u);
   f = u - fl;
-  long long i = (long long)fl % n;
-  if (i < 0) i += n;
-  i0 = (int)i;
+  // periodic wrap; n is a power of two, so two's complement masking is the
+  // non-negative remainder
+  i0 = (int)((long long)fl & (long long)(n - 1));
 }
 
 __global__ __launch_bounds__(kPmThreads) void k_fill_u64(unsigned long long *p, uint64_t count) {
@@ -307,14 +307,25 @@ __device__ inline double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
 
 // Green's function, CIC deconvolution and gradient, per wave vector:
 // B holds rho_k on entry and (a_z + i phi)_k on exit, A gets (a_x + i a_y)_k.
+// The deconvolution 1 / W^2 = prod over axes of sinc(pi m / n)^-4 is
+// tabulated once per workgroup (n <= 1024 entries); n is a power of two,
+// so the cell index splits by shifts.
 __global__ __launch_bounds__(kPmThreads) void k_green(double2 *B, double2 *A, int n, double L, double G,
                                                       double r_s) {
-  const uint64_t cells = (uint64_t)n * n * n;
+  __shared__ double dec[1024];
+  for (int j = threadIdx.x; j < n; j += kPmThreads) {
+    const int m = j < n / 2 ? j : j - n;
+    const double sj = sinc(M_PI * m / n), s2 = sj * sj;
+    dec[j] = 1.0 / (s2 * s2);
+  }
+  __syncthreads();
+  const int logn = __builtin_ctz((unsigned)n);
+  const uint64_t cells = (uint64_t)n * n * n, mask = (uint64_t)(n - 1);
+  const double kf = 2.0 * M_PI / L;
   for (uint64_t i = blockIdx.x * (uint64_t)kPmThreads + threadIdx.x; i < cells;
        i += (uint64_t)gridDim.x * kPmThreads) {
-    const int iz = (int)(i % n), iy = (int)((i / n) % n), ix = (int)(i / ((uint64_t)n * n));
+    const int iz = (int)(i & mask), iy = (int)((i >> logn) & mask), ix = (int)(i >> (2 * logn));
     const int mx = ix < n / 2 ? ix : ix - n, my = iy < n / 2 ? iy : iy - n, mz = iz < n / 2 ? iz : iz - n;
-    const double kf = 2.0 * M_PI / L;
     const double kx = kf * mx, ky = kf * my, kz = kf * mz;
     const double k2 = kx * kx + ky * ky + kz * kz;
     if (k2 == 0.0) {
@@ -322,9 +333,7 @@ __global__ __launch_bounds__(kPmThreads) void k_green(double2 *B, double2 *A, in
       B[i] = make_double2(0.0, 0.0);
       continue;
     }
-    const double w = sinc(M_PI * mx / n) * sinc(M_PI * my / n) * sinc(M_PI * mz / n);
-    const double w2 = w * w;
-    const double g = -4.0 * M_PI * G * exp(-k2 * r_s * r_s) / k2 / (w2 * w2);
+    const double g = -4.0 * M_PI * G * exp(-k2 * r_s * r_s) / k2 * (dec[ix] * dec[iy] * dec[iz]);
     const double2 rho = B[i];
     const double pr = g * rho.x, pi = g * rho.y;  // phi_k
     // derivative wavenumbers, the Nyquist one dropped
