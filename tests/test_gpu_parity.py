@@ -294,6 +294,34 @@ def test_full_size_mixture2m_sampled(og_mod, oracle_mod, theta):
     tree.close()
 
 
+
+def test_full_size_zeldovich256_sampled(og_mod, oracle_mod):
+    """N = 256^3 Zel'dovich-displaced grid (the largest single-box
+    workload): both forms on 2000 seeded targets against the oracle."""
+    w = synth.zeldovich256()
+    _note("zeldovich256 N=%d" % w.pos.shape[0])
+    rng = np.random.default_rng(78)
+    tg = np.sort(rng.choice(w.pos.shape[0], 2000, replace=False))
+    op = oracle_params(oracle_mod, w.params)
+    ot = oracle_mod.build_tree(w.pos, w.mass, 1.0, op)
+    acc, pot, nint = oracle_mod.walk(ot, targets=tg)
+    tp, tm = _dev(w.pos), _dev(w.mass)
+    tree = og_mod.Tree(tp, tm, 1.0, w.params, stream=torch.cuda.current_stream())
+    assert tree.stats()["n_nodes"] == ot.n_nodes
+    for prec in ("fp64", "mixed"):
+        a, p, n = tree.force(targets=_dev(tg, torch.int64), precision=prec, with_counts=True)
+        torch.cuda.synchronize()
+        e = rel_err(a.cpu().numpy(), acc)
+        _note("  %s: median %.3g p99 %.3g max %.3g" % (prec, np.median(e), np.percentile(e, 99), e.max()))
+        if prec == "fp64":
+            assert np.array_equal(n.cpu().numpy(), nint)
+            assert e.max() <= 1e-11
+        else:
+            assert np.median(e) <= 1e-3 and np.percentile(e, 99) <= 1e-2
+    assert tree.status() == 0
+    tree.close()
+
+
 def test_mixed_walk_groups_across_the_periodic_boundary(og_mod, oracle_mod):
     """Every target of the walk groups (64 consecutive particles in curve
     order) whose members lie on both sides of a periodic face, N = 128^3
