@@ -214,6 +214,17 @@ __device__ inline double minimg(double d, bool periodic, double box) {
   return periodic ? w : d;
 }
 
+// The minimum image of three offsets, applied only when the (wave-uniform)
+// flag says it can change one: a branch, not a select, so groups that need
+// no wrap skip the work.
+__device__ inline void minimg3(double &x, double &y, double &z, bool wrap, double box) {
+  if (wrap) {
+    x = minimg(x, true, box);
+    y = minimg(y, true, box);
+    z = minimg(z, true, box);
+  }
+}
+
 // Spline-softened 1/r^3 (g) and 1/r (w) of a unit mass spread with the
 // cubic spline density of support h (paper, "Force evaluation"); u = r/h.
 __device__ inline void spline64(double r, double h, double &g, double &w) {
@@ -424,9 +435,8 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
       const double c2 = bx.lo[2] + ((double)(uint32_t)((t.corner >> 42) & 0x1fffffull) + half) * h;
       bool open_int = false;
       if (next == n) {
-        const double dcx = minimg(c0 - xi.x, wrap, box);
-        const double dcy = minimg(c1 - xi.y, wrap, box);
-        const double dcz = minimg(c2 - xi.z, wrap, box);
+        double dcx = c0 - xi.x, dcy = c1 - xi.y, dcz = c2 - xi.z;
+        minimg3(dcx, dcy, dcz, wrap, box);
         bool pruned = false;
         if (bx.cutoff) {
           const double reach = bx.rcut + 0.5 * side;
@@ -435,9 +445,8 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
         if (pruned) {
           next = ns;
         } else {
-          const double dx = minimg(mm.cx - xi.x, wrap, box);
-          const double dy = minimg(mm.cy - xi.y, wrap, box);
-          const double dz = minimg(mm.cz - xi.z, wrap, box);
+          double dx = mm.cx - xi.x, dy = mm.cy - xi.y, dz = mm.cz - xi.z;
+          minimg3(dx, dy, dz, wrap, box);
           const double r2 = dx * dx + dy * dy + dz * dz;
           const double near = 0.6 * side;
           const bool far_open = relative ? (bx.G * mm.m * side * side > bx.alpha * aold * r2 * r2)
