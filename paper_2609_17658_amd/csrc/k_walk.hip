@@ -928,6 +928,18 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
     }
     const bool periodic = bx.periodic;
     const double box = bx.box, h = bx.L * 0x1p-21;
+    // as in the per-target FP64 walk: a group farther than r_cut from every
+    // periodic face needs the minimum image only for the nodes of levels 0
+    // and 1, and never for particle offsets (a particle more than half a box
+    // away is beyond the cutoff in either image)
+    bool interior = false;
+    if (periodic) {
+      const double m = bx.rcut + 0x1p-40 * box;
+      const bool inside = !valid || (xi.x >= m && xi.x <= box - m && xi.y >= m && xi.y <= box - m &&
+                                     xi.z >= m && xi.z <= box - m);
+      interior = bx.rcut <= 0.24 * box && __ballot(!inside) == 0;
+    }
+    const bool pwrap = periodic && !interior;
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
     uint32_t ni = 0;
     uint32_t n = bx.root;
@@ -938,6 +950,7 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
       const bool leaf = (t.corner & kLeafBit) != 0;
       const uint32_t ns = leaf ? n + 1 : t.a;
       const int lev = (int)(t.b >> kCountBits);
+      const bool wrap = periodic && !(interior && lev >= 2);
       const double side = ldexp(bx.L, -lev);
       const double half = ldexp(1.0, 20 - lev);
       const double c0 = bx.lo[0] + ((double)(uint32_t)(t.corner & 0x1fffffull) + half) * h;
@@ -946,17 +959,17 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
       bool live = false, open = false;
       double dx = 0.0, dy = 0.0, dz = 0.0;
       if (valid) {
-        const double dcx = minimg(c0 - xi.x, periodic, box);
-        const double dcy = minimg(c1 - xi.y, periodic, box);
-        const double dcz = minimg(c2 - xi.z, periodic, box);
+        double dcx = c0 - xi.x, dcy = c1 - xi.y, dcz = c2 - xi.z;
+        minimg3(dcx, dcy, dcz, wrap, box);
         bool pruned = false;
         if (bx.cutoff) {
           const double reach = bx.rcut + 0.5 * side;
           pruned = fabs(dcx) > reach || fabs(dcy) > reach || fabs(dcz) > reach;
         }
-        dx = minimg(mm.cx - xi.x, periodic, box);
-        dy = minimg(mm.cy - xi.y, periodic, box);
-        dz = minimg(mm.cz - xi.z, periodic, box);
+        dx = mm.cx - xi.x;
+        dy = mm.cy - xi.y;
+        dz = mm.cz - xi.z;
+        minimg3(dx, dy, dz, wrap, box);
         if (!pruned) {
           live = true;
           const double r2 = dx * dx + dy * dy + dz * dz;
@@ -982,9 +995,8 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
           for (uint32_t j = 0; j < m; ++j) {
             const double qx = rdl(q.x, j), qy = rdl(q.y, j), qz = rdl(q.z, j), qm = rdl(q.w, j);
             if (valid && f + base + j != p) {
-              const double ex = minimg(qx - xi.x, periodic, box);
-              const double ey = minimg(qy - xi.y, periodic, box);
-              const double ez = minimg(qz - xi.z, periodic, box);
+              double ex = qx - xi.x, ey = qy - xi.y, ez = qz - xi.z;
+              minimg3(ex, ey, ez, pwrap, box);
               pair64<kExt>(ex, ey, ez, qm, bx.eps, bx, ax, ay, az, ph, ni);
             }
           }
