@@ -1011,11 +1011,14 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
   }
 }
 
-// Mixed: list entries hold a node centre (exact half-cells) and an FP32
-// offset from it (centre of mass, or particle), so each lane forms its own
-// offset exactly as the per-target mixed walk does.
+// Mixed: list entries hold a node centre and an FP32 offset from it (centre
+// of mass, or particle), so each lane forms its own offset exactly as the
+// per-target mixed walk does.  The centre is stored as the scalar term of
+// that walk's exact half-cell offset (2^23 plus the centre reduced against
+// the group's first lane), or, for groups that take the minimum image per
+// lane, as the raw centre.
 struct __attribute__((aligned(16))) GEntry {
-  int c[3];
+  float c[3];
   uint32_t tag;  // bit 31: offsets may need the minimum image; bits 0..30: particle, or kGNoSelf
   float o[3];
   float m;
@@ -1076,117 +1079,152 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
       yr = (float)(q.y - (bx.lo[1] + (double)o1 * h22));
       zr = (float)(q.z - (bx.lo[2] + (double)o2 * h22));
     }
+    // node centre minus lane origin in half-cells, as in the per-target
+    // mixed walk: a scalar reduction against the first lane's origin g, and a
+    // fixed per-lane term; groups wider than r_cut + |o - g| allows take the
+    // minimum image per lane
     const int g0 = __builtin_amdgcn_readfirstlane(o0), g1 = __builtin_amdgcn_readfirstlane(o1),
               g2 = __builtin_amdgcn_readfirstlane(o2);
-    int thr = 0;
+    constexpr int kHalf = 1 << 21, kMask = (1 << 22) - 1;
+    const int gq0 = g0 - kHalf, gq1 = g1 - kHalf, gq2 = g2 - kHalf;
+    const float qb0 = biased(kPer ? o0 - gq0 : o0), qb1 = biased(kPer ? o1 - gq1 : o1),
+                qb2 = biased(kPer ? o2 - gq2 : o2);
+    bool lane_wrap = false;
     if (kPer) {
       const int e = valid ? max(abs(o0 - g0), max(abs(o1 - g1), abs(o2 - g2))) : 0;
-      thr = (1 << 21) - wave_max_i32(e);
+      const float rc_cells = sqrtf(k.rc2) / k.h22;
+      lane_wrap = !((float)wave_max_i32(e) + rc_cells < (float)((1 << 20) - (1 << 16)));
     }
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
     uint32_t ni = 0, cnt = 0;
-    // every lane evaluates every entry for its own target, in list order
-    auto flush = [&]() {
-      __syncthreads();
-      for (uint32_t e = 0; e < cnt; ++e) {
-        const GEntry q = list[e];
-        int d0 = q.c[0] - o0, d1 = q.c[1] - o1, d2 = q.c[2] - o2;
-        if (kPer && (abs(q.c[0] - g0) > thr || abs(q.c[1] - g1) > thr || abs(q.c[2] - g2) > thr)) {
-          d0 = wrap_cells(d0);
-          d1 = wrap_cells(d1);
-          d2 = wrap_cells(d2);
+    auto walk = [&](auto lane_wrap_t) {
+      constexpr bool kLaneWrap = decltype(lane_wrap_t)::value;
+      // the stored form of a node centre (uniform over the wave)
+      auto centre = [&](const int *c, float *f) {
+        if (kPer && !kLaneWrap) {
+          f[0] = biased((c[0] - gq0) & kMask);
+          f[1] = biased((c[1] - gq1) & kMask);
+          f[2] = biased((c[2] - gq2) & kMask);
+        } else if (kPer) {
+          f[0] = __int_as_float(c[0]);
+          f[1] = __int_as_float(c[1]);
+          f[2] = __int_as_float(c[2]);
+        } else {
+          f[0] = biased(c[0]);
+          f[1] = biased(c[1]);
+          f[2] = biased(c[2]);
         }
-        float dx = ((float)d0 * k.h22 - xr) + q.o[0];
-        float dy = ((float)d1 * k.h22 - yr) + q.o[1];
-        float dz = ((float)d2 * k.h22 - zr) + q.o[2];
-        if (kPer && (q.tag & kGWrap)) {
+      };
+      // this lane's offset to a stored centre, in half-cells (exact)
+      auto offset = [&](const float *f, float &f0, float &f1, float &f2) {
+        if (kPer && kLaneWrap) {
+          f0 = (float)wrap_cells(__float_as_int(f[0]) - o0);
+          f1 = (float)wrap_cells(__float_as_int(f[1]) - o1);
+          f2 = (float)wrap_cells(__float_as_int(f[2]) - o2);
+        } else {
+          f0 = f[0] - qb0;
+          f1 = f[1] - qb1;
+          f2 = f[2] - qb2;
+        }
+      };
+      // every lane evaluates every entry for its own target, in list order
+      auto flush = [&]() {
+        __syncthreads();
+        for (uint32_t e = 0; e < cnt; ++e) {
+          const GEntry q = list[e];
+          float f0, f1, f2;
+          offset(q.c, f0, f1, f2);
+          float dx = (f0 * k.h22 - xr) + q.o[0];
+          float dy = (f1 * k.h22 - yr) + q.o[1];
+          float dz = (f2 * k.h22 - zr) + q.o[2];
+          if (kPer && (q.tag & kGWrap)) {
+            dx = wrap_box(dx, k);
+            dy = wrap_box(dy, k);
+            dz = wrap_box(dz, k);
+          }
+          const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
+          const bool use = valid && (!kCut || r2 < k.rc2) && (q.tag & kGNoSelf) != p;
+          if (use) {
+            eval32<kExt>(dx, dy, dz, r2, q.m, k, ax, ay, az, ph);
+            ++ni;
+          }
+        }
+        __syncthreads();
+        cnt = 0;
+      };
+      uint32_t n = bx.root;
+      const uint32_t nend = bx.node_end;
+      while (n < nend) {
+        const WNode w = ldw(A.wnode + n);
+        const bool leaf = (w.cf & kWLeaf) != 0;
+        const uint32_t ns = leaf ? n + 1 : w.a;
+        const uint32_t lc = w.cf & kWCount;
+        float fc[3], f0, f1, f2;
+        centre(w.c, fc);
+        offset(fc, f0, f1, f2);
+        const float dcx = f0 * k.h22 - xr, dcy = f1 * k.h22 - yr, dcz = f2 * k.h22 - zr;
+        const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
+        const bool wrapd = kPer && (w.cf & kWWrap) != 0;
+        float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
+        if (wrapd) {
           dx = wrap_box(dx, k);
           dy = wrap_box(dy, k);
           dz = wrap_box(dz, k);
         }
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const bool use = valid && (!kCut || r2 < k.rc2) && (q.tag & kGNoSelf) != p;
-        if (use) {
-          eval32<kExt>(dx, dy, dz, r2, q.m, k, ax, ay, az, ph);
-          ++ni;
-        }
-      }
-      __syncthreads();
-      cnt = 0;
-    };
-    uint32_t n = bx.root;
-    const uint32_t nend = bx.node_end;
-    while (n < nend) {
-      const WNode w = ldw(A.wnode + n);
-      const bool leaf = (w.cf & kWLeaf) != 0;
-      const uint32_t ns = leaf ? n + 1 : w.a;
-      const uint32_t lc = w.cf & kWCount;
-      int d0 = w.c[0] - o0, d1 = w.c[1] - o1, d2 = w.c[2] - o2;
-      if (kPer && (abs(w.c[0] - g0) > thr || abs(w.c[1] - g1) > thr || abs(w.c[2] - g2) > thr)) {
-        d0 = wrap_cells(d0);
-        d1 = wrap_cells(d1);
-        d2 = wrap_cells(d2);
-      }
-      const float dcx = (float)d0 * k.h22 - xr, dcy = (float)d1 * k.h22 - yr, dcz = (float)d2 * k.h22 - zr;
-      const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
-      const bool wrapd = kPer && (w.cf & kWWrap) != 0;
-      float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
-      if (wrapd) {
-        dx = wrap_box(dx, k);
-        dy = wrap_box(dy, k);
-        dz = wrap_box(dz, k);
-      }
-      const float r2 = dx * dx + dy * dy + dz * dz;
-      const bool live = valid && !(kCut && mdc > w.reach);
-      const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
-      const bool open = live && (far_open || mdc < w.near);
-      const uint32_t nskip = ns > n ? ns : n + 1;  // a skip always moves forward
-      uint32_t nn;
-      if (!__ballot(live)) {
-        nn = nskip;
-      } else if (!__ballot(open)) {
-        if (cnt == kGroupCap) flush();
-        if (lane == 0) {
-          GEntry q;
-          q.c[0] = w.c[0];
-          q.c[1] = w.c[1];
-          q.c[2] = w.c[2];
-          q.tag = kGNoSelf | (wrapd ? kGWrap : 0u);
-          q.o[0] = w.o[0];
-          q.o[1] = w.o[1];
-          q.o[2] = w.o[2];
-          q.m = w.m;
-          list[cnt] = q;
-        }
-        ++cnt;
-        nn = nskip;
-      } else {
-        if (leaf) {
-          for (uint32_t j0 = 0; j0 < lc; j0 += 64) {
-            const uint32_t m = min(64u, lc - j0);
-            if (cnt + m > kGroupCap) flush();
-            if (lane < m) {
-              const uint32_t j = (w.a & kTagFirst) + j0 + lane;
-              const float4 pq = A.part32[j];
-              GEntry q;
-              q.c[0] = w.c[0];
-              q.c[1] = w.c[1];
-              q.c[2] = w.c[2];
-              q.tag = j | (wrapd ? kGWrap : 0u);
-              q.o[0] = pq.x;
-              q.o[1] = pq.y;
-              q.o[2] = pq.z;
-              q.m = pq.w;
-              list[cnt + lane] = q;
-            }
-            cnt += m;
+        const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
+        const bool live = valid && !(kCut && mdc > w.reach);
+        const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
+        const bool open = live && (far_open || mdc < w.near);
+        const uint32_t nskip = ns > n ? ns : n + 1;  // a skip always moves forward
+        uint32_t nn;
+        if (!__ballot(live)) {
+          nn = nskip;
+        } else if (!__ballot(open)) {
+          if (cnt == kGroupCap) flush();
+          if (lane == 0) {
+            GEntry q;
+            q.c[0] = fc[0];
+            q.c[1] = fc[1];
+            q.c[2] = fc[2];
+            q.tag = kGNoSelf | (wrapd ? kGWrap : 0u);
+            q.o[0] = w.o[0];
+            q.o[1] = w.o[1];
+            q.o[2] = w.o[2];
+            q.m = w.m;
+            list[cnt] = q;
           }
+          ++cnt;
+          nn = nskip;
+        } else {
+          if (leaf) {
+            for (uint32_t j0 = 0; j0 < lc; j0 += 64) {
+              const uint32_t m = min(64u, lc - j0);
+              if (cnt + m > kGroupCap) flush();
+              if (lane < m) {
+                const uint32_t j = (w.a & kTagFirst) + j0 + lane;
+                const float4 pq = A.part32[j];
+                GEntry q;
+                q.c[0] = fc[0];
+                q.c[1] = fc[1];
+                q.c[2] = fc[2];
+                q.tag = j | (wrapd ? kGWrap : 0u);
+                q.o[0] = pq.x;
+                q.o[1] = pq.y;
+                q.o[2] = pq.z;
+                q.m = pq.w;
+                list[cnt + lane] = q;
+              }
+              cnt += m;
+            }
+          }
+          nn = n + 1;
         }
-        nn = n + 1;
+        n = nn;
       }
-      n = nn;
-    }
-    flush();
+      flush();
+    };
+    if (kPer && lane_wrap) walk(std::true_type{});
+    else walk(std::false_type{});
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
