@@ -146,9 +146,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
-    ap.add_argument("--legs", default="batch,serving,zeldovich,variants,hilbert,active,pm,groups",
+    ap.add_argument("--legs", default="batch,serving,zeldovich,variants,hilbert,active,pm,groups,theta",
                     help="extra workloads reported beside the headline: batch, serving, zeldovich, "
-                         "variants, hilbert, active, pm, groups (comma list, or 'none')")
+                         "variants, hilbert, active, pm, groups, theta (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -266,7 +266,7 @@ def main():
     for leg in legs:
         fn = {"batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich,
               "variants": leg_variants, "hilbert": leg_hilbert, "active": leg_active, "pm": leg_pm,
-              "groups": leg_groups}[leg]
+              "groups": leg_groups, "theta": leg_theta}[leg]
         log("leg %s" % leg)
         try:
             out[LEG_NAMES[leg]] = fn(og, torch, synth, args)
@@ -334,7 +334,8 @@ def main():
 
 LEG_NAMES = {"batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256",
              "variants": "variants_mixture2m", "hilbert": "hilbert_mixture2m", "active": "active_mixture2m",
-             "pm": "treepm", "groups": "group_lists_mixture2m"}
+             "pm": "treepm", "groups": "group_lists_mixture2m",
+             "theta": "theta_mixture2m"}
 
 
 def _oracle_params(oracle, prm):
@@ -642,6 +643,49 @@ def leg_hilbert(og, torch, synth, args):
                                   "fp64_max": float(_rel_err(ad.cpu().numpy(), a_o).max()),
                                   "fp64_counts_equal": bool(np.array_equal(nd.cpu().numpy(), n_o))}
     out["workload"] = "mixture2m as the headline, Peano-Hilbert keys"
+    return out
+
+
+def leg_theta(og, torch, synth, args):
+    """The headline mixture at the other opening angles of its sweep
+    (theta 0.3 and 0.7): both forms, error on sampled targets."""
+    out = {}
+    for theta in (0.3, 0.7):
+        w = synth.mixture2m(theta=theta)
+        n = w.pos.shape[0]
+        prm = w.params.as_dict()
+        tp = torch.as_tensor(w.pos, device="cuda")
+        tm = torch.as_tensor(w.mass, device="cuda")
+        wsb = torch.empty(og.og_tree_workspace_bound(n, og.make_params(prm)), dtype=torch.uint8, device="cuda")
+        res = {}
+        for prec, steps in (("mixed", 5), ("fp64", 2)):
+            r = time_steps(og, torch, tp, tm, prm, wsb, prec, steps, 1)
+            for t in r["trees"]:
+                t.close()
+            res[prec] = {"value": n / (r["total_ms"] / steps * 1e-3), "ms_per_step": r["total_ms"] / steps,
+                         "build_ms": float(r["build_ms"].mean()), "walk_ms": float(r["walk_ms"].mean())}
+            log("  theta %.1f %s: %.3f ms/step (build %.3f, walk %.3f)" % (
+                theta, prec, res[prec]["ms_per_step"], res[prec]["build_ms"], res[prec]["walk_ms"]))
+        rng = np.random.default_rng(11)
+        tg = np.sort(rng.choice(n, 4096, replace=False))
+        t = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream(), workspace=wsb)
+        tgd = torch.as_tensor(tg, device="cuda")
+        am, _, nm = t.force(targets=tgd, precision="mixed", with_counts=True)
+        ad, _, nd = t.force(targets=tgd, precision="fp64", with_counts=True)
+        torch.cuda.synchronize()
+        t.close()
+        res["interactions_per_target"] = float(nd.double().mean().item())
+        if not args.no_oracle:
+            import oracle
+            a_o, _, n_o = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, prm), targets=tg)
+            e_m = _rel_err(am.cpu().numpy(), a_o)
+            res["error_vs_oracle"] = {"targets": int(tg.size), "mixed_median": float(np.median(e_m)),
+                                      "mixed_p99": float(np.percentile(e_m, 99)),
+                                      "fp64_max": float(_rel_err(ad.cpu().numpy(), a_o).max()),
+                                      "fp64_counts_equal": bool(np.array_equal(nd.cpu().numpy(), n_o))}
+        out["theta%.1f" % theta] = res
+        del tp, tm, wsb
+    out["workload"] = "mixture2m as the headline at theta 0.3 and 0.7 (the headline runs theta 0.5)"
     return out
 
 
