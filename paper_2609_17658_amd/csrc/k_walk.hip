@@ -779,8 +779,10 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
       constexpr bool kLaneWrap = decltype(lane_wrap_t)::value;
       // A leaf of more than 8 particles takes one list entry per 8 of its
       // particles: the wave stays on it (pend = the next particle offset)
-      // until the lanes that opened it (bigopen) have appended every entry.
-      uint32_t pend = 0, bigopen = 0;
+      // until the lanes that opened it have appended every entry.  While the
+      // wave stays, those are exactly the lanes with next <= n (an opening
+      // lane keeps next, every other lane is past n).
+      uint32_t pend = 0;
       // the next node's record is read after the decision (the wave's other
       // work and the other waves on the SIMD cover the scalar load)
       for (uint32_t n = bx.root; n < nend;) {
@@ -812,7 +814,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
           const uint32_t lc = cf & kWCount;
           const bool wrapd = kPer && (cf & kWWrap) != 0;
           if (pend) {
-            if (bigopen) {
+            if (next <= n) {
               list[cnt][lane] = make_float4(dcx, dcy, dcz, leaf_tag((w.a & kTagFirst) + pend, min(8u, lc - pend), wrapd));
               ++cnt;
             }
@@ -846,12 +848,11 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
           list[cnt][lane] = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a & kTagFirst, min(8u, lc), wrapd))
                                       : make_float4(dx, dy, dz, w.m);
           if (kSoft) lsoft[cnt][lane] = emono;
-          cnt += contrib ? 1u : (open_here ? (cf >> 30) & 1u : 0u);
+          cnt += (contrib || (open_here && (cf & kWLeaf) != 0)) ? 1u : 0u;
           if (act && !open_here) next = ns;
           const bool opened = __ballot(open_here) != 0;
           if ((cf & kWBig) && opened) {
             pend = 8;
-            bigopen = open_here ? 1u : 0u;
           } else {
             n = opened ? n + 1 : max(ns, n + 1);
           }
@@ -878,7 +879,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
                                        : make_float4(dx, dy, dz, w.m);
         list[cnt][lane] = entry;
         if (kSoft) lsoft[cnt][lane] = emono;
-        cnt += contrib ? 1u : (open_here ? (cf >> 30) & 1u : 0u);
+        cnt += (contrib || (open_here && (cf & kWLeaf) != 0)) ? 1u : 0u;
         if (act && !open_here) next = ns;
         // the lanes that opened n are those still at or before n; a leaf's
         // skip is n + 1; a skip always moves forward
