@@ -682,7 +682,10 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
 // boundaries; 2 = cutoff, periodic; 3 = plain Newtonian, open boundaries.
 // kExt: the spline softening and the relative criterion are read from each
 // box (only with kMode 0); kSoft (with kExt): per-particle softening lengths.
-template <int kCap, int kMode, bool kExt, bool kSoft = false>
+// kWide: node records addressed with 64-bit offsets (forests whose records
+// exceed 4 GiB); otherwise a record's byte offset is one 32-bit scalar
+// product, which the scalar load takes as its offset register.
+template <int kCap, int kMode, bool kExt, bool kSoft = false, bool kWide = false>
 // With 4-deep lists every variant fits 8 waves per SIMD (64 vector and at
 // most 96 scalar registers, no spills), which hides more latency than the
 // 7 that the scalar registers would otherwise allow.
@@ -786,7 +789,8 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
       // the next node's record is read after the decision (the wave's other
       // work and the other waves on the SIMD cover the scalar load)
       for (uint32_t n = bx.root; n < nend;) {
-        const WNode w = ldw(A.wnode + n);
+        const WNode w = kWide ? ldw(A.wnode + n)
+                              : ldw((const WNode *)((const char *)A.wnode + n * (uint32_t)sizeof(WNode)));
         const uint32_t cf = w.cf;
         // room for this visit's entry
         if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
@@ -1242,6 +1246,13 @@ int walk_list_capacity() {
   return cap;
 }
 
+// OG_WIDE_NODES=1 takes the 64-bit record offsets for every forest (the
+// tests compare both forms on small inputs); read at each launch.
+static bool wide_nodes_forced() {
+  const char *e = getenv("OG_WIDE_NODES");
+  return e && atoi(e) == 1;
+}
+
 void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
   const uint32_t cus = (uint32_t)device_cu_count();
   const uint32_t groups = W.n_groups > 0 ? W.n_groups : 1;
@@ -1274,9 +1285,12 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
     const uint32_t per_cu = std::min<uint32_t>(32u, 160u / (uint32_t)cap);
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(per_cu * cus, groups));
     const int mode = W.box_kind;
+    const bool wide = W.wide_nodes || wide_nodes_forced();
 #define OG_WALK32(C)                                                                 \
   do {                                                                               \
-    if (W.seps) k_walk32<C, 0, true, true><<<blocks, kWalk32Threads, 0, s>>>(W);     \
+    if (wide && W.seps) k_walk32<4, 0, true, true, true><<<blocks, kWalk32Threads, 0, s>>>(W); \
+    else if (wide) k_walk32<4, 0, true, false, true><<<blocks, kWalk32Threads, 0, s>>>(W); \
+    else if (W.seps) k_walk32<C, 0, true, true><<<blocks, kWalk32Threads, 0, s>>>(W); \
     else if (W.ext) k_walk32<C, 0, true><<<blocks, kWalk32Threads, 0, s>>>(W);       \
     else if (mode == 2) k_walk32<C, 2, false><<<blocks, kWalk32Threads, 0, s>>>(W);  \
     else if (mode == 1) k_walk32<C, 1, false><<<blocks, kWalk32Threads, 0, s>>>(W);  \

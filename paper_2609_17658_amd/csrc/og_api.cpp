@@ -282,6 +282,7 @@ WalkArgs Forest::walk_args() const {
   W.semax = A.semax;
   W.semin = A.semin;
   if (A.seps) W.ext = 1;
+  W.wide_nodes = (uint64_t)node_cap * sizeof(WNode) > 0xffffffffull ? 1 : 0;
   return W;
 }
 

@@ -112,6 +112,7 @@ struct WalkArgs {
   const double *seps, *semax, *semin;  // per-particle softening (null: the boxes' eps)
   int group_lists;            // 1: group-shared interaction lists, 0: per-target walk
   const double *a_old;        // relative criterion: previous accelerations [n][3], caller order
+  int wide_nodes;             // the node records span more than 4 GiB (64-bit record offsets)
 };
 void launch_walk(const WalkArgs &W, int precision, hipStream_t s);
 void launch_reset(uint32_t *word, hipStream_t s);

@@ -200,6 +200,22 @@ def test_list_depth_does_not_change_results(og_mod, case):
         assert np.array_equal(g["nint"], ref["nint"]), cap
 
 
+@pytest.mark.parametrize("case", ["mixture32k", "rand10007_lm16", "coincident300", "open3000", "box3_faces"])
+def test_wide_node_offsets_match(og_mod, case, monkeypatch):
+    """Forests whose node records exceed 4 GiB address them with 64-bit
+    offsets (the general kernel instance); OG_WIDE_NODES=1 forces that form
+    on a small input.  It computes the same pair terms in the same order, so
+    the results are bitwise those of the 32-bit-offset walk."""
+    _, pos, mass, box, prm = next(c for c in CASES if c[0] == case)
+    ref = gpu_run(og_mod, pos, mass, box, prm, precision="mixed")
+    monkeypatch.setenv("OG_WIDE_NODES", "1")
+    g = gpu_run(og_mod, pos, mass, box, prm, precision="mixed")
+    monkeypatch.delenv("OG_WIDE_NODES")
+    assert np.array_equal(g["nint"], ref["nint"])
+    assert np.array_equal(g["acc"], ref["acc"])
+    assert np.array_equal(g["pot"], ref["pot"])
+
+
 def test_subset_targets_match_all_targets(og_mod):
     w = synth.mixture32k()
     rng = np.random.default_rng(5)
