@@ -693,9 +693,9 @@ __global__ __launch_bounds__(kThreads) void k_wnodes(const BoxDev *boxes, int B,
     const bool leaf = (t.corner & kLeafBit) != 0;
     const float side = ldexpf(bx.Lf, -lev);
     WNode w;
-    w.c[0] = 2 * (int)(t.corner & 0x1fffffull) + hc;
-    w.c[1] = 2 * (int)((t.corner >> 21) & 0x1fffffull) + hc;
-    w.c[2] = 2 * (int)((t.corner >> 42) & 0x1fffffull) + hc;
+    w.c[0] = 0x4B000000 | (2 * (int)(t.corner & 0x1fffffull) + hc);
+    w.c[1] = 0x4B000000 | (2 * (int)((t.corner >> 21) & 0x1fffffull) + hc);
+    w.c[2] = 0x4B000000 | (2 * (int)((t.corner >> 42) & 0x1fffffull) + hc);
     w.side2 = side * side;
     w.o[0] = m.ox;
     w.o[1] = m.oy;

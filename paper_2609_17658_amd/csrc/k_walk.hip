@@ -618,6 +618,8 @@ __device__ inline int wave_max_i32(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+__device__ inline int wave_min_i32(int v) { return -wave_max_i32(-v); }
+
 // List entries (float4).  A monopole: (offset, mass), mass >= 0, already
 // known to pass the cutoff.  A leaf: (offset of the leaf centre, tag), the
 // tag's bits as laid out by leaf_tag_bits.
@@ -754,22 +756,28 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
     // as r_cut + E stays below a quarter of the box; a node out of reach is
     // pruned in either image.  Wider groups (also those that straddle the
     // box boundary) take the minimum image per lane.
+    // Groups whose targets all lie farther than r_cut from every face of the
+    // box take c - o as it is: a node for which that is not the minimum
+    // image lies beyond the face nearest the target, so none of its points
+    // is within r_cut of it in either image.  Such a node is pruned in the
+    // raw image (it is more than a quarter box away); in the minimum image it
+    // may be visited, but it contributes nothing, so the contributions and
+    // their order are the same.
     const int g0 = __builtin_amdgcn_readfirstlane(o0), g1 = __builtin_amdgcn_readfirstlane(o1),
               g2 = __builtin_amdgcn_readfirstlane(o2);
     constexpr int kHalf = 1 << 21, kMask = (1 << 22) - 1;
     const int gq0 = g0 - kHalf, gq1 = g1 - kHalf, gq2 = g2 - kHalf;
     // per-lane term subtracted from the reduced node centre: (o - g) + 2^21
     const int q0 = o0 - gq0, q1 = o1 - gq1, q2 = o2 - gq2;
-    // Offsets in half-cells become floats exactly without a per-lane
-    // conversion: for 0 <= a, b < 2^23 the float with bit pattern
-    // 0x4B000000 | a is 2^23 + a, and (2^23 + a) - (2^23 + b) = a - b
-    // exactly.  The node's term is a scalar OR, the lane's is fixed.
-    const float qb0 = biased(kPer ? q0 : o0), qb1 = biased(kPer ? q1 : o1), qb2 = biased(kPer ? q2 : o2);
-    bool lane_wrap = false;
+    bool lane_wrap = false, interior = false;
     if (kPer) {
+      const float rc = sqrtf(k.rc2);
       const int e = valid ? max(abs(o0 - g0), max(abs(o1 - g1), abs(o2 - g2))) : 0;
-      const float rc_cells = sqrtf(k.rc2) / k.h22;
-      lane_wrap = !((float)wave_max_i32(e) + rc_cells < (float)((1 << 20) - (1 << 16)));
+      lane_wrap = !((float)wave_max_i32(e) + rc / k.h22 < (float)((1 << 20) - (1 << 16)));
+      // half-cells from the lane origin to the nearest face; the target is
+      // within one half-cell of its origin
+      const int df = valid ? min(min(min(o0, o1), o2), (1 << 22) - max(max(o0, o1), o2)) : (1 << 22);
+      interior = (float)(wave_min_i32(df) - 2) * k.h22 > rc;
     }
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
     uint32_t ni = 0, cnt = 0;
@@ -778,8 +786,16 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
     // value and so stays active in the subtree; a lane that prunes or accepts
     // n moves next to skip(n).
     uint32_t next = valid ? bx.root : nend;
-    auto walk = [&](auto lane_wrap_t) {
-      constexpr bool kLaneWrap = decltype(lane_wrap_t)::value;
+    // kForm: 0 = c - o as it is (open boxes, interior groups); 1 = reduced
+    // against the first lane; 2 = the minimum image per lane
+    auto walk = [&](auto form_t) {
+      constexpr int kForm = decltype(form_t)::value;
+      // Offsets in half-cells become floats exactly without a per-lane
+      // conversion: for 0 <= a, b < 2^23 the float with bit pattern
+      // 0x4B000000 | a is 2^23 + a, and (2^23 + a) - (2^23 + b) = a - b
+      // exactly.  The node's term is a scalar OR, the lane's is fixed.
+      const float qb0 = biased(kForm == 1 ? q0 : o0), qb1 = biased(kForm == 1 ? q1 : o1),
+                  qb2 = biased(kForm == 1 ? q2 : o2);
       // A leaf of more than 8 particles takes one list entry per 8 of its
       // particles: the wave stays on it (pend = the next particle offset)
       // until the lanes that opened it have appended every entry.  While the
@@ -795,18 +811,18 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
         // room for this visit's entry
         if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
         float f0, f1, f2;  // node centre minus lane origin, in half-cells (exact)
-        if (kPer && !kLaneWrap) {
+        if (kPer && kForm == 1) {
           f0 = biased((w.c[0] - gq0) & kMask) - qb0;
           f1 = biased((w.c[1] - gq1) & kMask) - qb1;
           f2 = biased((w.c[2] - gq2) & kMask) - qb2;
-        } else if (kPer) {
-          f0 = (float)wrap_cells(w.c[0] - o0);
-          f1 = (float)wrap_cells(w.c[1] - o1);
-          f2 = (float)wrap_cells(w.c[2] - o2);
-        } else {
-          f0 = biased(w.c[0]) - qb0;
-          f1 = biased(w.c[1]) - qb1;
-          f2 = biased(w.c[2]) - qb2;
+        } else if (kPer && kForm == 2) {
+          f0 = (float)wrap_cells((w.c[0] & kMask) - o0);
+          f1 = (float)wrap_cells((w.c[1] & kMask) - o1);
+          f2 = (float)wrap_cells((w.c[2] & kMask) - o2);
+        } else {  // the record holds the node's term already
+          f0 = __int_as_float(w.c[0]) - qb0;
+          f1 = __int_as_float(w.c[1]) - qb1;
+          f2 = __int_as_float(w.c[2]) - qb2;
         }
         const float dcx = f0 * k.h22 - xr, dcy = f1 * k.h22 - yr, dcz = f2 * k.h22 - zr;
         const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
@@ -890,8 +906,9 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
         n = __ballot(next <= n) ? n + 1 : max(ns, n + 1);
       }
     };
-    if (kPer && lane_wrap) walk(std::true_type{});
-    else walk(std::false_type{});
+    if (kPer && lane_wrap) walk(std::integral_constant<int, 2>{});
+    else if (kPer && !interior) walk(std::integral_constant<int, 1>{});
+    else walk(std::integral_constant<int, 0>{});
     flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
@@ -1020,8 +1037,9 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
 // of mass, or particle), so each lane forms its own offset exactly as the
 // per-target mixed walk does.  The centre is stored as the scalar term of
 // that walk's exact half-cell offset (2^23 plus the centre reduced against
-// the group's first lane), or, for groups that take the minimum image per
-// lane, as the raw centre.
+// the group's first lane), or, for open boxes and for groups that take the
+// minimum image per lane, as the node record holds it (2^23 plus the
+// centre, as float bits).
 struct __attribute__((aligned(16))) GEntry {
   float c[3];
   uint32_t tag;  // bit 31: offsets may need the minimum image; bits 0..30: particle, or kGNoSelf
@@ -1110,22 +1128,18 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
           f[0] = biased((c[0] - gq0) & kMask);
           f[1] = biased((c[1] - gq1) & kMask);
           f[2] = biased((c[2] - gq2) & kMask);
-        } else if (kPer) {
+        } else {  // the record's form: 2^23 + c as float bits
           f[0] = __int_as_float(c[0]);
           f[1] = __int_as_float(c[1]);
           f[2] = __int_as_float(c[2]);
-        } else {
-          f[0] = biased(c[0]);
-          f[1] = biased(c[1]);
-          f[2] = biased(c[2]);
         }
       };
       // this lane's offset to a stored centre, in half-cells (exact)
       auto offset = [&](const float *f, float &f0, float &f1, float &f2) {
         if (kPer && kLaneWrap) {
-          f0 = (float)wrap_cells(__float_as_int(f[0]) - o0);
-          f1 = (float)wrap_cells(__float_as_int(f[1]) - o1);
-          f2 = (float)wrap_cells(__float_as_int(f[2]) - o2);
+          f0 = (float)wrap_cells((__float_as_int(f[0]) & kMask) - o0);
+          f1 = (float)wrap_cells((__float_as_int(f[1]) & kMask) - o1);
+          f2 = (float)wrap_cells((__float_as_int(f[2]) & kMask) - o2);
         } else {
           f0 = f[0] - qb0;
           f1 = f[1] - qb1;

@@ -67,7 +67,9 @@ struct __attribute__((aligned(16))) Mom32 {
 
 // Walk record of a node for the mixed-precision walk, 48 bytes (scalar
 // loads): everything the per-node decisions need, precomputed in FP32.
-//   c[3]:   cube centre in half-cells of the level-21 grid (exact integers)
+//   c[3]:   cube centre c in half-cells of the level-21 grid, stored as
+//           0x4B000000 | c: the bits of the float 2^23 + c, a multiple of
+//           2^22 above c (so c modulo 2^22 is unchanged)
 //   side2:  side^2;  reach: r_cut + side/2;  near: 0.6 side
 //   o[3]:   centre of mass minus cube centre;  m: mass
 //   a:      internal node: skip (the next node after the subtree);
