@@ -1051,7 +1051,8 @@ constexpr uint32_t kGroupCap = 128;
 
 // 128 entries (4 KB of LDS per wave) leave room for 8 waves per SIMD, which
 // pays for the extra flushes.
-template <int kMode, bool kExt>
+// kWide as for the per-target mixed walk: 64-bit node record offsets.
+template <int kMode, bool kExt, bool kWide = false>
 __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kExt ? 1 : 8, 8))) void k_walkg32(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ GEntry list[kGroupCap];
@@ -1174,7 +1175,8 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
       uint32_t n = bx.root;
       const uint32_t nend = bx.node_end;
       while (n < nend) {
-        const WNode w = ldw(A.wnode + n);
+        const WNode w = kWide ? ldw(A.wnode + n)
+                              : ldw((const WNode *)((const char *)A.wnode + n * (uint32_t)sizeof(WNode)));
         const bool leaf = (w.cf & kWLeaf) != 0;
         const uint32_t ns = leaf ? n + 1 : w.a;
         const uint32_t lc = w.cf & kWCount;
@@ -1280,7 +1282,8 @@ void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
       // one wave per workgroup, 4 KB of list each, 8 waves per SIMD
       const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(32u * cus, groups));
       const int mode = W.box_kind;
-      if (W.ext) k_walkg32<0, true><<<blocks, kWalk32Threads, 0, s>>>(W);
+      if (W.wide_nodes || wide_nodes_forced()) k_walkg32<0, true, true><<<blocks, kWalk32Threads, 0, s>>>(W);
+      else if (W.ext) k_walkg32<0, true><<<blocks, kWalk32Threads, 0, s>>>(W);
       else if (mode == 2) k_walkg32<2, false><<<blocks, kWalk32Threads, 0, s>>>(W);
       else if (mode == 1) k_walkg32<1, false><<<blocks, kWalk32Threads, 0, s>>>(W);
       else if (mode == 3) k_walkg32<3, false><<<blocks, kWalk32Threads, 0, s>>>(W);

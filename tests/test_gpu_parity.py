@@ -200,16 +200,18 @@ def test_list_depth_does_not_change_results(og_mod, case):
         assert np.array_equal(g["nint"], ref["nint"]), cap
 
 
+@pytest.mark.parametrize("lists", ["target", "group"])
 @pytest.mark.parametrize("case", ["mixture32k", "rand10007_lm16", "coincident300", "open3000", "box3_faces"])
-def test_wide_node_offsets_match(og_mod, case, monkeypatch):
+def test_wide_node_offsets_match(og_mod, case, lists, monkeypatch):
     """Forests whose node records exceed 4 GiB address them with 64-bit
     offsets (the general kernel instance); OG_WIDE_NODES=1 forces that form
     on a small input.  It computes the same pair terms in the same order, so
-    the results are bitwise those of the 32-bit-offset walk."""
+    the results are bitwise those of the 32-bit-offset walk, for per-target
+    and for group-shared lists."""
     _, pos, mass, box, prm = next(c for c in CASES if c[0] == case)
-    ref = gpu_run(og_mod, pos, mass, box, prm, precision="mixed")
+    ref = gpu_run(og_mod, pos, mass, box, prm, precision="mixed", lists=lists)
     monkeypatch.setenv("OG_WIDE_NODES", "1")
-    g = gpu_run(og_mod, pos, mass, box, prm, precision="mixed")
+    g = gpu_run(og_mod, pos, mass, box, prm, precision="mixed", lists=lists)
     monkeypatch.delenv("OG_WIDE_NODES")
     assert np.array_equal(g["nint"], ref["nint"])
     assert np.array_equal(g["acc"], ref["acc"])
