@@ -777,7 +777,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
       // half-cells from the lane origin to the nearest face; the target is
       // within one half-cell of its origin
       const int df = valid ? min(min(min(o0, o1), o2), (1 << 22) - max(max(o0, o1), o2)) : (1 << 22);
-      interior = (float)(wave_min_i32(df) - 2) * k.h22 > rc;
+      interior = !A.no_interior && (float)(wave_min_i32(df) - 2) * k.h22 > rc;
     }
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
     uint32_t ni = 0, cnt = 0;
@@ -1262,14 +1262,18 @@ int walk_list_capacity() {
   return cap;
 }
 
-// OG_WIDE_NODES=1 takes the 64-bit record offsets for every forest (the
-// tests compare both forms on small inputs); read at each launch.
-static bool wide_nodes_forced() {
-  const char *e = getenv("OG_WIDE_NODES");
+// OG_WIDE_NODES=1 takes the 64-bit record offsets for every forest, and
+// OG_NO_INTERIOR=1 the reduced periodic offsets for every group (the tests
+// compare both forms on small inputs); read at each launch.
+static bool env_flag(const char *name) {
+  const char *e = getenv(name);
   return e && atoi(e) == 1;
 }
+static bool wide_nodes_forced() { return env_flag("OG_WIDE_NODES"); }
 
-void launch_walk(const WalkArgs &W, int precision, hipStream_t s) {
+void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
+  WalkArgs W = W0;
+  W.no_interior = env_flag("OG_NO_INTERIOR") ? 1 : 0;
   const uint32_t cus = (uint32_t)device_cu_count();
   const uint32_t groups = W.n_groups > 0 ? W.n_groups : 1;
   launch_reset_n(W.counter, kQueues, s);

@@ -113,6 +113,7 @@ struct WalkArgs {
   int group_lists;            // 1: group-shared interaction lists, 0: per-target walk
   const double *a_old;        // relative criterion: previous accelerations [n][3], caller order
   int wide_nodes;             // the node records span more than 4 GiB (64-bit record offsets)
+  int no_interior;            // mixed walk: reduce every periodic offset (no raw form for interior groups)
 };
 void launch_walk(const WalkArgs &W, int precision, hipStream_t s);
 void launch_reset(uint32_t *word, hipStream_t s);

@@ -218,6 +218,25 @@ def test_wide_node_offsets_match(og_mod, case, lists, monkeypatch):
     assert np.array_equal(g["pot"], ref["pot"])
 
 
+@pytest.mark.parametrize("case", ["mixture32k", "rand10007_lm16", "coincident300", "box3_faces", "rcut8rs5000"])
+def test_interior_groups_raw_offsets_match(og_mod, case, monkeypatch):
+    """In a periodic box, groups whose targets all lie farther than r_cut
+    from every face take node offsets without the modulo reduction; a node
+    for which that is not the minimum image has no point within r_cut of
+    the target, so the contributions and their order are unchanged.
+    OG_NO_INTERIOR=1 reduces every offset: the results must be bitwise
+    equal."""
+    _, pos, mass, box, prm = next(c for c in CASES if c[0] == case)
+    assert (prm.as_dict() if hasattr(prm, "as_dict") else prm)["periodic"]
+    ref = gpu_run(og_mod, pos, mass, box, prm, precision="mixed")
+    monkeypatch.setenv("OG_NO_INTERIOR", "1")
+    g = gpu_run(og_mod, pos, mass, box, prm, precision="mixed")
+    monkeypatch.delenv("OG_NO_INTERIOR")
+    assert np.array_equal(g["nint"], ref["nint"])
+    assert np.array_equal(g["acc"], ref["acc"])
+    assert np.array_equal(g["pot"], ref["pot"])
+
+
 def test_subset_targets_match_all_targets(og_mod):
     w = synth.mixture32k()
     rng = np.random.default_rng(5)
