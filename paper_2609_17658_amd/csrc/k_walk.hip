@@ -826,7 +826,9 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
         }
         const float dcx = f0 * k.h22 - xr, dcy = f1 * k.h22 - yr, dcz = f2 * k.h22 - zr;
         const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
-        const uint32_t ns = (cf & kWLeaf) ? n + 1 : w.a;
+        // a leaf's record holds its list tag (sign bit set) where an internal
+        // node's holds its skip (node indices stay below 2^31)
+        const uint32_t ns = (int32_t)w.a < 0 ? n + 1 : w.a;
         // the rare cases (a big leaf, offsets that may need the minimum
         // image) take the general path; the common visit below has no
         // branch of its own
@@ -900,7 +902,9 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
         list[cnt][lane] = entry;
         if (kSoft) lsoft[cnt][lane] = emono;
         cnt += (contrib || (open_here && (cf & kWLeaf) != 0)) ? 1u : 0u;
-        if (act && !open_here) next = ns;
+        // a lane past n is past all of n's subtree, so max() leaves it as
+        // it is, and moves an active lane that did not open n to skip(n)
+        next = open_here ? next : max(next, ns);
         // the lanes that opened n are those still at or before n; a leaf's
         // skip is n + 1; a skip always moves forward
         n = __ballot(next <= n) ? n + 1 : max(ns, n + 1);

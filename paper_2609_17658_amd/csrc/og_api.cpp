@@ -206,7 +206,9 @@ int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream
   uint64_t ntot = 0;
   for (auto &b : boxes) ntot += b.n;
   if (ntot > kCountMask) return fail(OG_EINVAL, "total particle count %llu exceeds 2^27-1", (unsigned long long)ntot);
-  if (node_cap_ > 0xfffffff0ull) return fail(OG_EINVAL, "node bound too large");
+  // the walks tell a leaf's record from an internal node's by the sign bit
+  // of the skip / tag word, so node indices stay below 2^31
+  if (node_cap_ > 0x7fffffffull) return fail(OG_EINVAL, "node bound too large");
   N = (uint32_t)ntot;
   node_cap = (uint32_t)node_cap_;
   stream = s;
