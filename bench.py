@@ -81,13 +81,20 @@ def walk_issue(walk_ms):
     for 4 cycles; 1024 SIMDs at 2.4 GHz.  From the profiled instruction count
     and this run's walk time."""
     try:
-        valu = float(walk_profile()["walk_valu_insts_per_launch"])
+        rec = walk_profile()
+        valu = float(rec["walk_valu_insts_per_launch"])
     except (KeyError, ValueError):
         return None
     busy = valu * 4 / (1024 * walk_ms * 1e-3 * 2.4e9)
-    return {"valu_insts_per_launch": valu, "valu_busy_frac": busy,
-            "note": "vector instructions x 4 cycles / SIMD cycles of the launch; 1 = vector issue saturated "
-                    "(an estimate: it assumes every wave64 vector instruction holds its SIMD for 4 cycles)"}
+    out = {"valu_insts_per_launch": valu, "valu_busy_frac": busy,
+           "note": "vector instructions x 4 cycles / SIMD cycles of the launch; 1 = vector issue saturated "
+                   "(an estimate: it assumes every wave64 vector instruction holds its SIMD for 4 cycles, "
+                   "so values slightly above 1 mean some take fewer)"}
+    try:
+        out["salu_insts_per_launch"] = float(rec["walk_salu_insts_per_launch"])
+    except (KeyError, ValueError):
+        pass
+    return out
 
 
 def git_hash():
