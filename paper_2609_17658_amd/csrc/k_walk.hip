@@ -270,8 +270,14 @@ __device__ inline double erfcx64(double u) {
   const auto q = cptr(c);
   const double t = fma(u, 2.0 / 3.0, -1.0);
   double y = q[0];
+  // y * t + c_i as one three-operand FMA with the coefficient read from the
+  // scalar registers (the compiler's two-operand form first copies every
+  // coefficient into vector registers: two moves per step)
 #pragma unroll
-  for (int i = 1; i < 26; ++i) y = fma(y, t, q[i]);
+  for (int i = 1; i < 26; ++i) {
+    const double ci = q[i];
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(y) : "v"(y), "v"(t), "s"(ci));
+  }
   return y;
 }
 
