@@ -682,7 +682,8 @@ __global__ __launch_bounds__(kThreads) void k_targets_map(const BoxDev *boxes, c
 // Walk records for the mixed-precision walk (see WNode).
 __global__ __launch_bounds__(kThreads) void k_wnodes(const BoxDev *boxes, int B, const Topo *topo,
                                                      const Mom32 *mom32, const uint32_t *first,
-                                                     const uint32_t *scalars, uint32_t node_cap, WNode *wn) {
+                                                     const uint32_t *scalars, uint32_t node_cap, WNode *wn,
+                                                     double4 *cen64) {
   const uint32_t tot = min(scalars[3], node_cap);
   for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
     const Topo t = topo[r];
@@ -708,6 +709,13 @@ __global__ __launch_bounds__(kThreads) void k_wnodes(const BoxDev *boxes, int B,
     w.a = leaf ? leaf_tag_bits(t.a, min(count, 8u), wrap) : t.a;
     w.cf = count | (leaf && count > 8u ? kWBig : 0u) | (leaf ? kWLeaf : 0u) | (wrap ? kWWrap : 0u);
     wn[r] = w;
+    // the FP64 walks' cube centre and side, in the expressions they used to
+    // evaluate at every visit (so the values are the same to the bit)
+    const double h = bx.L * 0x1p-21, half = ldexp(1.0, 20 - lev);
+    cen64[r] = make_double4(bx.lo[0] + ((double)(uint32_t)(t.corner & 0x1fffffull) + half) * h,
+                            bx.lo[1] + ((double)(uint32_t)((t.corner >> 21) & 0x1fffffull) + half) * h,
+                            bx.lo[2] + ((double)(uint32_t)((t.corner >> 42) & 0x1fffffull) + half) * h,
+                            ldexp(bx.L, -lev));
   }
 }
 
@@ -825,7 +833,7 @@ void launch_build(BuildArrays &A, hipStream_t s) {
                                               A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32, A.semax,
                                               A.semin);
   k_wnodes<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.mom32, A.first, A.scalars, A.node_cap,
-                                       A.wnode);
+                                       A.wnode, A.cen64);
 }
 
 // Active targets (see ActiveArrays).  Flags and the compaction run over the

@@ -54,6 +54,10 @@ __device__ inline Topo ld(const Topo *p) {
   t.b = q->b;
   return t;
 }
+__device__ inline double4 ld(const double4 *p) {
+  const auto q = cptr(p);
+  return make_double4(q->x, q->y, q->z, q->w);
+}
 __device__ inline Mom64 ld(const Mom64 *p) {
   const auto q = cptr(p);
   return Mom64{q->cx, q->cy, q->cz, q->m};
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
     const bool soft = kExt && A.seps != nullptr && bx.epsp != nullptr;
     const double ei = soft && valid ? A.seps[p] : bx.eps;
     const bool periodic = bx.periodic;
-    const double box = bx.box, h = bx.L * 0x1p-21;
+    const double box = bx.box;
     // A group whose targets all lie farther than r_cut from every face of
     // the periodic box (r_cut below a quarter of the box) needs no minimum
     // image below level 1: a node of side <= box/4 within reach of such a
@@ -434,11 +438,9 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
       const uint32_t ns = leaf ? n + 1 : t.a;
       const int lev = (int)(t.b >> kCountBits);
       const bool wrap = periodic && !(interior && lev >= 2);
-      const double side = ldexp(bx.L, -lev);
-      const double half = ldexp(1.0, 20 - lev);
-      const double c0 = bx.lo[0] + ((double)(uint32_t)(t.corner & 0x1fffffull) + half) * h;
-      const double c1 = bx.lo[1] + ((double)(uint32_t)((t.corner >> 21) & 0x1fffffull) + half) * h;
-      const double c2 = bx.lo[2] + ((double)(uint32_t)((t.corner >> 42) & 0x1fffffull) + half) * h;
+      // cube centre and side, computed once per build
+      const double4 cs = ld(A.cen64 + n);
+      const double side = cs.w, c0 = cs.x, c1 = cs.y, c2 = cs.z;
       bool open_int = false;
       if (next == n) {
         double dcx = c0 - xi.x, dcy = c1 - xi.y, dcz = c2 - xi.z;
@@ -959,7 +961,7 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
       aold = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     }
     const bool periodic = bx.periodic;
-    const double box = bx.box, h = bx.L * 0x1p-21;
+    const double box = bx.box;
     // as in the per-target FP64 walk: a group farther than r_cut from every
     // periodic face needs the minimum image only for the nodes of levels 0
     // and 1, and never for particle offsets (a particle more than half a box
@@ -983,11 +985,9 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
       const uint32_t ns = leaf ? n + 1 : t.a;
       const int lev = (int)(t.b >> kCountBits);
       const bool wrap = periodic && !(interior && lev >= 2);
-      const double side = ldexp(bx.L, -lev);
-      const double half = ldexp(1.0, 20 - lev);
-      const double c0 = bx.lo[0] + ((double)(uint32_t)(t.corner & 0x1fffffull) + half) * h;
-      const double c1 = bx.lo[1] + ((double)(uint32_t)((t.corner >> 21) & 0x1fffffull) + half) * h;
-      const double c2 = bx.lo[2] + ((double)(uint32_t)((t.corner >> 42) & 0x1fffffull) + half) * h;
+      // cube centre and side, computed once per build
+      const double4 cs = ld(A.cen64 + n);
+      const double side = cs.w, c0 = cs.x, c1 = cs.y, c2 = cs.z;
       bool live = false, open = false;
       double dx = 0.0, dy = 0.0, dz = 0.0;
       if (valid) {

@@ -85,6 +85,7 @@ void carve(Carver &c, BuildArrays &A, uint32_t n, uint32_t node_cap, int B, bool
   A.mom64 = c.take<Mom64>(node_cap);
   A.mom32 = c.take<Mom32>(node_cap);
   A.wnode = c.take<WNode>(node_cap);
+  A.cen64 = c.take<double4>(node_cap);
   A.first = c.take<uint32_t>(node_cap);
   A.skip = c.take<uint32_t>(node_cap);
   A.parent = c.take<uint32_t>(node_cap);
@@ -264,6 +265,7 @@ WalkArgs Forest::walk_args() const {
   W.topo = A.topo;
   W.mom32 = A.mom32;
   W.wnode = A.wnode;
+  W.cen64 = A.cen64;
   W.mom64 = A.mom64;
   W.part32 = A.part32;
   W.part64 = A.part64;

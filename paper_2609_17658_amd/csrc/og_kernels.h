@@ -41,6 +41,7 @@ struct BuildArrays {
   Mom64 *mom64;
   Mom32 *mom32;
   WNode *wnode;
+  double4 *cen64;  // per node: FP64 cube centre (x, y, z) and side (w), for the FP64 walks
   uint32_t *first, *skip, *parent, *nchild;
   uint32_t *lvl_cnt, *lvl_fill, *lvl_nodes;   // internal nodes bucketed by level
   uint32_t *scalars;          // [0] status [3] n_nodes [4] n [8..15] walk queues
@@ -88,6 +89,7 @@ struct WalkArgs {
   const Topo *topo;
   const Mom32 *mom32;
   const WNode *wnode;
+  const double4 *cen64;
   const Mom64 *mom64;
   const float4 *part32;
   const double4 *part64;
