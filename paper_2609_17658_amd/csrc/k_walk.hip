@@ -287,7 +287,10 @@ __device__ inline double erfcx64(double u) {
 
 // e: the pair's softening length (used by the kExt variants; the others
 // take the box's).
-template <bool kExt>
+// kTail: some pair may have u = r / (2 r_s) > 3 (r_cut > 6 r_s), past the
+// erfcx polynomial; without it the kernel carries no library erfc, whose
+// constants would otherwise hold vector registers for the whole walk.
+template <bool kExt, bool kTail = true>
 __device__ inline void pair64(double dx, double dy, double dz, double m, double e, const BoxDev &bx,
                               double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(off)
@@ -306,7 +309,7 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, double 
     const double r = sqrt(r2);
     const double u = r * (0.5 / bx.r_s);
     const double eu = exp(-u * u);
-    const double e = u <= 3.0 ? eu * erfcx64(u) : erfc(u);
+    const double e = (!kTail || u <= 3.0) ? eu * erfcx64(u) : erfc(u);
     S = e + kTwoOverSqrtPi * u * eu;
     pf = e;
   }
@@ -335,7 +338,7 @@ constexpr int kWalk64Cap = 4;    // list entries per lane
 // mass >= 0; a leaf entry has w = -1 and, in the bits of x, its first
 // particle (bits 0..31), count (32..62) and whether its particles' offsets
 // need the minimum image (bit 63).
-template <bool kExt>
+template <bool kExt, bool kTail>
 __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*lsoft)[64], uint32_t lane,
                                uint32_t p, const double4 &xi, double ei, bool soft, const BoxDev &bx,
                                uint32_t &cnt, double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
@@ -371,7 +374,7 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
         }
       }
       // one evaluation site, shared by both kinds of partner
-      if (use) pair64<kExt>(dx, dy, dz, m, es, bx, ax, ay, az, ph, ni);
+      if (use) pair64<kExt, kTail>(dx, dy, dz, m, es, bx, ax, ay, az, ph, ni);
     }
   }
   cnt = 0;
@@ -379,7 +382,7 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
 
 // Four waves per SIMD (a few registers spill to scratch) run faster than
 // the three the registers would otherwise allow.
-template <bool kExt>
+template <bool kExt, bool kTail>
 __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk64(WalkArgs A) {
 #pragma clang fp contract(off)
   __shared__ double4 lists[kWalk64Waves][kWalk64Cap][64];
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
     while (n < nend) {
       // room for this visit's entry
       if (__ballot(cnt >= (uint32_t)kWalk64Cap))
-        flush64<kExt>(A, list, lsoft, lane, p, xi, ei, soft, bx, cnt, ax, ay, az, ph, ni);
+        flush64<kExt, kTail>(A, list, lsoft, lane, p, xi, ei, soft, bx, cnt, ax, ay, az, ph, ni);
       const Topo t = ld(A.topo + n);
       const Mom64 mm = ld(A.mom64 + n);
       const bool leaf = (t.corner & kLeafBit) != 0;
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
       // a leaf's skip is n + 1; a skip always moves forward
       n = (leaf || __ballot(open_int) || t.a <= n) ? n + 1 : t.a;
     }
-    flush64<kExt>(A, list, lsoft, lane, p, xi, ei, soft, bx, cnt, ax, ay, az, ph, ni);
+    flush64<kExt, kTail>(A, list, lsoft, lane, p, xi, ei, soft, bx, cnt, ax, ay, az, ph, ni);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
@@ -939,7 +942,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
 // the result depends on the grouping.
 
 // FP64: the same arithmetic as the per-target FP64 walk, evaluated at the node.
-template <bool kExt>
+template <bool kExt, bool kTail>
 __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
 #pragma clang fp contract(off)
   const uint32_t lane = threadIdx.x & 63;
@@ -1016,7 +1019,7 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
       if (!__ballot(live)) {
         nn = nskip;
       } else if (!__ballot(open)) {
-        if (valid) pair64<kExt>(dx, dy, dz, mm.m, bx.eps, bx, ax, ay, az, ph, ni);
+        if (valid) pair64<kExt, kTail>(dx, dy, dz, mm.m, bx.eps, bx, ax, ay, az, ph, ni);
         nn = nskip;
       } else if (leaf) {
         const uint32_t f = t.a, cnt = t.b & kCountMask;
@@ -1029,7 +1032,7 @@ __global__ __launch_bounds__(256) void k_walkg64(WalkArgs A) {
             if (valid && f + base + j != p) {
               double ex = qx - xi.x, ey = qy - xi.y, ez = qz - xi.z;
               minimg3(ex, ey, ez, pwrap, box);
-              pair64<kExt>(ex, ey, ez, qm, bx.eps, bx, ax, ay, az, ph, ni);
+              pair64<kExt, kTail>(ex, ey, ez, qm, bx.eps, bx, ax, ay, az, ph, ni);
             }
           }
         }
@@ -1290,8 +1293,10 @@ void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
   if (W.group_lists) {
     if (precision == 0) {
       const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(3u * cus, (groups + 3) / 4));
-      if (W.ext) k_walkg64<true><<<blocks, 256, 0, s>>>(W);
-      else k_walkg64<false><<<blocks, 256, 0, s>>>(W);
+      if (W.ext && W.erfc_tail) k_walkg64<true, true><<<blocks, 256, 0, s>>>(W);
+      else if (W.ext) k_walkg64<true, false><<<blocks, 256, 0, s>>>(W);
+      else if (W.erfc_tail) k_walkg64<false, true><<<blocks, 256, 0, s>>>(W);
+      else k_walkg64<false, false><<<blocks, 256, 0, s>>>(W);
     } else {
       // one wave per workgroup, 4 KB of list each, 8 waves per SIMD
       const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(32u * cus, groups));
@@ -1308,8 +1313,10 @@ void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
   if (precision == 0) {
     // 4 waves per workgroup, 4 waves per SIMD
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(4u * cus, (groups + 3) / 4));
-    if (W.ext) k_walk64<true><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
-    else k_walk64<false><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
+    if (W.ext && W.erfc_tail) k_walk64<true, true><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
+    else if (W.ext) k_walk64<true, false><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
+    else if (W.erfc_tail) k_walk64<false, true><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
+    else k_walk64<false, false><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
   } else {
     // one wave per workgroup; LDS per wave = cap x 1 KB of lists
     const int cap = W.list_cap > 0 ? W.list_cap : walk_list_capacity();

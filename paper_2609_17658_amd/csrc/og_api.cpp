@@ -287,6 +287,10 @@ WalkArgs Forest::walk_args() const {
   W.semin = A.semin;
   if (A.seps) W.ext = 1;
   W.wide_nodes = (uint64_t)node_cap * sizeof(WNode) > 0xffffffffull ? 1 : 0;
+  // u = r / (2 r_s) < r_cut / (2 r_s) for every pair term (r < r_cut); a margin
+  // covers the rounding of u
+  for (const auto &b : hboxes)
+    if (b.cutoff && !(b.rcut * (0.5 / b.r_s) < 2.99)) W.erfc_tail = 1;
   return W;
 }
 

@@ -116,6 +116,7 @@ struct WalkArgs {
   const double *a_old;        // relative criterion: previous accelerations [n][3], caller order
   int wide_nodes;             // the node records span more than 4 GiB (64-bit record offsets)
   int no_interior;            // mixed walk: reduce every periodic offset (no raw form for interior groups)
+  int erfc_tail;              // FP64 walks: some box has r_cut / (2 r_s) >= 3 (library erfc past the polynomial)
 };
 void launch_walk(const WalkArgs &W, int precision, hipStream_t s);
 void launch_reset(uint32_t *word, hipStream_t s);
