@@ -360,9 +360,11 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
         const uint32_t i = first + j;
         use = i != p;
         const double4 s = A.part64[i];
-        dx = minimg(s.x - xi.x, wrap, bx.box);
-        dy = minimg(s.y - xi.y, wrap, bx.box);
-        dz = minimg(s.z - xi.z, wrap, bx.box);
+        dx = s.x - xi.x;
+        dy = s.y - xi.y;
+        dz = s.z - xi.z;
+        // a branch: leaves of interior groups (below level 1) need no image
+        minimg3(dx, dy, dz, wrap, bx.box);
         m = s.w;
         if (soft) {
           const double ej = A.seps[i];
