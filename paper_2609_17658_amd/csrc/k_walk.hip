@@ -285,6 +285,37 @@ __device__ inline double erfcx64(double u) {
   return y;
 }
 
+// exp(x) for the pair term's x = -u^2 <= 0.  Cody and Waite's reduction:
+// x = k ln2 + r with k = rint(x / ln2), |r| <= ln2/2, and ln2 in two parts
+// whose first has 29 significant bits, so k ln2_hi is exact.  exp(r) is
+// its Taylor series to r^13 (the truncation is below 5e-18 relative), one
+// three-operand FMA per term with the coefficient as a scalar operand, and
+// the result is scaled by 2^k (underflowing to 0 far below the doubles the
+// walk can reach; the clamp keeps r finite there).
+__constant__ double kExpTaylor[14] = {
+    1.6059043836821613e-10, 2.08767569878681e-09, 2.505210838544172e-08, 2.755731922398589e-07,
+    2.7557319223985893e-06, 2.48015873015873e-05, 0.0001984126984126984, 0.001388888888888889,
+    0.008333333333333333,   0.041666666666666664, 0.16666666666666666,   0.5,
+    1.0,                    1.0,
+};  // 1/13!, 1/12!, ..., 1/1!, 1/0!
+constexpr double kLn2Hi = 0x1.62e42ff000000p-1, kLn2Lo = -0x1.718432a1b0e26p-35, kLog2e = 1.4426950408889634;
+__device__ inline double exp_nonpos(double x) {
+  x = fmax(x, -1100.0);
+  const double kd = rint(x * kLog2e);
+  double r = fma(-kd, kLn2Hi, x);
+  r = fma(-kd, kLn2Lo, r);
+  const double *c = kExpTaylor;
+  asm volatile("" : "+s"(c));
+  const auto q = cptr(c);
+  double y = q[0];
+#pragma unroll
+  for (int i = 1; i < 14; ++i) {
+    const double ci = q[i];
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(y) : "v"(y), "v"(r), "s"(ci));
+  }
+  return ldexp(y, (int)kd);
+}
+
 // e: the pair's softening length (used by the kExt variants; the others
 // take the box's).
 // kTail: some pair may have u = r / (2 r_s) > 3 (r_cut > 6 r_s), past the
@@ -308,7 +339,7 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, double 
   if (bx.cutoff) {
     const double r = sqrt(r2);
     const double u = r * (0.5 / bx.r_s);
-    const double eu = exp(-u * u);
+    const double eu = exp_nonpos(-u * u);
     const double e = (!kTail || u <= 3.0) ? eu * erfcx64(u) : erfc(u);
     S = e + kTwoOverSqrtPi * u * eu;
     pf = e;
