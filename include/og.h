@@ -289,17 +289,28 @@ typedef struct og_server og_server;
 
 int og_server_create(size_t hbm_budget_bytes, int32_t max_slots, og_server **out);
 /* Submit a request; its pos/mass/acc/pot are device buffers owned by the
- * caller and must stay valid until the ticket is released.  OG_EBUSY when
- * the request can never fit the budget or the pending queue is full. */
+ * caller and must stay valid until the ticket is released.  The request's
+ * params.stream (hipStream_t, NULL = the null stream) is the stream its
+ * inputs are written on: submit records an event there and the request's
+ * build waits for it, so the caller need not synchronise before submitting.
+ * The request itself runs on a slot stream of the server's; acc/pot are
+ * valid once og_server_poll reports done or og_server_wait returns.
+ * OG_EBUSY when the request can never fit the budget or the pending queue
+ * is full.  A request that fails after submission (a launch error, a
+ * position outside the box, a forced fault) is reported by poll/wait with
+ * its error code; the server keeps serving the others. */
 int og_server_submit(og_server *s, const og_box *req, uint64_t *ticket);
 /* Progress the server (admit, launch, retire) without blocking. */
 int og_server_progress(og_server *s);
 /* done = 1 once acc/pot are written; times in seconds on the server's
  * monotonic clock (arrival = submit call, done = completion observed). */
 int og_server_poll(og_server *s, uint64_t ticket, int32_t *done, double *t_arrive, double *t_done);
-/* Block until the ticket is done (progressing the server meanwhile). */
+/* Block until the ticket is done (progressing the server meanwhile).  May
+ * run concurrently with calls on other threads, including a release of the
+ * same ticket (the wait then returns OG_ENOTFOUND or the request's result). */
 int og_server_wait(og_server *s, uint64_t ticket);
-/* Free the request's resident tree and slot. */
+/* Free the request's resident tree and its arena range (waiting for a
+ * request still on the device). */
 int og_server_release(og_server *s, uint64_t ticket);
 /* Bytes currently reserved by admitted requests, and counts. */
 int og_server_stats(const og_server *s, size_t *reserved, int32_t *in_flight, int32_t *pending);

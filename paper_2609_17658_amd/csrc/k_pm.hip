@@ -19,6 +19,7 @@
 //   4. inverse FFTs, then CIC interpolation at the particles.
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 
 #include "og_pm.h"
 
@@ -403,10 +404,17 @@ inline uint32_t blocks_for(uint64_t work, uint32_t threads, uint32_t cap) {
 
 }  // namespace
 
-// Lines per workgroup: up to 16, at most n, and a tile plus twiddles within 64 KB of LDS.
+// Lines per workgroup: up to 16, at most n, and a tile plus twiddles within
+// 64 KB of LDS (16 up to n = 128, then 8, 4 and 2 at n = 256, 512 and
+// 1024).  OG_FFT_LINES=k (a power of two, 1..16), read at each launch,
+// caps it, so that the tests run every width the library can pick on small
+// meshes.
 int fft_lines_per_block(int n) {
   int tl = 16;
   while (tl > 1 && (tl > n || (size_t)tl * n * sizeof(double2) + (size_t)(n / 2) * sizeof(double2) > 65536)) tl >>= 1;
+  const char *e = getenv("OG_FFT_LINES");
+  const int cap = e ? atoi(e) : 0;
+  if (cap >= 1 && cap <= 16 && (cap & (cap - 1)) == 0 && cap < tl) tl = cap;
   return tl;
 }
 

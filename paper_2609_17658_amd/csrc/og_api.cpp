@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -47,6 +49,21 @@ bool is_device_ptr(const void *p) {
     return false;
   }
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+bool fault_fires(FaultKind k) {
+  static std::mutex mu;
+  static std::string seen[2];
+  static long count[2] = {0, 0};
+  const char *v = std::getenv(k == kFaultAlloc ? "OG_FAULT_ALLOC" : "OG_FAULT_LAUNCH");
+  const std::string cur = v ? v : "";
+  std::lock_guard<std::mutex> lk(mu);
+  if (cur != seen[k]) {
+    seen[k] = cur;
+    count[k] = 0;
+  }
+  const long at = cur.empty() ? 0 : std::strtol(cur.c_str(), nullptr, 10);
+  return at > 0 && ++count[k] == at;
 }
 
 // ---------------------------------------------------------- layout --
@@ -232,6 +249,7 @@ int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream
     mem = workspace;
     own = false;
   } else {
+    if (fault_fires(kFaultAlloc)) return fail(OG_ENOMEM, "forced failure of the tree allocation (OG_FAULT_ALLOC)");
     hipError_t e = hipMalloc(&mem, bytes);
     if (e != hipSuccess) {
       mem = nullptr;
@@ -253,6 +271,7 @@ int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream
 }
 
 int Forest::build() {
+  if (fault_fires(kFaultLaunch)) return fail(OG_EDEVICE, "forced failure of the build launch (OG_FAULT_LAUNCH)");
   launch_build(A, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "build launch");
@@ -296,6 +315,7 @@ WalkArgs Forest::walk_args() const {
 
 int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_override, int64_t *nint,
                      const double *a_old) {
+  if (fault_fires(kFaultLaunch)) return fail(OG_EDEVICE, "forced failure of the walk launch (OG_FAULT_LAUNCH)");
   WalkArgs W = walk_args();
   W.a_old = a_old;
   W.n_groups = n_groups;
@@ -323,6 +343,8 @@ int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M,
   };
   Carver c;
   plan(c);
+  if (fault_fires(kFaultLaunch)) return fail(OG_EDEVICE, "forced failure of the walk launch (OG_FAULT_LAUNCH)");
+  if (fault_fires(kFaultAlloc)) return fail(OG_ENOMEM, "forced failure of the target scratch (OG_FAULT_ALLOC)");
   void *tmp = nullptr;
   hipError_t e = hipMallocAsync(&tmp, c.off + 256, s);
   if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(targets)");
@@ -364,6 +386,8 @@ int Forest::walk_active(int prec, hipStream_t s, const int8_t *bin, int32_t leve
   };
   Carver c;
   plan(c);
+  if (fault_fires(kFaultLaunch)) return fail(OG_EDEVICE, "forced failure of the walk launch (OG_FAULT_LAUNCH)");
+  if (fault_fires(kFaultAlloc)) return fail(OG_ENOMEM, "forced failure of the active-set scratch (OG_FAULT_ALLOC)");
   void *tmp = nullptr;
   hipError_t e = hipMallocAsync(&tmp, c.off + 256, s);
   if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(active)");

@@ -22,6 +22,14 @@ int hip_fail(hipError_t e, const char *what);
 // they are the same stream).  OG_OK or OG_EDEVICE.
 int order_after(hipStream_t waiter, hipStream_t producer);
 bool is_device_ptr(const void *p);
+// Host-forced faults, for tests of the error paths; nothing is enqueued when
+// one fires.  OG_FAULT_ALLOC=k makes the k-th device allocation of the
+// library (tree workspace, server arena, a served request's admission,
+// target and active-set scratch, mesh) fail with OG_ENOMEM; OG_FAULT_LAUNCH=k
+// makes the k-th enqueue of a build or a walk fail with OG_EDEVICE.  The
+// count restarts whenever the variable's value changes.
+enum FaultKind { kFaultAlloc = 0, kFaultLaunch = 1 };
+bool fault_fires(FaultKind k);
 int check_params(const og_params *p, int64_t N, double box, bool need_stream_fields);
 void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, double box, const og_params &p,
               uint32_t p_off);

@@ -49,6 +49,10 @@ int og_pm_create(int32_t n_grid, double box, double G, double r_s, void *stream,
   p->G = G;
   p->r_s = r_s;
   p->stream = (hipStream_t)stream;
+  if (fault_fires(kFaultAlloc)) {
+    delete p;
+    return fail(OG_ENOMEM, "forced failure of the mesh allocation (OG_FAULT_ALLOC)");
+  }
   hipError_t e = hipMalloc(&p->mem, pm_bytes(n_grid));
   if (e != hipSuccess) {
     delete p;

@@ -9,11 +9,16 @@
 // first-come first-served.  A request's completion is observed through an
 // event; its slot is then free for the next request while its tree stays
 // resident (and its memory reserved) until the caller releases the ticket.
+//
+// Inputs are ordered after the caller's stream: submit records an event on
+// the request's params.stream, and the slot stream waits for it before the
+// build, so positions still being written there are read only once written.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -72,6 +77,26 @@ struct Arena {
 
 enum State { kPending = 0, kRunning = 1, kDone = 2, kFailed = 3 };
 
+// An event shared between the request and any thread waiting on it outside
+// the server's lock, so that a concurrent release cannot destroy it under
+// the waiter: it is destroyed when the last holder lets go.
+struct Event {
+  hipEvent_t e = nullptr;
+  ~Event() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+using EventRef = std::shared_ptr<Event>;
+
+EventRef make_event() {
+  auto ev = std::make_shared<Event>();
+  if (hipEventCreateWithFlags(&ev->e, hipEventDisableTiming) != hipSuccess) {
+    ev->e = nullptr;
+    return nullptr;
+  }
+  return ev;
+}
+
 struct Request {
   og_box box;
   size_t bytes = 0, off = 0;
@@ -81,7 +106,8 @@ struct Request {
   int error = OG_OK;
   double t_arrive = 0, t_done = 0;
   og_tree *tree = nullptr;
-  hipEvent_t ev = nullptr;
+  EventRef ready;  // recorded on the caller's stream at submit
+  EventRef done;   // recorded on the slot stream after the walk
 };
 
 }  // namespace
@@ -107,7 +133,7 @@ int og_server::retire_locked() {
   for (auto &kv : reqs) {
     Request &r = kv.second;
     if (r.state != kRunning) continue;
-    hipError_t e = hipEventQuery(r.ev);
+    hipError_t e = hipEventQuery(r.done->e);
     if (e == hipErrorNotReady) continue;
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -141,6 +167,13 @@ int og_server::admit_locked() {
       }
     if (slot < 0) return OG_OK;                      // wait for a slot
     if (reserved + r.bytes > budget) return OG_OK;   // wait for memory
+    if (fault_fires(kFaultAlloc)) {                  // forced: this request fails, the rest go on
+      pending.pop_front();
+      r.error = fail(OG_ENOMEM, "forced failure of the admission (OG_FAULT_ALLOC)");
+      r.state = kFailed;
+      r.t_done = now_s();
+      continue;
+    }
     size_t off = 0;
     if (!arena.alloc(r.bytes, off)) return OG_OK;    // fragmented: wait for releases
     pending.pop_front();
@@ -152,10 +185,16 @@ int og_server::admit_locked() {
     p.stream = streams[slot];
     p.workspace = static_cast<char *>(mem) + off;
     p.workspace_bytes = r.bytes;
-    int rc = og_tree_build(r.box.pos, r.box.mass, r.box.N, r.box.box, &p, &r.tree);
+    int rc = hipStreamWaitEvent(streams[slot], r.ready->e, 0) == hipSuccess ? OG_OK
+                                                                           : hip_fail(hipGetLastError(), "hipStreamWaitEvent");
+    if (rc == OG_OK) rc = og_tree_build(r.box.pos, r.box.mass, r.box.N, r.box.box, &p, &r.tree);
     if (rc == OG_OK) rc = og_tree_force(r.tree, nullptr, r.box.acc, r.box.pot);
-    if (rc == OG_OK && hipEventRecord(r.ev, streams[slot]) != hipSuccess) rc = OG_EDEVICE;
+    if (rc == OG_OK && hipEventRecord(r.done->e, streams[slot]) != hipSuccess) rc = OG_EDEVICE;
     if (rc != OG_OK) {
+      // whatever was enqueued before the failure must finish before the
+      // request's arena range can be handed to another request
+      (void)hipStreamSynchronize(streams[slot]);
+      (void)hipGetLastError();
       r.error = rc;
       r.state = kFailed;
       r.t_done = now_s();
@@ -178,6 +217,10 @@ int og_server_create(size_t hbm_budget_bytes, int32_t max_slots, og_server **out
   og_server *s = new (std::nothrow) og_server();
   if (!s) return fail(OG_ENOMEM, "host allocation");
   s->budget = hbm_budget_bytes;
+  if (fault_fires(kFaultAlloc)) {
+    delete s;
+    return fail(OG_ENOMEM, "forced failure of the server arena (OG_FAULT_ALLOC)");
+  }
   hipError_t e = hipMalloc(&s->mem, hbm_budget_bytes);
   if (e != hipSuccess) {
     delete s;
@@ -220,9 +263,15 @@ int og_server_submit(og_server *s, const og_box *req, uint64_t *ticket) {
   r.box = *req;
   r.bytes = bytes;
   r.t_arrive = now_s();
-  if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) {
+  r.ready = make_event();
+  r.done = make_event();
+  if (!r.ready || !r.done) {
     s->reqs.erase(tk);
     return hip_fail(hipGetLastError(), "hipEventCreate");
+  }
+  if (hipEventRecord(r.ready->e, (hipStream_t)req->params.stream) != hipSuccess) {
+    s->reqs.erase(tk);
+    return hip_fail(hipGetLastError(), "hipEventRecord(caller stream)");
   }
   s->pending.push_back(tk);
   s->retire_locked();
@@ -256,7 +305,7 @@ int og_server_poll(og_server *s, uint64_t ticket, int32_t *done, double *t_arriv
 int og_server_wait(og_server *s, uint64_t ticket) {
   if (!s) return fail(OG_EINVAL, "server is NULL");
   while (true) {
-    hipEvent_t ev = nullptr;
+    EventRef ev;  // held outside the lock: a concurrent release cannot destroy it
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->retire_locked();
@@ -266,18 +315,18 @@ int og_server_wait(og_server *s, uint64_t ticket) {
       const Request &r = it->second;
       if (r.state == kDone) return OG_OK;
       if (r.state == kFailed) return fail(r.error, "request failed");
-      if (r.state == kRunning) ev = r.ev;
+      if (r.state == kRunning) ev = r.done;
       else if (s->in_flight > 0) {
         // pending: wait for any running request to finish
         for (auto &kv : s->reqs)
           if (kv.second.state == kRunning) {
-            ev = kv.second.ev;
+            ev = kv.second.done;
             break;
           }
       }
     }
     if (ev) {
-      hipError_t e = hipEventSynchronize(ev);
+      hipError_t e = hipEventSynchronize(ev->e);
       if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     } else {
       // pending with nothing running: memory is held by done, unreleased requests
@@ -294,7 +343,7 @@ int og_server_release(og_server *s, uint64_t ticket) {
   if (it == s->reqs.end()) return fail(OG_ENOTFOUND, "unknown ticket");
   Request &r = it->second;
   if (r.state == kRunning) {
-    (void)hipEventSynchronize(r.ev);
+    (void)hipEventSynchronize(r.done->e);
     s->retire_locked();
   }
   if (r.state == kPending) {
@@ -310,8 +359,7 @@ int og_server_release(og_server *s, uint64_t ticket) {
       s->reserved -= (r.bytes + 255) & ~(size_t)255;
     }
   }
-  if (r.ev) (void)hipEventDestroy(r.ev);
-  s->reqs.erase(it);
+  s->reqs.erase(it);  // its events go with the last holder
   s->admit_locked();
   return OG_OK;
 }
@@ -329,10 +377,9 @@ int og_server_stats(const og_server *cs, size_t *reserved, int32_t *in_flight, i
 int og_server_destroy(og_server *s) {
   if (!s) return OG_OK;
   for (auto st : s->streams) (void)hipStreamSynchronize(st);
-  for (auto &kv : s->reqs) {
+  for (auto &kv : s->reqs)
     if (kv.second.tree) og::tree_free_nosync(kv.second.tree);
-    if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
-  }
+  s->reqs.clear();
   for (auto st : s->streams) (void)hipStreamDestroy(st);
   if (s->mem) (void)hipFree(s->mem);
   delete s;

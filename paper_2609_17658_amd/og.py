@@ -451,13 +451,18 @@ class Server:
         self._keep = {}
 
     def submit(self, pos, mass, box, params, precision="mixed", group_max=0, walk_list_cap=0,
-               acc=None, pot=None):
+               acc=None, pot=None, stream=None):
+        """stream: where pos/mass are written (default: torch's current
+        stream); the request's build waits for the work enqueued there."""
         import torch
         if acc is None:
             acc = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
         if pot is None:
             pot = torch.empty(pos.shape[0], dtype=torch.float64, device=pos.device)
-        p = make_params(params, precision=precision, group_max=group_max, walk_list_cap=walk_list_cap)
+        if stream is None:
+            stream = torch.cuda.current_stream(pos.device)
+        p = make_params(params, precision=precision, group_max=group_max, walk_list_cap=walk_list_cap,
+                        stream=stream)
         t = og_server_submit(self.handle, box_struct(pos, mass, box, p, acc, pot))
         self._keep[t] = (pos, mass, acc, pot)
         return t

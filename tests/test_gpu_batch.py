@@ -2,7 +2,10 @@
 size and parameters.  Each box's result must equal the result of building
 and walking that box alone (bitwise: the same per-lane walk and the same
 arithmetic), for the eager path and for replays of the captured graph;
-replays re-read positions, so a changed input gives the changed result."""
+replays re-read positions, so a changed input gives the changed result.
+Every box is also checked on all its targets against the FP64 oracle at its
+own parameters: FP64 interaction counts equal and |da|/|a| <= 1e-11 per
+target; mixed median <= 1e-3 and p99 <= 1e-2 per box."""
 import sys
 
 import numpy as np
@@ -45,6 +48,24 @@ def _boxes(n_boxes, seed, nmin=50, nmax=6000, periodic=True):
     return items
 
 
+def _oracle(oracle_mod, pos, mass, box, prm):
+    op = oracle_mod.Params(**{k: prm[k] for k in ("G", "eps", "r_s", "r_cut", "theta", "periodic",
+                                                  "leaf_max")})
+    return oracle_mod.tree_force(pos, mass, box, op)
+
+
+def _check_vs_oracle(a, p, ref, prec, what):
+    ra, rp, _ = ref
+    e = np.linalg.norm(a - ra, axis=1) / np.maximum(np.linalg.norm(ra, axis=1), 1e-300)
+    if prec == "fp64":
+        assert e.max() <= 1e-11, (what, e.max())
+        assert np.all(np.abs(p - rp) <= 1e-12 * np.abs(rp)), what
+    else:
+        assert np.median(e) <= 1e-3 and np.percentile(e, 99) <= 1e-2, (what, np.median(e),
+                                                                      np.percentile(e, 99))
+    return e
+
+
 def _alone(og, pos, mass, box, prm, prec):
     tp = torch.as_tensor(pos, device="cuda")
     tm = torch.as_tensor(mass, device="cuda")
@@ -56,7 +77,7 @@ def _alone(og, pos, mass, box, prm, prec):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_batch_equals_alone(og_mod, prec):
+def test_batch_equals_alone(og_mod, oracle_mod, prec):
     items = _boxes(24, 11)
     _note("batch of %d boxes, %d particles (%s)" % (len(items), sum(i[0].shape[0] for i in items), prec))
     dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), b, prm)
@@ -65,14 +86,45 @@ def test_batch_equals_alone(og_mod, prec):
     outs = bt.force()
     torch.cuda.synchronize()
     assert bt.status() == 0
-    for (pos, mass, box, prm), (a, p) in zip(items, outs):
+    for b, ((pos, mass, box, prm), (a, p)) in enumerate(zip(items, outs)):
         ra, rp = _alone(og_mod, pos, mass, box, prm, prec)
         assert np.array_equal(a.cpu().numpy(), ra)
         assert np.array_equal(p.cpu().numpy(), rp)
+        _check_vs_oracle(ra, rp, _oracle(oracle_mod, pos, mass, box, prm), prec, "box %d" % b)
     bt.close()
 
 
-def test_batch_mixed_kinds_matches_alone(og_mod):
+def test_batch512_recipe_vs_oracle(og_mod, oracle_mod):
+    """The first 96 boxes of the 512-box recipe (N log-uniform in
+    [1e3, 2e5], per-box seeds), mixed form, graph replay: every target of
+    every box against the FP64 oracle; FP64 form on every fourth box."""
+    ws = synth.batch512(n_boxes=96)  # the first 96 boxes of the 512-box draw
+    _note("batch512 recipe, %d boxes, %d particles" % (len(ws), sum(w.pos.shape[0] for w in ws)))
+    dev = [(torch.as_tensor(w.pos, device="cuda"), torch.as_tensor(w.mass, device="cuda"), w.box,
+            w.params.as_dict()) for w in ws]
+    refs = [_oracle(oracle_mod, w.pos, w.mass, w.box, w.params.as_dict()) for w in ws]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bt = og_mod.Batch(dev, stream=stream, precision="mixed")
+        outs = bt.replay()
+        stream.synchronize()
+    assert bt.status() == 0
+    worst = 0.0
+    for b, ((a, p), ref) in enumerate(zip(outs, refs)):
+        e = _check_vs_oracle(a.cpu().numpy(), p.cpu().numpy(), ref, "mixed", "box %d" % b)
+        worst = max(worst, float(np.percentile(e, 99)))
+    _note("  mixed: worst per-box p99 %.3g" % worst)
+    bt.close()
+    sub = dev[::4]
+    bt = og_mod.Batch(sub, stream=torch.cuda.current_stream(), precision="fp64")
+    outs = bt.force()
+    torch.cuda.synchronize()
+    for b, ((a, p), ref) in enumerate(zip(outs, refs[::4])):
+        _check_vs_oracle(a.cpu().numpy(), p.cpu().numpy(), ref, "fp64", "fp64 box %d" % (4 * b))
+    bt.close()
+
+
+def test_batch_mixed_kinds_matches_alone(og_mod, oracle_mod):
     """Periodic and open boxes in one batch (generic walk variant)."""
     items = _boxes(10, 12, periodic=False)
     dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), b, prm)
@@ -81,7 +133,7 @@ def test_batch_mixed_kinds_matches_alone(og_mod):
         bt = og_mod.Batch(dev, stream=torch.cuda.current_stream(), precision=prec)
         outs = bt.force()
         torch.cuda.synchronize()
-        for (pos, mass, box, prm), (a, p) in zip(items, outs):
+        for b, ((pos, mass, box, prm), (a, p)) in enumerate(zip(items, outs)):
             ra, rp = _alone(og_mod, pos, mass, box, prm, prec)
             a = a.cpu().numpy()
             if prec == "fp64":
@@ -89,6 +141,7 @@ def test_batch_mixed_kinds_matches_alone(og_mod):
             else:
                 e = np.linalg.norm(a - ra, axis=1) / np.maximum(np.linalg.norm(ra, axis=1), 1e-300)
                 assert np.median(e) <= 1e-6 and e.max() <= 1e-3
+            _check_vs_oracle(a, p.cpu().numpy(), _oracle(oracle_mod, pos, mass, box, prm), prec, "box %d" % b)
         bt.close()
 
 

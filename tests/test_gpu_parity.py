@@ -136,8 +136,8 @@ def test_tree_bit_exact_and_fp64_walk(og_mod, oracle_mod, case):
     acc, pot, nint = oracle_mod.walk(ot)
     assert np.array_equal(g["nint"], nint)
     e = rel_err(g["acc"], acc)
-    _note("  fp64 walk: max rel err %.3g, median %.3g" % (e.max(), np.median(e)))
-    assert e.max() <= 1e-11 or (np.percentile(e, 99.9) <= 1e-12 and e.max() <= 1e-9)
+    _note("  fp64 walk %s: max rel err %.3g, median %.3g" % (name, e.max(), np.median(e)))
+    assert e.max() <= 1e-11
     assert np.all(np.abs(g["pot"] - pot) <= 1e-12 * np.abs(pot) + 1e-300)
 
 
@@ -160,8 +160,13 @@ def test_mixed_walk_error(og_mod, oracle_mod, case):
     assert np.percentile(e, 99) <= 1e-2
     # FP32 decisions may flip a few opening/cutoff tests, no more
     assert (g["nint"] != nint).mean() <= 0.01
-    pe = np.abs(g["pot"] - pot) / np.abs(pot).max()
-    assert np.median(pe) <= 1e-4
+    # the potential is a sum of terms of one sign (no cancellation): the
+    # same per-target bar as the force
+    okp = np.abs(pot) > 0
+    pe = np.abs(g["pot"][okp] - pot[okp]) / np.abs(pot[okp])
+    _note("  mixed potential: median %.3g p99 %.3g" % (np.median(pe), np.percentile(pe, 99)))
+    assert np.median(pe) <= 1e-3
+    assert np.percentile(pe, 99) <= 1e-2
 
 
 def test_group_size_does_not_change_results(og_mod):
@@ -387,3 +392,39 @@ def test_mixed_walk_groups_across_the_periodic_boundary(og_mod, oracle_mod):
     e = rel_err(a.cpu().numpy()[tg], acc)
     _note("  median %.3g max %.3g" % (np.median(e), e.max()))
     assert e.max() <= 1e-2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_og_tree_force_plain_call(og_mod, oracle_mod, prec):
+    """og_tree_build + og_tree_force exactly as the C ABI names them (no
+    options struct): the tree's own precision and stream, all targets, then
+    a subset; checked against the oracle."""
+    import ctypes
+    _, pos, mass, box, prm = CASES[0]
+    lib = og_mod.load()
+    params = og_mod.make_params(prm, precision=prec, stream=torch.cuda.current_stream())
+    tp, tm = _dev(pos), _dev(mass)
+    h = og_mod.og_tree_build(tp, tm, pos.shape[0], box, params)
+    n = pos.shape[0]
+    acc = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    pot = torch.empty(n, dtype=torch.float64, device="cuda")
+    assert lib.og_tree_force(h, None, ctypes.c_void_p(acc.data_ptr()), ctypes.c_void_p(pot.data_ptr())) == 0
+    idx = torch.as_tensor(np.arange(5, n, 37), dtype=torch.int64, device="cuda")
+    sub = torch.empty((idx.numel(), 3), dtype=torch.float64, device="cuda")
+    tg = og_mod.og_targets(ctypes.c_void_p(idx.data_ptr()), int(idx.numel()))
+    assert lib.og_tree_force(h, ctypes.byref(tg), ctypes.c_void_p(sub.data_ptr()), None) == 0
+    torch.cuda.synchronize()
+    assert og_mod.og_tree_status(h) == 0
+    og_mod.og_tree_free(h)
+    ra, rp, _ = oracle_mod.tree_force(pos, mass, box, oracle_params(oracle_mod, prm))
+    e = rel_err(acc.cpu().numpy(), ra)
+    es = rel_err(sub.cpu().numpy(), ra[np.arange(5, n, 37)])
+    _note("og_tree_force %s: max %.3g median %.3g; subset max %.3g" % (prec, e.max(), np.median(e), es.max()))
+    if prec == "fp64":
+        assert e.max() <= 1e-11 and es.max() <= 1e-11
+        assert np.all(np.abs(pot.cpu().numpy() - rp) <= 1e-12 * np.abs(rp))
+    else:
+        assert np.median(e) <= 1e-3 and np.percentile(e, 99) <= 1e-2
+        assert np.median(es) <= 1e-3 and np.percentile(es, 99) <= 1e-2
+    # the subset entries are bitwise the full call's
+    assert np.array_equal(sub.cpu().numpy(), acc.cpu().numpy()[np.arange(5, n, 37)])

@@ -63,6 +63,49 @@ def test_pm_matches_oracle(og_mod, n_grid, N, box, G):
     m.close()
 
 
+def test_pm_256_eight_line_tiles_match_oracle(og_mod):
+    """n_grid = 256: the FFT passes take 8 lines per workgroup (the smaller
+    meshes take 16)."""
+    from oracle import pm as opm
+    pos, mass = _particles(120000, 256)
+    r_s = 1.25 / 256
+    _note("pm n_grid=256 N=120000 (8-line FFT tiles)")
+    a_o, p_o = opm.long_range(pos, mass, 1.0, 256, 1.0, r_s)
+    m = og_mod.PM(256, 1.0, 1.0, r_s, stream=torch.cuda.current_stream())
+    acc, pot = m.force(_dev(pos), _dev(mass))
+    torch.cuda.synchronize()
+    a, p = acc.cpu().numpy(), pot.cpu().numpy()
+    _note("  max |da|/max|a| %.3g" % (np.abs(a - a_o).max() / np.abs(a_o).max()))
+    assert np.abs(a - a_o).max() <= 1e-10 * np.abs(a_o).max()
+    assert np.abs(p - p_o).max() <= 1e-10 * np.abs(p_o).max()
+    m.close()
+
+
+@pytest.mark.parametrize("n_grid", [64, 128])
+def test_pm_every_fft_tile_width(og_mod, n_grid, monkeypatch):
+    """OG_FFT_LINES caps the lines per FFT workgroup, so the 8-, 4-, 2- and
+    1-line tiles (the larger meshes' widths, and one below) run on small
+    meshes: each is bitwise the 16-line result (the same butterflies per
+    line) and within 1e-10 of the oracle."""
+    from oracle import pm as opm
+    pos, mass = _particles(30000, n_grid + 1)
+    r_s = 1.25 / n_grid
+    a_o, p_o = opm.long_range(pos, mass, 1.0, n_grid, 1.0, r_s)
+    m = og_mod.PM(n_grid, 1.0, 1.0, r_s, stream=torch.cuda.current_stream())
+    ref_a, ref_p = m.force(_dev(pos), _dev(mass))
+    for lines in (8, 4, 2, 1):
+        _note("pm n_grid=%d with %d-line FFT tiles" % (n_grid, lines))
+        monkeypatch.setenv("OG_FFT_LINES", str(lines))
+        acc, pot = m.force(_dev(pos), _dev(mass))
+        torch.cuda.synchronize()
+        monkeypatch.delenv("OG_FFT_LINES")
+        assert torch.equal(acc, ref_a) and torch.equal(pot, ref_p), lines
+        a, p = acc.cpu().numpy(), pot.cpu().numpy()
+        assert np.abs(a - a_o).max() <= 1e-10 * np.abs(a_o).max()
+        assert np.abs(p - p_o).max() <= 1e-10 * np.abs(p_o).max()
+    m.close()
+
+
 def test_pm_wraps_positions_and_accumulates(og_mod):
     pos, mass = _particles(4000, 5)
     m = og_mod.PM(32, 1.0, 1.0, 1.25 / 32, stream=torch.cuda.current_stream())

@@ -1,8 +1,10 @@
 """Serving: requests of different sizes admitted by device-memory footprint
 as slots and memory free up, overlapping on the device.  Each request's
 result must be the same alone and in the mix (bitwise: same kernels, same
-tree, same per-lane walk), and the admitted footprint must never exceed the
-budget."""
+tree, same per-lane walk), must match the FP64 oracle at its own parameters
+(FP64: interaction counts equal and |da|/|a| <= 1e-11 per target; mixed:
+median <= 1e-3 and p99 <= 1e-2), and the admitted footprint must never
+exceed the budget."""
 import sys
 import time
 
@@ -40,6 +42,36 @@ def _requests(k, seed, nmin=2000, nmax=60000):
     return out
 
 
+_ORACLE = {}
+
+
+def _oracle(oracle_mod, key, pos, mass, prm, targets=None):
+    """Oracle acc/pot/counts of one request (cached: both precisions use it)."""
+    if key not in _ORACLE:
+        op = oracle_mod.Params(**{k: prm[k] for k in ("G", "eps", "r_s", "r_cut", "theta", "periodic",
+                                                      "leaf_max")})
+        _ORACLE[key] = oracle_mod.tree_force(pos, mass, 1.0, op, targets=targets)
+    return _ORACLE[key]
+
+
+def _check_vs_oracle(a, p, nint, ref, prec, what):
+    ra, rp, rn = ref
+    e = np.linalg.norm(a - ra, axis=1) / np.maximum(np.linalg.norm(ra, axis=1), 1e-300)
+    _note("  %s %s: median %.3g p99 %.3g max %.3g" % (what, prec, np.median(e), np.percentile(e, 99), e.max()))
+    if prec == "fp64":
+        assert e.max() <= 1e-11, what
+        assert np.all(np.abs(p - rp) <= 1e-12 * np.abs(rp)), what
+        if nint is not None:
+            assert np.array_equal(nint, rn), what
+    else:
+        assert np.median(e) <= 1e-3 and np.percentile(e, 99) <= 1e-2, what
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
 def _alone(og, pos, mass, prm, prec):
     t = og.Tree(torch.as_tensor(pos, device="cuda"), torch.as_tensor(mass, device="cuda"), 1.0, prm,
                 stream=torch.cuda.current_stream())
@@ -50,8 +82,10 @@ def _alone(og, pos, mass, prm, prec):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_served_equals_alone_and_budget_respected(og_mod, prec):
+def test_served_equals_alone_and_budget_respected(og_mod, oracle_mod, prec):
     reqs = _requests(14, 21)
+    _note("serving %d requests (%s), N %d..%d" % (len(reqs), prec, min(r[0].shape[0] for r in reqs),
+                                                   max(r[0].shape[0] for r in reqs)))
     p0 = og_mod.make_params(reqs[0][2])
     sizes = [og_mod.og_tree_workspace_bound(r[0].shape[0], p0) for r in reqs]
     budget = int(max(sizes) * 2.2)          # forces queueing
@@ -75,6 +109,8 @@ def test_served_equals_alone_and_budget_respected(og_mod, prec):
                 ra, rp = _alone(og_mod, reqs[i][0], reqs[i][1], reqs[i][2], prec)
                 assert np.array_equal(a.cpu().numpy(), ra), i
                 assert np.array_equal(p.cpu().numpy(), rp), i
+                ref = _oracle(oracle_mod, ("r21", i), reqs[i][0], reqs[i][1], reqs[i][2])
+                _check_vs_oracle(a.cpu().numpy(), p.cpu().numpy(), None, ref, prec, "request %d" % i)
         time.sleep(0.001)
     assert len(done) == len(tickets)
     assert seen_pending
@@ -101,4 +137,153 @@ def test_latencies_and_errors(og_mod):
     assert e.value.code == og_mod.OG_EBUSY
     for t in tickets:
         srv.release(t)
+    srv.close()
+
+
+def test_served_zeldovich_1m_vs_oracle(og_mod, oracle_mod):
+    """A served Zel'dovich request of 100^3 particles among smaller ones,
+    checked against the oracle on 2000 sampled targets (mixed and FP64)."""
+    pos = synth.zeldovich(100, 31)
+    n = pos.shape[0]
+    mass = synth.equal_masses(n)
+    prm = synth.scale_free_params(n).as_dict()
+    small = _requests(4, 32)
+    rng = np.random.default_rng(33)
+    tg = np.sort(rng.choice(n, 2000, replace=False))
+    ref = _oracle(oracle_mod, ("zel100", 31), pos, mass, prm, targets=tg)
+    tp, tm = torch.as_tensor(pos, device="cuda"), torch.as_tensor(mass, device="cuda")
+    dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), pr) for p, m, pr in small]
+    for prec in ("mixed", "fp64"):
+        _note("served zeldovich N=%d among %d small requests (%s)" % (n, len(small), prec))
+        srv = og_mod.Server(4 << 30, max_slots=3)
+        tickets = [srv.submit(p, m, 1.0, pr, precision=prec) for p, m, pr in dev[:2]]
+        big = srv.submit(tp, tm, 1.0, prm, precision=prec)
+        tickets += [srv.submit(p, m, 1.0, pr, precision=prec) for p, m, pr in dev[2:]]
+        srv.wait(big)
+        a, p = srv.result(big)
+        a = a.cpu().numpy()[tg]
+        p = p.cpu().numpy()[tg]
+        _check_vs_oracle(a, p, None, ref, prec, "zeldovich100")
+        for t in tickets:
+            srv.wait(t)
+            srv.release(t)
+        srv.release(big)
+        srv.close()
+
+
+def test_submit_orders_after_the_callers_stream(og_mod, oracle_mod):
+    """Positions written by a kernel on a side stream and submitted at once,
+    with no synchronisation: the build waits for that stream."""
+    reqs = _requests(3, 41, nmin=20000, nmax=40000)
+    srv = og_mod.Server(1 << 30, max_slots=2)
+    side = torch.cuda.Stream()
+    tickets, bufs = [], []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(42)
+    busy = torch.randn((4096, 4096), device="cuda", generator=gen)
+    with torch.cuda.stream(side):
+        for pos, mass, prm in reqs:
+            # stale positions first (another random box), the real ones
+            # copied in on the side stream behind a few milliseconds of work
+            tp = torch.rand((pos.shape[0], 3), dtype=torch.float64, device="cuda", generator=gen)
+            tm = torch.as_tensor(mass, device="cuda")
+            src = torch.as_tensor(pos).pin_memory()
+            torch.cuda.synchronize()
+            x = busy
+            for _ in range(8):
+                x = (x @ busy) * 1e-3
+            tp.copy_(src, non_blocking=True)
+            tickets.append(srv.submit(tp, tm, 1.0, prm, precision="fp64"))
+            bufs.append((tp, tm, src, x))
+    for i, t in enumerate(tickets):
+        srv.wait(t)
+        a, p = srv.result(t)
+        pos, mass, prm = reqs[i]
+        ref = _oracle(oracle_mod, ("r41", i), pos, mass, prm)
+        _check_vs_oracle(a.cpu().numpy(), p.cpu().numpy(), None, ref, "fp64", "side-stream request %d" % i)
+        srv.release(t)
+    srv.close()
+
+
+def test_forced_admission_failure_keeps_serving(og_mod, monkeypatch):
+    """OG_FAULT_ALLOC=2 fails the second admission on the host: that request
+    reports OG_ENOMEM, every other request completes with its alone result."""
+    reqs = _requests(5, 51)
+    dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), prm) for p, m, prm in reqs]
+    srv = og_mod.Server(1 << 30, max_slots=2)   # created before the knob: the arena is allocation 0
+    monkeypatch.setenv("OG_FAULT_ALLOC", "2")
+    tickets = [srv.submit(p, m, 1.0, prm) for p, m, prm in dev]
+    failed = []
+    for i, t in enumerate(tickets):
+        try:
+            srv.wait(t)
+        except og_mod.OgError as e:
+            assert e.code == og_mod.OG_ENOMEM
+            failed.append(i)
+            continue
+        a, p = srv.result(t)
+        ra, rp = _alone(og_mod, reqs[i][0], reqs[i][1], reqs[i][2], "mixed")
+        assert np.array_equal(a.cpu().numpy(), ra), i
+    assert failed == [1]
+    monkeypatch.delenv("OG_FAULT_ALLOC")
+    for t in tickets:
+        srv.release(t)
+    assert srv.stats() == {"reserved": 0, "in_flight": 0, "pending": 0}
+    srv.close()
+
+
+def test_forced_launch_failure_keeps_serving(og_mod, monkeypatch):
+    """OG_FAULT_LAUNCH=3 fails the third enqueue (the second request's build)
+    on the host: that request reports OG_EDEVICE, the others complete."""
+    reqs = _requests(4, 52)
+    dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), prm) for p, m, prm in reqs]
+    srv = og_mod.Server(1 << 30, max_slots=1)   # one slot: build, walk, build (fails), ...
+    monkeypatch.setenv("OG_FAULT_LAUNCH", "3")
+    tickets = [srv.submit(p, m, 1.0, prm) for p, m, prm in dev]
+    codes = []
+    for i, t in enumerate(tickets):
+        try:
+            srv.wait(t)
+            codes.append(0)
+            a, _ = srv.result(t)
+            ra, _ = _alone(og_mod, reqs[i][0], reqs[i][1], reqs[i][2], "mixed")
+            assert np.array_equal(a.cpu().numpy(), ra), i
+        except og_mod.OgError as e:
+            codes.append(e.code)
+    monkeypatch.delenv("OG_FAULT_LAUNCH")
+    assert codes == [0, og_mod.OG_EDEVICE, 0, 0]
+    for t in tickets:
+        srv.release(t)
+    assert srv.stats() == {"reserved": 0, "in_flight": 0, "pending": 0}
+    srv.close()
+
+
+def test_wait_and_release_from_two_threads(og_mod):
+    """A wait blocked on a running request while another thread releases the
+    same ticket: the wait returns (done or not found), nothing is used after
+    it is destroyed."""
+    import threading
+    reqs = _requests(6, 53, nmin=50000, nmax=200000)
+    dev = [(torch.as_tensor(p, device="cuda"), torch.as_tensor(m, device="cuda"), prm) for p, m, prm in reqs]
+    srv = og_mod.Server(2 << 30, max_slots=2)
+    tickets = [srv.submit(p, m, 1.0, prm) for p, m, prm in dev]
+    results = {}
+
+    def waiter(t):
+        try:
+            srv.wait(t)
+            results[t] = 0
+        except og_mod.OgError as e:
+            results[t] = e.code
+
+    th = [threading.Thread(target=waiter, args=(t,)) for t in tickets]
+    for x in th:
+        x.start()
+    for t in reversed(tickets):
+        srv.release(t)
+    for x in th:
+        x.join(60)
+        assert not x.is_alive()
+    assert all(c in (0, og_mod.OG_ENOTFOUND) for c in results.values()), results
+    assert srv.stats() == {"reserved": 0, "in_flight": 0, "pending": 0}
     srv.close()
