@@ -181,7 +181,9 @@ int og_tree_build(const double *pos, const double *mass, int64_t N, double box,
 
 /* Targets of a force evaluation: caller-order particle indices (device,
  * int64, each in [0,N); repeats allowed) or idx = NULL for all N particles
- * in caller order. */
+ * in caller order.  An index outside [0,N) is found on the device: its
+ * entry receives particle 0's result, and the tree is marked so that
+ * og_tree_status reports OG_ERANGE from then on. */
 typedef struct og_targets {
     const int64_t *idx;
     int64_t M;

@@ -671,8 +671,8 @@ __global__ __launch_bounds__(kThreads) void k_targets_map(const BoxDev *boxes, c
   if (t >= M) return;
   int64_t i = idx[t];
   const uint32_t n = boxes[0].n;
-  if (i < 0 || i >= (int64_t)n) {
-    atomicOr(status, kStatusRange);
+  if (i < 0 || i >= (int64_t)n) {  // reported through the tree's status word
+    atomicOr(status, kStatusTarget);
     i = 0;
   }
   tkey[t] = inv[(uint32_t)i];
@@ -876,7 +876,7 @@ void launch_targets(const BuildArrays &A, TargetArrays &T, hipStream_t s) {
   const uint32_t M = T.M;
   k_reset<<<1, 1, 0, s>>>(&T.scalars[0]);
   k_targets_map<<<cdiv(M, kThreads), kThreads, 0, s>>>(A.boxes, T.idx, M, A.inv, T.tkey_a, T.tval_a,
-                                                      &T.scalars[0]);
+                                                      &A.scalars[0]);
   int passes = 1;
   while (passes < 4 && (A.n >> (8 * passes)) != 0) ++passes;
   bool in_b = radix_sort(T.tkey_a, T.tval_a, T.tkey_b, T.tval_b, M, 0, passes, 0, A.boxes, 1, T.hist,

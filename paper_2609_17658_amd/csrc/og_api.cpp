@@ -329,28 +329,25 @@ int Forest::walk_all(int prec, hipStream_t s, double *acc, double *pot, int pot_
   return OG_OK;
 }
 
-int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
-                        int64_t *nint, const double *a_old) {
-  TargetArrays T{};
-  auto plan = [&](Carver &cv) {
-    T.tkey_a = cv.take<uint64_t>(M);
-    T.tkey_b = cv.take<uint64_t>(M);
-    T.tval_a = cv.take<uint32_t>(M);
-    T.tval_b = cv.take<uint32_t>(M);
-    T.hist = cv.take<uint32_t>(radix_hist_words(M));
-    T.digit_tot = cv.take<uint32_t>(256);
-    T.scalars = cv.take<uint32_t>(32);
-  };
+// Carve the scratch of a subset walk of M targets from `base` (null: only
+// measure); returns its size in bytes.
+size_t subset_plan(TargetArrays &T, uint32_t M, char *base) {
   Carver c;
-  plan(c);
-  if (fault_fires(kFaultLaunch)) return fail(OG_EDEVICE, "forced failure of the walk launch (OG_FAULT_LAUNCH)");
-  if (fault_fires(kFaultAlloc)) return fail(OG_ENOMEM, "forced failure of the target scratch (OG_FAULT_ALLOC)");
-  void *tmp = nullptr;
-  hipError_t e = hipMallocAsync(&tmp, c.off + 256, s);
-  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(targets)");
-  Carver c2;
-  c2.base = static_cast<char *>(tmp);
-  plan(c2);
+  c.base = base;
+  T.tkey_a = c.take<uint64_t>(M);
+  T.tkey_b = c.take<uint64_t>(M);
+  T.tval_a = c.take<uint32_t>(M);
+  T.tval_b = c.take<uint32_t>(M);
+  T.hist = c.take<uint32_t>(radix_hist_words(M));
+  T.digit_tot = c.take<uint32_t>(256);
+  T.scalars = c.take<uint32_t>(32);
+  return c.off + 256;
+}
+
+int Forest::walk_subset_in(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
+                           int64_t *nint, const double *a_old, void *scratch) {
+  TargetArrays T{};
+  subset_plan(T, M, static_cast<char *>(scratch));
   T.idx = idx;
   T.M = M;
   launch_targets(A, T, s);
@@ -366,10 +363,24 @@ int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M,
   W.nint = nint;
   W.a_old = a_old;
   launch_walk(W, prec, s);
-  e = hipGetLastError();
-  hipError_t e2 = hipFreeAsync(tmp, s);
+  const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "walk launch (targets)");
-  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync(targets)");
+  return OG_OK;
+}
+
+int Forest::walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
+                        int64_t *nint, const double *a_old) {
+  TargetArrays T{};
+  const size_t bytes = subset_plan(T, M, nullptr);
+  if (fault_fires(kFaultLaunch)) return fail(OG_EDEVICE, "forced failure of the walk launch (OG_FAULT_LAUNCH)");
+  if (fault_fires(kFaultAlloc)) return fail(OG_ENOMEM, "forced failure of the target scratch (OG_FAULT_ALLOC)");
+  void *tmp = nullptr;
+  hipError_t e = hipMallocAsync(&tmp, bytes, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(targets)");
+  const int rc = walk_subset_in(prec, s, idx, M, acc, pot, nint, a_old, tmp);
+  e = hipFreeAsync(tmp, s);
+  if (rc != OG_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "hipFreeAsync(targets)");
   return OG_OK;
 }
 
@@ -426,6 +437,7 @@ int Forest::read_status(hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status)");
   if (st & kStatusRange) return fail(OG_ERANGE, "a position lies outside [0, box) or is not finite");
   if (st & kStatusNodes) return fail(OG_EDEVICE, "node bound exceeded");
+  if (st & kStatusTarget) return fail(OG_ERANGE, "a target index lies outside [0, N)");
   return OG_OK;
 }
 

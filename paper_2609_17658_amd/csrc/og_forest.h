@@ -35,6 +35,9 @@ void fill_box(BoxDev &b, const double *pos, const double *mass, int64_t N, doubl
               uint32_t p_off);
 uint64_t node_bound(uint64_t n, int leaf_max);
 size_t forest_bytes(uint32_t n, uint32_t node_cap, int B, bool soft);
+// Scratch of a walk over M listed targets, carved from `base` (null: only
+// measure); returns its size in bytes.
+size_t subset_plan(TargetArrays &T, uint32_t M, char *base);
 
 struct Forest {
   int B = 0;
@@ -62,6 +65,9 @@ struct Forest {
                const double *a_old = nullptr);
   int walk_subset(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
                   int64_t *nint, const double *a_old = nullptr);
+  // The same walk with its target scratch (subset_plan bytes) given.
+  int walk_subset_in(int prec, hipStream_t s, const int64_t *idx, uint32_t M, double *acc, double *pot,
+                     int64_t *nint, const double *a_old, void *scratch);
   int walk_active(int prec, hipStream_t s, const int8_t *bin, int32_t level, double *acc, double *pot,
                   int64_t *nint, const double *a_old, int64_t *n_active);
   int read_status(hipStream_t s);

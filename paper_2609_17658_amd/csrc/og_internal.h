@@ -21,6 +21,7 @@ constexpr uint64_t kLeafBit = 1ull << 63;   // in Topo::corner
 // Status bits written by kernels (read by the host at sync points).
 constexpr uint32_t kStatusRange = 1u;       // a position outside the box
 constexpr uint32_t kStatusNodes = 2u;       // node bound exceeded (never expected)
+constexpr uint32_t kStatusTarget = 4u;      // a target index outside [0, N)
 
 // Per-box descriptor, device resident.
 struct BoxDev {

@@ -275,6 +275,23 @@ def test_out_of_box_position_reports_erange(og_mod):
     assert g["status"] == og_mod.OG_ERANGE
 
 
+def test_out_of_range_target_index_reports_erange(og_mod):
+    w = synth.mixture32k()
+    tp, tm = _dev(w.pos), _dev(w.mass)
+    tree = og_mod.Tree(tp, tm, 1.0, w.params, stream=torch.cuda.current_stream())
+    ok = torch.as_tensor([0, 5, 32767], dtype=torch.int64, device="cuda")
+    tree.force(targets=ok)
+    torch.cuda.synchronize()
+    assert tree.status() == 0
+    for bad in (32768, -1):
+        t2 = og_mod.Tree(tp, tm, 1.0, w.params, stream=torch.cuda.current_stream())
+        t2.force(targets=torch.as_tensor([3, bad, 7], dtype=torch.int64, device="cuda"))
+        torch.cuda.synchronize()
+        assert t2.status() == og_mod.OG_ERANGE
+        t2.close()
+    tree.close()
+
+
 def test_host_pointers_rejected(og_mod):
     import ctypes
     lib = og_mod.load()
