@@ -196,6 +196,21 @@ typedef struct og_targets {
  * a_old (og_tree_force_ex); here it gives OG_EINVAL. */
 int og_tree_force(const og_tree *tree, const og_targets *targets, double *acc, double *pot);
 
+/* Allocation-free variant of og_tree_force, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, precision, stream and
+ * results (bitwise) as og_tree_force; the caller passes the inputs and
+ * outputs, and the call makes no hipMalloc, hipFree or other allocating
+ * call.  A target list's sort scratch lives in a fixed device array inside
+ * the library (about 25 MB, for up to OG_NOALLOC_MAX_TARGETS targets),
+ * which each GPU the library runs on holds until the process ends; a walk
+ * over all N particles (targets NULL or idx NULL) needs none.  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (on other
+ * streams or threads) race, so serialise them.  Errors: as og_tree_force,
+ * and OG_EINVAL when targets->M > OG_NOALLOC_MAX_TARGETS. */
+#define OG_NOALLOC_MAX_TARGETS 1048576
+int og_tree_force_noalloc(const og_tree *tree, const og_targets *targets, double *acc, double *pot);
+
 typedef struct og_force_opts {
     uint32_t struct_size;   /* = sizeof(og_force_opts) */
     int32_t precision;      /* -1: the tree's; else OG_PREC_* */

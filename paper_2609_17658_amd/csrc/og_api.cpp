@@ -469,6 +469,55 @@ void Forest::release() {
 
 }  // namespace og
 
+// ------------------------------------------- allocation-free subset walk --
+// og_tree_force_noalloc takes the target list's scratch (sorted keys and
+// slots with their sort ping-pong, histograms, queue counters) from this
+// array instead of a stream-ordered allocation.  Every buffer in it is
+// written or reset by the kernels of each call before it is read.  Host
+// code reaches the array only through the address hipGetSymbolAddress
+// gives for the current device (its name stands for a host-side shadow).
+namespace {
+constexpr uint32_t kNoAllocTargets = OG_NOALLOC_MAX_TARGETS;
+constexpr size_t noalloc_align(size_t x) { return (x + 255) & ~(size_t)255; }
+// the sizes subset_plan carves for M targets, each 256-byte aligned
+constexpr size_t noalloc_bytes(size_t M) {
+  const size_t parts[7] = {8 * M, 8 * M, 4 * M, 4 * M, 4 * 256 * ((M + kSortTile - 1) / kSortTile), 4 * 256, 4 * 32};
+  size_t off = 0;
+  for (size_t p : parts) off = noalloc_align(off) + p;
+  return off + 256;
+}
+constexpr size_t kNoAllocBytes = noalloc_bytes(kNoAllocTargets);
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the current device, looked up on the
+// first call there.
+int scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(OG_EDEVICE, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    TargetArrays T{};
+    if (subset_plan(T, kNoAllocTargets, nullptr) > kNoAllocBytes)
+      return fail(OG_EDEVICE, "allocation-free scratch smaller than its plan");
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return OG_OK;
+}
+}  // namespace
+
 // ================================================================= ABI ==
 struct og_batch {
   Forest F;
@@ -570,6 +619,30 @@ int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_fo
 
 int og_tree_force(const og_tree *tree, const og_targets *targets, double *acc, double *pot) {
   return og_tree_force_ex(tree, targets, nullptr, acc, pot);
+}
+
+int og_tree_force_noalloc(const og_tree *tree, const og_targets *targets, double *acc, double *pot) {
+  if (!tree) return fail(OG_EINVAL, "tree is NULL");
+  og_tree *t = const_cast<og_tree *>(tree);
+  Forest &F = t->F;
+  if (F.hboxes[0].relative) return fail(OG_EINVAL, "the relative criterion needs a_old (og_tree_force_ex)");
+  if (!is_device_ptr(acc)) return fail(OG_EINVAL, "acc must be a device pointer");
+  if (pot && !is_device_ptr(pot)) return fail(OG_EINVAL, "pot must be a device pointer");
+  if (!targets || !targets->idx) {  // every particle: the tree's own workspace suffices
+    if (targets && targets->M != (int64_t)F.N)
+      return fail(OG_EINVAL, "targets->idx NULL requires M == N");
+    return F.walk_all(F.precision, F.stream, acc, pot, 1, nullptr);
+  }
+  if (targets->M < 1) return fail(OG_EINVAL, "targets->M out of range");
+  if (targets->M > (int64_t)kNoAllocTargets)
+    return fail(OG_EINVAL, "targets->M = %lld exceeds the allocation-free limit of %u targets",
+                (long long)targets->M, kNoAllocTargets);
+  if (!is_device_ptr(targets->idx)) return fail(OG_EINVAL, "targets->idx must be a device pointer");
+  void *scr = nullptr;
+  const int rc = scratch_address(&scr);
+  if (rc != OG_OK) return rc;
+  return F.walk_subset_in(F.precision, F.stream, targets->idx, (uint32_t)targets->M, acc, pot, nullptr,
+                          nullptr, scr);
 }
 
 int og_tree_force_active(const og_tree *tree, const int8_t *bin, int32_t level, const og_force_opts *opts,

@@ -27,6 +27,7 @@ CRITERIA = {"bh": OG_OPEN_BH, "relative": OG_OPEN_RELATIVE, 0: 0, 1: 1}
 OG_CURVE_MORTON, OG_CURVE_HILBERT = 0, 1
 CURVES = {"morton": OG_CURVE_MORTON, "hilbert": OG_CURVE_HILBERT, 0: 0, 1: 1}
 OG_LISTS_TARGET, OG_LISTS_GROUP = 0, 1
+OG_NOALLOC_MAX_TARGETS = 1048576
 LISTS = {"target": OG_LISTS_TARGET, "group": OG_LISTS_GROUP, 0: 0, 1: 1}
 
 
@@ -65,6 +66,7 @@ _SIGNATURES = {
     "og_tree_build": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(og_params),
                                      ctypes.POINTER(_P)]),
     "og_tree_force": (ctypes.c_int, [_P, ctypes.POINTER(og_targets), _P, _P]),
+    "og_tree_force_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(og_targets), _P, _P]),
     "og_tree_force_ex": (ctypes.c_int, [_P, ctypes.POINTER(og_targets), ctypes.POINTER(og_force_opts),
                                         _P, _P]),
     "og_tree_force_active": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(og_force_opts), _P, _P,
@@ -221,6 +223,14 @@ def og_tree_force(tree, targets, acc, pot, precision=None, stream=None, n_inter=
                          _stream_handle(stream), _ptr(n_inter), _ptr(a_old))
     _check(load().og_tree_force_ex(tree, ctypes.byref(tg) if tg is not None else None,
                                    ctypes.byref(opts), _ptr(acc), _ptr(pot)))
+
+
+def og_tree_force_noalloc(tree, targets, acc, pot):
+    """og_tree_force with the target scratch in the library's fixed device
+    array (no allocation); targets: None (all) or an int64 device tensor of
+    at most OG_NOALLOC_MAX_TARGETS caller-order indices."""
+    tg = None if targets is None else og_targets(_ptr(targets), int(targets.numel()))
+    _check(load().og_tree_force_noalloc(tree, ctypes.byref(tg) if tg is not None else None, _ptr(acc), _ptr(pot)))
 
 
 def og_tree_force_active(tree, bin, level, acc, pot, precision=None, stream=None, n_inter=None, a_old=None,
