@@ -924,10 +924,16 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
           }
           continue;
         }
-        const float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
-        const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
         const bool act = next <= n;
         const bool live = act && !(kCut && mdc > w.reach);
+        // every active lane prunes n: the wave skips its subtree (the lanes'
+        // next stays at or before n, which is where the walk resumes)
+        if (kCut && !__ballot(live)) {
+          n = max(ns, n + 1);
+          continue;
+        }
+        const float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
+        const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
         const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
         bool open = far_open || (mdc < w.near);
         float emono = 0.0f;  // the monopole's softening length (k.soft)
@@ -945,13 +951,13 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
                                        : make_float4(dx, dy, dz, w.m);
         list[cnt][lane] = entry;
         if (kSoft) lsoft[cnt][lane] = emono;
-        cnt += (contrib || (open_here && (cf & kWLeaf) != 0)) ? 1u : 0u;
+        cnt += (uint32_t)(contrib || (open_here && (cf & kWLeaf) != 0));
         // a lane past n is past all of n's subtree, so max() leaves it as
         // it is, and moves an active lane that did not open n to skip(n)
         next = open_here ? next : max(next, ns);
-        // the lanes that opened n are those still at or before n; a leaf's
-        // skip is n + 1; a skip always moves forward
-        n = __ballot(next <= n) ? n + 1 : max(ns, n + 1);
+        // the lanes still at or before n are exactly those that opened it; a
+        // leaf's skip is n + 1; a skip always moves forward
+        n = __ballot(open_here) ? n + 1 : max(ns, n + 1);
       }
     };
     if (kPer && lane_wrap) walk(std::integral_constant<int, 2>{});
