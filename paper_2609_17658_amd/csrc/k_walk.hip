@@ -322,11 +322,11 @@ __device__ inline double exp_nonpos(double x) {
 // erfcx polynomial; without it the kernel carries no library erfc, whose
 // constants would otherwise hold vector registers for the whole walk.
 template <bool kExt, bool kTail = true>
-__device__ inline void pair64(double dx, double dy, double dz, double m, double e, const BoxDev &bx,
-                              double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
+__device__ inline bool pair64_terms(double dx, double dy, double dz, double m, double e, const BoxDev &bx,
+                                    double4 &t) {
 #pragma clang fp contract(off)
   const double r2 = dx * dx + dy * dy + dz * dz;
-  if (bx.cutoff && !(r2 < bx.rc2)) return;
+  if (bx.cutoff && !(r2 < bx.rc2)) return false;
   double g, w;  // softened 1/r^3 and 1/r
   if (kExt && bx.spline) {
     spline64(sqrt(r2), 2.8 * e, g, w);
@@ -345,10 +345,22 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, double 
     pf = e;
   }
   const double f = bx.G * m * g * S;
-  ax += f * dx;
-  ay += f * dy;
-  az += f * dz;
-  ph -= bx.G * m * pf * w;
+  t = make_double4(f * dx, f * dy, f * dz, bx.G * m * pf * w);
+  return true;
+}
+
+// The pair term added to one target's sums: the force terms and the
+// potential term of pair64_terms, each rounded once and then added.
+template <bool kExt, bool kTail = true>
+__device__ inline void pair64(double dx, double dy, double dz, double m, double e, const BoxDev &bx,
+                              double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
+#pragma clang fp contract(off)
+  double4 t;
+  if (!pair64_terms<kExt, kTail>(dx, dy, dz, m, e, bx, t)) return;
+  ax += t.x;
+  ay += t.y;
+  az += t.z;
+  ph -= t.w;
   ++ni;
 }
 
@@ -356,73 +368,149 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, double 
 // expressions (and no contraction) as a direct reading of the walk rules.
 // The decisions are taken at the node; an accepted monopole (FP64 offset and
 // mass) or an opened leaf (its particle range) goes to the lane's own list
-// in LDS, and the lists are evaluated lane-parallel when one is full and at
-// the end of the walk.  Each target still sums its partners in traversal
-// order, but the costly FP64 pair terms run with the lanes of many nodes at
-// once instead of only the lanes that accepted or opened the current node.
+// in LDS, and the lists are evaluated when one is full and at the end of
+// the walk, with the pair terms spread over all lanes (flush64).  Each
+// target still sums its partners in traversal order, but the costly FP64
+// pair terms run with the lanes of many nodes at once instead of only the
+// lanes that accepted or opened the current node.
 // kExt: the spline softening and the relative criterion are read from each
 // box.
 constexpr int kWalk64Waves = 4;  // waves per workgroup
 constexpr int kWalk64Cap = 4;    // list entries per lane
 
-// Evaluate and empty every lane's list.  A monopole entry is (offset, mass),
-// mass >= 0; a leaf entry has w = -1 and, in the bits of x, its first
-// particle (bits 0..31), count (32..62) and whether its particles' offsets
-// need the minimum image (bit 63).
+// List entries: a monopole is (offset, mass), mass >= 0; a leaf has w = -1
+// and, in the bits of x, its first particle (bits 0..31), count (32..62)
+// and whether its particles' offsets need the minimum image (bit 63).
+__device__ inline uint32_t entry_items64(const double4 &q) {
+  return q.w >= 0.0 ? 1u : (uint32_t)((uint64_t)__double_as_longlong(q.x) >> 32) & 0x7fffffffu;
+}
+
+__device__ inline uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Evaluate and empty every lane's list with the pair terms computed by all
+// lanes.  A lane's items are its partners in list order (a monopole entry is
+// one item, a leaf entry one item per particle).  Row k holds the k-th item
+// of every lane that has more than k items; whole rows are laid out one
+// after another in steps of at most 64 slots.  In each step the owners write their items'
+// descriptors into the slots, every lane computes the pair terms of one
+// slot (pair64_terms, the arithmetic of an evaluation by the owner), and the
+// owners add the terms of their items in row order, which is their list
+// order.  So each target sums its partners in traversal order with the same
+// FP64 operations, while the costly pair terms run on every lane instead of
+// only on the lanes whose lists are longest.  `slots` holds a step's
+// descriptors (x: owner lane | entry << 8, y: particle within the entry,
+// z: the owner's target) and then, in the same place, its terms; a ballot
+// marks the slots whose pair contributes.
 template <bool kExt, bool kTail>
-__device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*lsoft)[64], uint32_t lane,
-                               uint32_t p, const double4 &xi, double ei, bool soft, const BoxDev &bx,
-                               uint32_t &cnt, double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
+__device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*lsoft)[64], double4 *slots,
+                               uint32_t lane, uint32_t p, bool soft, const BoxDev &bx, uint32_t &cnt, double &ax,
+                               double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(off)
-  uint32_t e = 0, j = 0;
-  while (__ballot(e < cnt)) {
-    if (e < cnt) {
-      const double4 q = list[e][lane];
-      // the partner: the monopole itself, or the leaf's j-th particle
+  // this lane's entry sizes (in items) and their total
+  uint32_t sz[kWalk64Cap];
+  uint32_t P = 0;
+#pragma unroll
+  for (int e = 0; e < kWalk64Cap; ++e) {
+    sz[e] = (uint32_t)e < cnt ? entry_items64(list[e][lane]) : 0u;
+    P += sz[e];
+  }
+  uint32_t ce = 0, cj = 0;  // entry and particle of this lane's next item
+  uint32_t k = 0;           // next row (wave-uniform)
+  uint64_t row = __ballot(P > 0);
+  while (row) {
+    // fill the step with whole rows k, k + 1, ... while they fit
+    const uint32_t k0 = k;
+    uint32_t f = 0;
+    do {
+      const uint32_t c = (uint32_t)__popcll(row);
+      if (f + c > 64u) break;
+      if (P > k) {
+        const uint32_t at = f + lane_rank(row);
+        *reinterpret_cast<uint4 *>(slots + at) = make_uint4(lane | (ce << 8), cj, p, 0u);
+        uint32_t n = sz[0];
+#pragma unroll
+        for (int e = 1; e < kWalk64Cap; ++e) n = ce == (uint32_t)e ? sz[e] : n;
+        ++cj;
+        const bool next_entry = cj == n;
+        ce += next_entry ? 1u : 0u;
+        cj = next_entry ? 0u : cj;
+      }
+      f += c;
+      ++k;
+      row = __ballot(P > k);
+    } while (row);
+    __builtin_amdgcn_wave_barrier();
+    // every lane computes the terms of one slot; a ballot marks the slots
+    // that contribute (a partner other than the target, within the cutoff)
+    double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
+    bool contributes = false;
+    if (lane < f) {
+      const uint4 d = *reinterpret_cast<const uint4 *>(slots + lane);
+      const uint32_t l = d.x & 63u, e = d.x >> 8, po = d.z;
+      const double4 q = list[e][l];
       double dx = q.x, dy = q.y, dz = q.z, m = q.w, es = bx.eps;
       bool use = true;
       if (q.w >= 0.0) {
-        if (soft) es = lsoft[e][lane];
-        ++e;
+        if (soft) es = lsoft[e][l];
       } else {
         const uint64_t bits = (uint64_t)__double_as_longlong(q.x);
-        const uint32_t first = (uint32_t)bits, count = (uint32_t)(bits >> 32) & 0x7fffffffu;
-        const bool wrap = (bits >> 63) != 0;
-        const uint32_t i = first + j;
-        use = i != p;
-        const double4 s = A.part64[i];
-        dx = s.x - xi.x;
-        dy = s.y - xi.y;
-        dz = s.z - xi.z;
+        const uint32_t i = (uint32_t)bits + d.y;
+        use = i != po;
+        const double4 xo = A.part64[po], sp = A.part64[i];
+        dx = sp.x - xo.x;
+        dy = sp.y - xo.y;
+        dz = sp.z - xo.z;
         // a branch: leaves of interior groups (below level 1) need no image
-        minimg3(dx, dy, dz, wrap, bx.box);
-        m = s.w;
+        minimg3(dx, dy, dz, (bits >> 63) != 0, bx.box);
+        m = sp.w;
         if (soft) {
-          const double ej = A.seps[i];
-          es = ei > ej ? ei : ej;
-        }
-        if (++j == count) {
-          j = 0;
-          ++e;
+          const double ej = A.seps[i], eo = A.seps[po];
+          es = eo > ej ? eo : ej;
         }
       }
-      // one evaluation site, shared by both kinds of partner
-      if (use) pair64<kExt, kTail>(dx, dy, dz, m, es, bx, ax, ay, az, ph, ni);
+      contributes = use && pair64_terms<kExt, kTail>(dx, dy, dz, m, es, bx, t);
     }
+    const uint64_t used = __ballot(contributes);
+    __builtin_amdgcn_wave_barrier();
+    slots[lane] = t;
+    __builtin_amdgcn_wave_barrier();
+    // the owners add their terms, row by row (the rows of the fill)
+    uint32_t g = 0;
+    for (uint32_t kk = k0; kk < k; ++kk) {
+      const uint64_t rr = __ballot(P > kk);
+      if (P > kk) {
+        const uint32_t at = g + lane_rank(rr);
+        if ((used >> at) & 1u) {
+          const double4 u = slots[at];
+          ax += u.x;
+          ay += u.y;
+          az += u.z;
+          ph -= u.w;
+          ++ni;
+        }
+      }
+      g += (uint32_t)__popcll(rr);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   cnt = 0;
 }
 
-// Four waves per SIMD (a few registers spill to scratch) run faster than
-// the three the registers would otherwise allow.
+// Four waves per SIMD: the instance for boxes with r_cut < 6 r_s needs 97
+// vector registers and no scratch; the one with the library erfc tail needs
+// 128 and spills a few values to scratch.
 template <bool kExt, bool kTail>
 __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk64(WalkArgs A) {
 #pragma clang fp contract(off)
   __shared__ double4 lists[kWalk64Waves][kWalk64Cap][64];
   __shared__ double lsofts[kExt ? kWalk64Waves : 1][kExt ? kWalk64Cap : 1][64];
+  __shared__ double4 slotss[kWalk64Waves][64];
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double4(*list)[64] = lists[wv];
   double(*lsoft)[64] = lsofts[kExt ? wv : 0];
+  double4 *slots = slotss[wv];
   device_counts(A);
   GroupQueue Q = make_queue(A);
   while (true) {
@@ -467,7 +555,7 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
     while (n < nend) {
       // room for this visit's entry
       if (__ballot(cnt >= (uint32_t)kWalk64Cap))
-        flush64<kExt, kTail>(A, list, lsoft, lane, p, xi, ei, soft, bx, cnt, ax, ay, az, ph, ni);
+        flush64<kExt, kTail>(A, list, lsoft, slots, lane, p, soft, bx, cnt, ax, ay, az, ph, ni);
       const Topo t = ld(A.topo + n);
       const Mom64 mm = ld(A.mom64 + n);
       const bool leaf = (t.corner & kLeafBit) != 0;
@@ -528,7 +616,7 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
       // a leaf's skip is n + 1; a skip always moves forward
       n = (leaf || __ballot(open_int) || t.a <= n) ? n + 1 : t.a;
     }
-    flush64<kExt, kTail>(A, list, lsoft, lane, p, xi, ei, soft, bx, cnt, ax, ay, az, ph, ni);
+    flush64<kExt, kTail>(A, list, lsoft, slots, lane, p, soft, bx, cnt, ax, ay, az, ph, ni);
     if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
   }
 }
