@@ -397,28 +397,44 @@ __device__ inline int lcp_at(const uint64_t *skeys, uint32_t q, uint32_t b0, uin
 // running minima of lcp to the right and to the left (merged, both
 // sequences are non-increasing).  nstart(p) = nodes whose first particle
 // is p = levels lcp(p)+1 .. depth(p).
-__global__ __launch_bounds__(kThreads) void k_lcp_depth(const BoxDev *boxes, int B, uint32_t n,
+// The block's lcp values, with a halo of lmax on each side, are formed once
+// in LDS from the keys: lcp(q) = shared levels of keys q-1 and q, -1 at the
+// first particle of a box and outside [0, n).  A particle's running minima
+// pass through its box's first particle (left) or the next box's first
+// particle (right) before they could leave its box, so values beyond
+// contribute min(-1, .) = -1, as when each is evaluated against the box.
+__global__ __launch_bounds__(kThreads) void k_lcp_depth(const BoxDev *boxes, int B, uint32_t n, int lmax,
                                                         const uint64_t *skeys, int8_t *lcp,
                                                         uint8_t *depth, uint32_t *nstart) {
-  uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  extern __shared__ int8_t sl[];  // lcp of particles lo .. lo + kThreads + 2 lmax
+  const int64_t p0 = (int64_t)blockIdx.x * kThreads, lo = p0 - lmax;
+  const int cnt = kThreads + 2 * lmax + 1;
+  for (int i = threadIdx.x; i < cnt; i += kThreads) {
+    const int64_t q = lo + i;
+    int v = -1;
+    if (q > 0 && q < (int64_t)n && (B == 1 || (uint32_t)q != boxes[box_of(boxes, B, (uint32_t)q)].p_off))
+      v = shared_levels(skeys[q - 1], skeys[q]);
+    sl[i] = (int8_t)v;
+  }
+  __syncthreads();
+  const uint32_t p = (uint32_t)p0 + threadIdx.x;
   if (p >= n) return;
-  const BoxDev &bx = boxes[box_of(boxes, B, p)];
-  const uint32_t b0 = bx.p_off, b1 = bx.p_off + bx.n;
-  const int lm = bx.leaf_max;
-  const int own = lcp_at(skeys, p, b0, b1);
+  const int lm = boxes[box_of(boxes, B, p)].leaf_max;
+  const int8_t *L = sl + (p - lo);  // L[j] = lcp(p + j)
+  const int own = L[0];
   int ri = 1, li = 1;
-  int rv = lcp_at(skeys, p + 1, b0, b1);
+  int rv = L[1];
   int lv = own;
   int v = -1;
   for (int k = 0; k < lm; ++k) {
     if (rv >= lv) {
       v = rv;
       ++ri;
-      rv = ri <= lm ? min(rv, lcp_at(skeys, p + ri, b0, b1)) : -2;
+      rv = ri <= lm ? min(rv, (int)L[ri]) : -2;
     } else {
       v = lv;
       ++li;
-      lv = (li <= lm && p + 1 >= (uint32_t)li) ? min(lv, lcp_at(skeys, p + 1 - li, b0, b1)) : -2;
+      lv = (li <= lm && p + 1 >= (uint32_t)li) ? min(lv, (int)L[1 - li]) : -2;
     }
   }
   int d = min(kLevels, v + 1);
@@ -428,12 +444,15 @@ __global__ __launch_bounds__(kThreads) void k_lcp_depth(const BoxDev *boxes, int
 }
 
 // Per box: node range [S[p_off], S[p_off+n]).
+// Node range of each box; a box's root has no parent.
 __global__ void k_box_nodes(BoxDev *boxes, int B, const uint32_t *S, uint32_t n, uint32_t node_cap,
-                            uint32_t *scalars) {
+                            uint32_t *scalars, uint32_t *parent) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < B) {
-    boxes[b].root = min(S[boxes[b].p_off], node_cap);
+    const uint32_t root = min(S[boxes[b].p_off], node_cap);
+    boxes[b].root = root;
     boxes[b].node_end = min(S[boxes[b].p_off + boxes[b].n], node_cap);
+    if (root < node_cap) parent[root] = 0xffffffffu;
   }
   if (b == 0) {
     uint32_t tot = S[n];
@@ -526,18 +545,8 @@ __global__ __launch_bounds__(kThreads) void k_links(const Topo *topo, const uint
   if (threadIdx.x <= kLevels && h[threadIdx.x]) atomicAdd(&lvl_cnt[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_zero_levels(uint32_t *lvl_cnt, uint32_t *lvl_fill) {
-  if (threadIdx.x <= kLevels) {
-    lvl_cnt[threadIdx.x] = 0;
-    lvl_fill[threadIdx.x] = 0;
-  }
-}
-
-// Roots of all boxes have no parent.
-__global__ void k_roots(const BoxDev *boxes, int B, uint32_t *parent) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < B) parent[boxes[b].root] = 0xffffffffu;
-}
+// Particles staged in LDS per round of the leaf-moment kernel (32 KB).
+constexpr int kLeafStage = 1024;
 
 // Cube centre of a node in FP64: lo + (corner + 2^(20-level)) L 2^-21.
 __device__ inline void node_centre(const BoxDev &bx, uint64_t corner, int level, double c[3]) {
@@ -562,6 +571,10 @@ __global__ __launch_bounds__(kThreads) void k_leaves_and_buckets(
     Mom32 *mom32, const uint32_t *scalars, uint32_t node_cap, const uint32_t *lvl_cnt, uint32_t *lvl_fill,
     uint32_t *lvl_nodes, const double *seps, double *semax, double *semin) {
   __shared__ uint32_t base[kLevels + 1], lcount[kLevels + 1], lres[kLevels + 1];
+  // the round's leaf particles, loaded coalesced (a leaf's thread would
+  // otherwise read its particles with a stride of a leaf between lanes)
+  __shared__ double4 stage[kLeafStage];
+  __shared__ uint32_t prange[2];
   if (threadIdx.x <= kLevels) {
     uint32_t o = 0;
     for (int l = 0; l < (int)threadIdx.x; ++l) o += lvl_cnt[l];
@@ -573,19 +586,34 @@ __global__ __launch_bounds__(kThreads) void k_leaves_and_buckets(
   for (uint32_t r0 = blockIdx.x * kThreads; r0 < tot; r0 += stride) {
     const uint32_t r = r0 + threadIdx.x;
     if (threadIdx.x <= kLevels) lcount[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+      prange[0] = 0xffffffffu;
+      prange[1] = 0u;
+    }
+    __syncthreads();
+    Topo t{};
+    const bool is_leaf = r < tot && ((t = topo[r]).corner & kLeafBit) != 0;
+    if (is_leaf) {
+      atomicMin(&prange[0], t.a);
+      atomicMax(&prange[1], t.a + (t.b & kCountMask));
+    }
+    __syncthreads();
+    const uint32_t pa = prange[0], pn = prange[1] > pa ? prange[1] - pa : 0u;
+    const bool staged = pn <= (uint32_t)kLeafStage;
+    if (staged)
+      for (uint32_t i = threadIdx.x; i < pn; i += kThreads) stage[i] = part64[pa + i];
     __syncthreads();
     int lvl = -1;
     uint32_t slot = 0;
     if (r < tot) {
-      const Topo t = topo[r];
-      if (t.corner & kLeafBit) {
+      if (is_leaf) {
         const uint32_t f = t.a, cnt = t.b & kCountMask;
         const BoxDev &bx = boxes[box_of(boxes, B, f)];
         double c[3];
         node_centre(bx, t.corner, (int)(t.b >> kCountBits), c);
         double M = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (uint32_t j = f; j < f + cnt; ++j) {
-          const double4 q = part64[j];
+          const double4 q = staged ? stage[j - pa] : part64[j];
           const double dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
           M += q.w;
           s0 += q.w * dx;
@@ -737,7 +765,18 @@ __global__ void k_reset(uint32_t *w) { *w = 0; }
 __global__ void k_reset_n(uint32_t *w, int n) {
   if ((int)threadIdx.x < n) w[threadIdx.x] = 0;
 }
-__global__ void k_set(uint32_t *w, uint32_t v) { *w = v; }
+// Status word cleared, particle count for the device-side scans, level
+// counters of the moment buckets cleared.
+__global__ void k_init_scalars(uint32_t *sc, uint32_t n, uint32_t *lvl_cnt, uint32_t *lvl_fill) {
+  if (threadIdx.x == 0) {
+    sc[0] = 0u;
+    sc[4] = n;
+  }
+  if (threadIdx.x <= kLevels) {
+    lvl_cnt[threadIdx.x] = 0;
+    lvl_fill[threadIdx.x] = 0;
+  }
+}
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
@@ -798,8 +837,7 @@ bool radix_sort(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *
 void launch_build(BuildArrays &A, hipStream_t s) {
   const uint32_t n = A.n;
   const uint32_t nb = cdiv(n, kThreads);
-  k_reset<<<1, 1, 0, s>>>(&A.scalars[0]);
-  k_set<<<1, 1, 0, s>>>(&A.scalars[4], n);
+  k_init_scalars<<<1, 64, 0, s>>>(A.scalars, n, A.lvl_cnt, A.lvl_fill);
   if (A.any_open) {
     k_frame_init<<<cdiv(6 * (uint64_t)A.B, kThreads), kThreads, 0, s>>>(A.B, A.minmax);
     k_frame_reduce<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.minmax, &A.scalars[0]);
@@ -814,20 +852,20 @@ void launch_build(BuildArrays &A, hipStream_t s) {
   radix_sort(k0, v0, k1, v1, n, 0, 8, box_passes, A.boxes, A.B, A.hist, A.digit_tot, s);
   const uint64_t *skeys = A.keys_a;
   k_gather<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.vals_a, A.perm, A.inv, A.part64, A.seps, &A.scalars[0]);
-  k_lcp_depth<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.nstart);
+  k_lcp_depth<<<nb, kThreads, kThreads + 2 * A.leaf_max + 1, s>>>(A.boxes, A.B, n, A.leaf_max, skeys, A.lcp,
+                                                                  A.depth, A.nstart);
   scan_u32(A.nstart, A.S, &A.scalars[4], n, A.scan_partial, s);
-  k_box_nodes<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.S, n, A.node_cap, A.scalars);
+  k_box_nodes<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.S, n, A.node_cap, A.scalars, A.parent);
   k_emit<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.S, A.node_cap, A.topo,
                                  A.first, A.skip);
   const uint32_t gnodes = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kThreads), 8192));
-  k_zero_levels<<<1, 64, 0, s>>>(A.lvl_cnt, A.lvl_fill);
   k_links<<<gnodes, kThreads, 0, s>>>(A.topo, A.skip, A.scalars, A.node_cap, A.parent, A.nchild, A.lvl_cnt);
-  k_roots<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.parent);
   k_leaves_and_buckets<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.part64, A.part32, A.mom64,
                                                    A.mom32, A.scalars, A.node_cap, A.lvl_cnt, A.lvl_fill,
                                                    A.lvl_nodes, A.seps, A.semax, A.semin);
-  // internal nodes at level L number at most n / (leaf_max + 1) <= n / 2
-  const uint32_t glev = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(n / 2 + 1, kThreads), 2048));
+  // internal nodes at level L number at most n / (leaf_max + 1) <= n / 2; most
+  // levels hold few, so a small grid (grid-stride) keeps the launches short
+  const uint32_t glev = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(n / 2 + 1, kThreads), 512));
   for (int L = kLevels - 1; L >= 0; --L)
     k_moments_level<<<glev, kThreads, 0, s>>>(A.boxes, A.B, L, A.topo, A.first, A.skip, A.lvl_cnt,
                                               A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32, A.semax,

@@ -264,7 +264,11 @@ int Forest::init(const std::vector<BoxDev> &boxes, uint64_t node_cap_, hipStream
   A.n = N;
   A.node_cap = node_cap;
   A.any_open = 0;
-  for (auto &b : hboxes) A.any_open |= b.periodic ? 0 : 1;
+  A.leaf_max = 1;
+  for (auto &b : hboxes) {
+    A.any_open |= b.periodic ? 0 : 1;
+    A.leaf_max = std::max(A.leaf_max, (int)b.leaf_max);
+  }
   hipError_t e = hipMemcpyAsync(A.boxes, hboxes.data(), sizeof(BoxDev) * B, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(boxes)");
   return OG_OK;

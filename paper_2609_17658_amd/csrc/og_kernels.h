@@ -47,6 +47,7 @@ struct BuildArrays {
   uint32_t *scalars;          // [0] status [3] n_nodes [4] n [8..15] walk queues
                               // [5] deepest level (stats)
   int any_open;               // some box has periodic = 0
+  int leaf_max;               // largest leaf_max of the boxes
   double *seps;               // sorted per-particle softening lengths (null: none given)
   double *semax, *semin;      // per node: largest and smallest of its particles' lengths
 };
