@@ -15,7 +15,6 @@ cores as a baseline.
 import argparse
 import json
 import os
-import subprocess
 import sys
 import time
 
@@ -97,12 +96,33 @@ def walk_issue(walk_ms):
     return out
 
 
-def git_hash():
+def source_id():
+    """Identity of the code that ran: sha256 over the library's sources,
+    headers, binding and this script (a GPU machine has no git metadata; the
+    same digest is reproducible from any checkout), plus the commit when a
+    git work tree is present (read from .git, no subprocess)."""
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2609_17658_amd", "csrc", "*"))
+                   + [os.path.join(ROOT, "include", "og.h"), os.path.join(ROOT, "paper_2609_17658_amd", "og.py"),
+                      os.path.abspath(__file__)])
+    h = hashlib.sha256()
+    for f in files:
+        if os.path.isfile(f) and not f.endswith(".pyc"):
+            h.update(os.path.relpath(f, ROOT).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    out = {"sources_sha256": h.hexdigest(), "files": len(files), "git": None}
     try:
-        return subprocess.run(["git", "-C", ROOT, "rev-parse", "--short", "HEAD"], capture_output=True,
-                              text=True, timeout=5).stdout.strip() or None
-    except Exception:  # noqa: BLE001
-        return None
+        with open(os.path.join(ROOT, ".git", "HEAD")) as f:
+            ref = f.read().strip()
+        if ref.startswith("ref:"):
+            with open(os.path.join(ROOT, ".git", ref.split(None, 1)[1])) as f:
+                ref = f.read().strip()
+        out["git"] = ref[:12]
+    except OSError:
+        pass
+    return out
 
 
 def time_steps(og, torch, tp, tm, params, ws, precision, steps, warmup, a_old=None):
@@ -153,9 +173,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
-    ap.add_argument("--legs", default="batch,serving,zeldovich,variants,hilbert,active,pm,groups,theta",
-                    help="extra workloads reported beside the headline: batch, serving, zeldovich, "
-                         "variants, hilbert, active, pm, groups, theta (comma list, or 'none')")
+    ap.add_argument("--legs", default="accuracy,tuned,batch,serving,zeldovich,variants,hilbert,active,pm,groups,theta",
+                    help="extra workloads reported beside the headline: accuracy (tree vs direct sum), tuned, batch, "
+                         "serving, zeldovich, variants, hilbert, active, pm, groups, theta (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -180,6 +200,13 @@ def main():
     tm = torch.as_tensor(w.mass, device=dev)
     ws = torch.empty(og.og_tree_workspace_bound(n, og.make_params(prm)), dtype=torch.uint8, device=dev)
 
+    # launch shape: the result-neutral knobs (targets per group, list depth)
+    # tuned at the workload's leaf size
+    from paper_2609_17658_amd import tune
+    neutral = tune.tune_tree(tp, tm, 1.0, prm, fixed_leaf=prm["leaf_max"], reps=3, log=log)
+    shape = {k: neutral["best"][k] for k in ("group_max", "walk_list_cap")}
+    prm = dict(prm, **shape)
+    log("tuned launch shape %s" % shape)
     res = {}
     for prec in ("mixed", "fp64"):
         log("timing %s: %d warmup + %d steps" % (prec, args.warmup, args.steps))
@@ -234,7 +261,9 @@ def main():
             "workload": "mixture2m: N=128^3 periodic unit box, 50%% uniform + 64 Plummer spheres "
                         "(a=0.005), eps=1/5120, r_s=1.25/256, r_cut=4.5 r_s, theta=%.2f, leaf_max=8"
                         % args.theta,
-            "N": n, "theta": args.theta, "leaf_max": 8, "group_max": 64,
+            "N": n, "theta": args.theta, "leaf_max": 8, "group_max": shape["group_max"],
+            "walk_list_cap": shape["walk_list_cap"],
+            "launch_shape_tuning": neutral["trials"],
             "precision": "mixed: FP32 interactions on node-relative offsets, FP64 offsets + accumulation",
             "step": "og_tree_build + og_tree_force on all N targets",
         },
@@ -263,7 +292,7 @@ def main():
             "bound": "hbm", "achieved": build_gbs / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
             "frac": build_gbs / PEAK_HBM, "algorithmic_bytes": bb,
         },
-        "git": git_hash(),
+        "source": source_id(),
     }
 
     legs = [l for l in args.legs.split(",") if l and l != "none"]
@@ -271,7 +300,7 @@ def main():
     del tp, tm, ws
     torch.cuda.empty_cache()
     for leg in legs:
-        fn = {"batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich,
+        fn = {"accuracy": leg_accuracy, "tuned": leg_tuned, "batch": leg_batch, "serving": leg_serving, "zeldovich": leg_zeldovich,
               "variants": leg_variants, "hilbert": leg_hilbert, "active": leg_active, "pm": leg_pm,
               "groups": leg_groups, "theta": leg_theta}[leg]
         log("leg %s" % leg)
@@ -339,7 +368,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-LEG_NAMES = {"batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256",
+LEG_NAMES = {"accuracy": "accuracy_vs_direct", "tuned": "tuned_mixture2m", "batch": "batch512", "serving": "serving", "zeldovich": "zeldovich256",
              "variants": "variants_mixture2m", "hilbert": "hilbert_mixture2m", "active": "active_mixture2m",
              "pm": "treepm", "groups": "group_lists_mixture2m",
              "theta": "theta_mixture2m"}
@@ -397,18 +426,21 @@ def leg_batch(og, torch, synth, args):
                       walk_list_cap=best["walk_list_cap"])
         outs = bt.force()
         torch.cuda.synchronize()
-        rng = np.random.default_rng(7)
-        pick = sorted(rng.choice(len(ws), 8, replace=False))
-        errs = []
-        for b in pick:
-            w = ws[b]
+        errs, worst_med, worst_p99 = [], 0.0, 0.0
+        t0 = time.perf_counter()
+        for b, w in enumerate(ws):
             op = _oracle_params(oracle, dict(w.params.as_dict(), leaf_max=best["leaf_max"]))
             a_o, _, _ = oracle.tree_force(w.pos, w.mass, w.box, op)
-            errs.append(_rel_err(outs[b][0].cpu().numpy(), a_o))
+            e = _rel_err(outs[b][0].cpu().numpy(), a_o)
+            worst_med = max(worst_med, float(np.median(e)))
+            worst_p99 = max(worst_p99, float(np.percentile(e, 99)))
+            errs.append(e)
+        t_or = time.perf_counter() - t0
         bt.close()
         e = np.concatenate(errs)
-        err = {"boxes": [int(b) for b in pick], "targets": int(e.size),
-               "mixed_median": float(np.median(e)), "mixed_p99": float(np.percentile(e, 99))}
+        err = {"boxes": len(ws), "targets": int(e.size), "leaf_max": best["leaf_max"],
+               "mixed_median": float(np.median(e)), "mixed_p99": float(np.percentile(e, 99)),
+               "per_box_median_worst": worst_med, "per_box_p99_worst": worst_p99, "oracle_s": t_or}
     except Exception as exc:  # noqa: BLE001
         log("batch parity failed: %r" % (exc,))
     return {"boxes": len(ws), "N_total": n_tot, "ms_per_pass": ms, "value": n_tot / (ms * 1e-3),
@@ -449,31 +481,37 @@ def leg_serving(og, torch, synth, args):
     arrivals = np.cumsum(rng.exponential(1.0 / rate, K))
     arrivals -= arrivals[0]
     lat, inflight, n_done, parts = [], [], 0, 0
+    kept = []          # (pool box, acc) of the first served requests, checked after the stream
+    n_check = 50
     k = 0
     start = time.perf_counter()
     while n_done < K:
         now = time.perf_counter() - start
         while k < K and arrivals[k] <= now:
             p, m, prm = pool[k % pool_n]
-            inflight.append((srv.submit(p, m, 1.0, prm), p.shape[0]))
+            inflight.append((srv.submit(p, m, 1.0, prm), p.shape[0], k % pool_n))
             k += 1
         still = []
-        for t, n in inflight:
+        for t, n, b in inflight:
             done, ta, td = srv.poll(t)
             if done:
                 lat.append(td - ta)
                 parts += n
                 n_done += 1
+                if len(kept) < n_check:
+                    kept.append((b, srv.result(t)[0]))
                 srv.release(t)
             else:
-                still.append((t, n))
+                still.append((t, n, b))
         inflight = still
         if k < K and not inflight:
             time.sleep(max(0.0, min(0.0005, arrivals[k] - (time.perf_counter() - start))))
     makespan = time.perf_counter() - start
     srv.close()
     lat = np.array(lat) * 1e3
+    check = _serving_check(og, torch, reqs, pool, kept)
     return {"requests": K, "pool": pool_n, "rate_per_s": rate, "sustainable_per_s": sustain,
+            "error_vs_oracle": check,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "value": parts / makespan, "unit": "particles/s",
             "makespan_s": makespan, "slots": 4, "hbm_budget_bytes": budget,
@@ -482,15 +520,54 @@ def leg_serving(og, torch, synth, args):
                         "N log-uniform [1e4, 4e6], Zel'dovich or mixture by seeded coin; mixed walk"}
 
 
+def _serving_check(og, torch, reqs, pool, kept):
+    """Served results of the first requests against the FP64 oracle (2000
+    seeded targets of their pool box, all when smaller) and bitwise against
+    an alone run of that box."""
+    try:
+        import oracle
+    except Exception as exc:  # noqa: BLE001
+        return {"failed": repr(exc)}
+    refs, alone = {}, {}
+    for b in sorted({b for b, _ in kept}):
+        w = reqs[b].workload()
+        n = w.pos.shape[0]
+        rng = np.random.default_rng(200 + b)
+        tg = np.arange(n) if n <= 2000 else np.sort(rng.choice(n, 2000, replace=False))
+        a_o, _, _ = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, w.params.as_dict()), targets=tg)
+        refs[b] = (tg, a_o)
+        p, m, prm = pool[b]
+        t = og.Tree(p, m, 1.0, prm, stream=torch.cuda.current_stream())
+        a, _ = t.force(precision="mixed")
+        torch.cuda.synchronize()
+        alone[b] = a.cpu().numpy()
+        t.close()
+    med, p99, same = [], [], 0
+    for b, acc in kept:
+        a = acc.cpu().numpy()
+        tg, a_o = refs[b]
+        e = _rel_err(a[tg], a_o)
+        med.append(float(np.median(e)))
+        p99.append(float(np.percentile(e, 99)))
+        same += int(np.array_equal(a, alone[b]))
+    return {"requests_checked": len(kept), "distinct_boxes": len(refs), "targets_per_request": "min(N, 2000)",
+            "mixed_median_worst": max(med), "mixed_p99_worst": max(p99),
+            "bitwise_equal_to_alone": same}
+
+
 def leg_zeldovich(og, torch, synth, args):
     """N = 256^3 Zel'dovich-displaced grid (P(k) ~ k^-2, rms 0.3 cell): the
     largest single box; both forms, error on sampled targets."""
+    from paper_2609_17658_amd import tune
     w = synth.zeldovich256()
     n = w.pos.shape[0]
     prm = w.params.as_dict()
     tp = torch.as_tensor(w.pos, device="cuda")
     tm = torch.as_tensor(w.mass, device="cuda")
     wsb = torch.empty(og.og_tree_workspace_bound(n, og.make_params(prm)), dtype=torch.uint8, device="cuda")
+    neutral = tune.tune_tree(tp, tm, 1.0, prm, fixed_leaf=prm["leaf_max"], reps=2, log=log)
+    shape = {k: neutral["best"][k] for k in ("group_max", "walk_list_cap")}
+    prm = dict(prm, **shape)
     res = {}
     for prec, steps in (("mixed", 5), ("fp64", 2)):
         r = time_steps(og, torch, tp, tm, prm, wsb, prec, steps, 1)
@@ -499,29 +576,135 @@ def leg_zeldovich(og, torch, synth, args):
         res[prec] = {"value": n / (r["total_ms"] / steps * 1e-3), "ms_per_step": r["total_ms"] / steps,
                      "build_ms": float(r["build_ms"].mean()), "walk_ms": float(r["walk_ms"].mean())}
     t = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream(), workspace=wsb)
-    a_m, _ = t.force(precision="mixed")
-    a_d, _ = t.force(precision="fp64")
+    a_m, _, ni_m = t.force(precision="mixed", with_counts=True)
+    a_d, _, ni_d = t.force(precision="fp64", with_counts=True)
     torch.cuda.synchronize()
     t.close()
+    inter_m = int(ni_m.sum().item())
+    walk_ms = res["mixed"]["walk_ms"]
+    achieved = inter_m * FLOP_PER_INTERACTION / (walk_ms * 1e-3)
+    roof = {"bound": "alu", "kernel": "k_walk32 (mixed walk)", "achieved": achieved / 1e12,
+            "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+            "flop_per_interaction": FLOP_PER_INTERACTION, "interactions": inter_m,
+            "interactions_per_target": inter_m / n, "walk_ms": walk_ms,
+            "fp64_walk_tflops": int(ni_d.sum().item()) * FLOP_PER_INTERACTION / (res["fp64"]["walk_ms"] * 1e-3) / 1e12}
     err = None
     try:
         import oracle
         rng = np.random.default_rng(3)
-        tg = np.sort(rng.choice(n, 20000, replace=False))
-        a_o, _, _ = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, prm), targets=tg)
-        e_m = _rel_err(a_m.cpu().numpy()[tg], a_o)
+        tg = np.sort(rng.choice(n, 1 << 20, replace=False))
+        t0 = time.perf_counter()
+        a_o, _, ni_o = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, prm), targets=tg)
+        t_or = time.perf_counter() - t0
+        a_mt = a_m.cpu().numpy()[tg]
+        e_m = _rel_err(a_mt, a_o)
         e_d = _rel_err(a_d.cpu().numpy()[tg], a_o)
         rms = np.sqrt(np.mean(np.sum(a_o ** 2, axis=1)))
         err = {"targets": int(tg.size), "mixed_median": float(np.median(e_m)),
-               "mixed_p99": float(np.percentile(e_m, 99)),
-               "mixed_p99_over_rms": float(np.percentile(np.linalg.norm(a_m.cpu().numpy()[tg] - a_o, axis=1),
-                                                         99) / rms),
-               "fp64_max": float(e_d.max())}
+               "mixed_p99": float(np.percentile(e_m, 99)), "mixed_max": float(e_m.max()),
+               "mixed_p99_over_rms": float(np.percentile(np.linalg.norm(a_mt - a_o, axis=1), 99) / rms),
+               "fp64_max": float(e_d.max()),
+               "fp64_counts_equal": bool(np.array_equal(ni_d.cpu().numpy()[tg], ni_o)),
+               "oracle_s": t_or}
     except Exception as exc:  # noqa: BLE001
         log("zeldovich parity failed: %r" % (exc,))
-    return {"N": n, "mixed": res["mixed"], "fp64": res["fp64"], "error_vs_oracle": err,
+    return {"N": n, "launch_shape": shape, "mixed": res["mixed"], "fp64": res["fp64"], "roofline": roof,
+            "error_vs_oracle": err,
             "workload": "256^3 grid, Gaussian field P(k)~k^-2 cut at k_Nyq, rms displacement 0.3 cell, "
-                        "eps=1/10240, r_s=1.25/512, theta 0.5, leaf_max 8"}
+                        "eps=1/10240, r_s=1.25/512, theta 0.5, leaf_max 8; oracle on 2^20 seeded targets"}
+
+
+def _err_stats(a, ref):
+    e = _rel_err(a, ref)
+    return {"median": float(np.median(e)), "p99": float(np.percentile(e, 99)), "max": float(e.max())}
+
+
+def leg_accuracy(og, torch, synth, args):
+    """Error of the tree force itself (the opening criterion's truncation):
+    the GPU mixed and FP64 walks and the oracle's walk against the
+    brute-force direct sum with the same split, cutoff and softening.  The
+    32k mixture on every target (the full N^2 direct sum); the 2M mixture on
+    4096 seeded targets at theta 0.3, 0.5 and 0.7.  The paper prints no such
+    error, so these values are not pinned to it."""
+    import oracle
+    out = {}
+    w = synth.mixture32k()
+    prm = w.params.as_dict()
+    n = w.pos.shape[0]
+    t0 = time.perf_counter()
+    a_dir = oracle.direct(w.pos, w.mass, 1.0, _oracle_params(oracle, prm))[0]
+    t_dir = time.perf_counter() - t0
+    tp, tm = torch.as_tensor(w.pos, device="cuda"), torch.as_tensor(w.mass, device="cuda")
+    tr = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream())
+    a_m, _ = tr.force(precision="mixed")
+    a_d, _ = tr.force(precision="fp64")
+    torch.cuda.synchronize()
+    tr.close()
+    a_t = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, prm))[0]
+    out["mixture32k"] = {"targets": n, "theta": prm["theta"], "direct_s": t_dir,
+                         "gpu_mixed": _err_stats(a_m.cpu().numpy(), a_dir),
+                         "gpu_fp64": _err_stats(a_d.cpu().numpy(), a_dir),
+                         "oracle_tree": _err_stats(a_t, a_dir)}
+    w = synth.mixture2m()
+    n = w.pos.shape[0]
+    tg = np.sort(np.random.default_rng(17).choice(n, 4096, replace=False))
+    t0 = time.perf_counter()
+    a_dir = oracle.direct(w.pos, w.mass, 1.0, _oracle_params(oracle, w.params.as_dict()), targets=tg)[0]
+    t_dir = time.perf_counter() - t0
+    tp, tm = torch.as_tensor(w.pos, device="cuda"), torch.as_tensor(w.mass, device="cuda")
+    tgd = torch.as_tensor(tg, dtype=torch.int64, device="cuda")
+    res = {"targets": int(tg.size), "direct_s": t_dir}
+    for theta in (0.3, 0.5, 0.7):
+        prm = dict(w.params.as_dict(), theta=theta)
+        tr = og.Tree(tp, tm, 1.0, prm, stream=torch.cuda.current_stream())
+        a_m, _ = tr.force(targets=tgd, precision="mixed")
+        a_d, _ = tr.force(targets=tgd, precision="fp64")
+        torch.cuda.synchronize()
+        tr.close()
+        a_t = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, prm), targets=tg)[0]
+        res["theta_%.1f" % theta] = {"gpu_mixed": _err_stats(a_m.cpu().numpy(), a_dir),
+                                     "gpu_fp64": _err_stats(a_d.cpu().numpy(), a_dir),
+                                     "oracle_tree": _err_stats(a_t, a_dir)}
+    med = [res["theta_%.1f" % th]["oracle_tree"]["median"] for th in (0.3, 0.5, 0.7)]
+    res["median_decreases_with_theta"] = bool(med[0] < med[1] < med[2])
+    out["mixture2m"] = res
+    out["vs"] = "brute-force direct sum (oracle), same erfc split, r_cut, Plummer softening, minimum image"
+    return out
+
+
+def leg_tuned(og, torch, synth, args):
+    """The 2M mixture with the leaf size searched too (tree build + mixed
+    walk timed for leaf_max 4, 8, 16 with both launch-shape knobs): the
+    fastest setting, its error against the oracle at that leaf size (65536
+    seeded targets) and against the direct sum (4096 seeded targets)."""
+    from paper_2609_17658_amd import tune
+    import oracle
+    w = synth.mixture2m()
+    n = w.pos.shape[0]
+    prm = w.params.as_dict()
+    tp, tm = torch.as_tensor(w.pos, device="cuda"), torch.as_tensor(w.mass, device="cuda")
+    res = tune.tune_tree(tp, tm, 1.0, prm, reps=3, log=log)
+    best = {k: res["best"][k] for k in ("group_max", "walk_list_cap", "leaf_max")}
+    p = dict(prm, **best)
+    tr = og.Tree(tp, tm, 1.0, p, stream=torch.cuda.current_stream())
+    a_m, _, ni = tr.force(precision="mixed", with_counts=True)
+    torch.cuda.synchronize()
+    tr.close()
+    a_m = a_m.cpu().numpy()
+    rng = np.random.default_rng(23)
+    tg = np.sort(rng.choice(n, 65536, replace=False))
+    a_o = oracle.tree_force(w.pos, w.mass, 1.0, _oracle_params(oracle, p), targets=tg)[0]
+    e = _rel_err(a_m[tg], a_o)
+    tgd = np.sort(np.random.default_rng(17).choice(n, 4096, replace=False))
+    a_dir = oracle.direct(w.pos, w.mass, 1.0, _oracle_params(oracle, p), targets=tgd)[0]
+    return {"best": best, "ms_per_step": res["best"]["ms"], "value": n / (res["best"]["ms"] * 1e-3),
+            "unit": "particles/s", "interactions_per_target": float(ni.sum().item()) / n,
+            "trials": res["trials"],
+            "error_vs_oracle_at_tuned_leaf": {"targets": int(tg.size), "mixed_median": float(np.median(e)),
+                                              "mixed_p99": float(np.percentile(e, 99))},
+            "error_vs_direct": dict(_err_stats(a_m[tgd], a_dir), targets=int(tgd.size)),
+            "workload": "mixture2m (the headline box) with leaf_max searched; the headline keeps leaf_max 8 "
+                        "as configured"}
 
 
 VARIANT_LEGS = (

@@ -376,7 +376,11 @@ __device__ inline void pair64(double dx, double dy, double dz, double m, double 
 // kExt: the spline softening and the relative criterion are read from each
 // box.
 constexpr int kWalk64Waves = 4;  // waves per workgroup
-constexpr int kWalk64Cap = 4;    // list entries per lane
+// List entries per lane: 4, or 3 for the instances with per-entry
+// softening lengths (kExt), so that lists, lengths and the evaluation slots
+// stay within 40 KB per workgroup (four workgroups, 16 waves, per CU).
+template <bool kExt>
+constexpr int walk64_cap() { return kExt ? 3 : 4; }
 
 // List entries: a monopole is (offset, mass), mass >= 0; a leaf has w = -1
 // and, in the bits of x, its first particle (bits 0..31), count (32..62)
@@ -409,10 +413,11 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
                                double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(off)
   // this lane's entry sizes (in items) and their total
-  uint32_t sz[kWalk64Cap];
+  constexpr int kCap = walk64_cap<kExt>();
+  uint32_t sz[kCap];
   uint32_t P = 0;
 #pragma unroll
-  for (int e = 0; e < kWalk64Cap; ++e) {
+  for (int e = 0; e < kCap; ++e) {
     sz[e] = (uint32_t)e < cnt ? entry_items64(list[e][lane]) : 0u;
     P += sz[e];
   }
@@ -431,7 +436,7 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
         *reinterpret_cast<uint4 *>(slots + at) = make_uint4(lane | (ce << 8), cj, p, 0u);
         uint32_t n = sz[0];
 #pragma unroll
-        for (int e = 1; e < kWalk64Cap; ++e) n = ce == (uint32_t)e ? sz[e] : n;
+        for (int e = 1; e < kCap; ++e) n = ce == (uint32_t)e ? sz[e] : n;
         ++cj;
         const bool next_entry = cj == n;
         ce += next_entry ? 1u : 0u;
@@ -504,8 +509,9 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
 template <bool kExt, bool kTail>
 __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk64(WalkArgs A) {
 #pragma clang fp contract(off)
-  __shared__ double4 lists[kWalk64Waves][kWalk64Cap][64];
-  __shared__ double lsofts[kExt ? kWalk64Waves : 1][kExt ? kWalk64Cap : 1][64];
+  constexpr int kCap = walk64_cap<kExt>();
+  __shared__ double4 lists[kWalk64Waves][kCap][64];
+  __shared__ double lsofts[kExt ? kWalk64Waves : 1][kExt ? kCap : 1][64];
   __shared__ double4 slotss[kWalk64Waves][64];
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double4(*list)[64] = lists[wv];
@@ -554,7 +560,7 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
     uint32_t next = valid ? n : nend;
     while (n < nend) {
       // room for this visit's entry
-      if (__ballot(cnt >= (uint32_t)kWalk64Cap))
+      if (__ballot(cnt >= (uint32_t)kCap))
         flush64<kExt, kTail>(A, list, lsoft, slots, lane, p, soft, bx, cnt, ax, ay, az, ph, ni);
       const Topo t = ld(A.topo + n);
       const Mom64 mm = ld(A.mom64 + n);

@@ -3,6 +3,8 @@
   python paper_2609_17658_amd/profiling.py walk --prec mixed --reps 3
       builds the 2M-particle mixture tree once and runs the force walk
       `reps` times (the build kernels run once, the walk kernel `reps` times);
+  python paper_2609_17658_amd/profiling.py build --reps 3 [--workload zeldovich256]
+      builds the tree `reps` times (every build kernel runs `reps` times);
   python paper_2609_17658_amd/profiling.py pm --n-grid 256 --reps 3
       the particle-mesh force of the same mixture on a 256^3 mesh;
   python paper_2609_17658_amd/profiling.py copy --mib 1024 --reps 3
@@ -32,6 +34,24 @@ def _walk(prec: str, reps: int, workload: str):
     torch.cuda.synchronize()
     t.close()
     print("walk %s x%d on %s: done" % (prec, reps, workload), flush=True)
+
+
+def _build(reps: int, workload: str):
+    import torch
+
+    from paper_2609_17658_amd import og, synth
+
+    w = synth.WORKLOADS[workload]()
+    dev = torch.device("cuda:0")
+    tp = torch.as_tensor(w.pos, device=dev)
+    tm = torch.as_tensor(w.mass, device=dev)
+    prm = w.params.as_dict()
+    ws = torch.empty(og.og_tree_workspace_bound(tp.shape[0], og.make_params(prm)), dtype=torch.uint8, device=dev)
+    for _ in range(reps):
+        t = og.Tree(tp, tm, w.box, prm, stream=torch.cuda.current_stream(), workspace=ws)
+        torch.cuda.synchronize()
+        t.close()
+    print("build x%d on %s: done" % (reps, workload), flush=True)
 
 
 def _pm(n_grid: int, reps: int, workload: str):
@@ -73,6 +93,9 @@ def main(argv=None):
     w.add_argument("--prec", default="mixed")
     w.add_argument("--reps", type=int, default=3)
     w.add_argument("--workload", default="mixture2m")
+    b = sub.add_parser("build")
+    b.add_argument("--reps", type=int, default=3)
+    b.add_argument("--workload", default="mixture2m")
     m = sub.add_parser("pm")
     m.add_argument("--n-grid", type=int, default=256)
     m.add_argument("--reps", type=int, default=3)
@@ -83,6 +106,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "walk":
         _walk(a.prec, a.reps, a.workload)
+    elif a.cmd == "build":
+        _build(a.reps, a.workload)
     elif a.cmd == "pm":
         _pm(a.n_grid, a.reps, a.workload)
     else:
