@@ -59,7 +59,8 @@ enum {
     OG_EDEVICE = -4,      /* a HIP runtime error */
     OG_EBUSY = -5,        /* server: over budget and queue full */
     OG_EUNSUPPORTED = -6, /* valid request the library does not handle */
-    OG_ENOTFOUND = -7     /* server: unknown ticket */
+    OG_ENOTFOUND = -7,    /* server: unknown ticket */
+    OG_ECORRUPT = -8      /* og_tree_validate: a tree invariant does not hold */
 };
 
 /* Arithmetic of the walk.  FP64: every step in double precision.  MIXED:
@@ -259,6 +260,33 @@ int og_tree_stats(const og_tree *tree, int64_t *n_nodes, int32_t *depth, size_t 
 int og_tree_export(const og_tree *tree, uint64_t *keys, uint32_t *perm, uint32_t *first,
                    uint32_t *count, uint8_t *level, uint32_t *skip, uint32_t *parent,
                    double *node_m_com);
+
+/* Check a built tree's invariants on the host (synchronises; copies the
+ * tree's arrays to host memory, O(N + n_nodes) work and host memory, so it
+ * is a test and audit tool, not part of a time step).  The invariants are
+ * those of the paper's "Tree construction" (particles in space-filling-
+ * curve order, the recursive 8-way cube hierarchy in pre-order with
+ * first-child / sibling links, mass and centre of mass from the bottom-up
+ * pass) and of this library's derived records:
+ *   - keys sorted; perm a permutation of [0,N); every particle's key is the
+ *     key of its position; periodic positions inside [0,box);
+ *   - node 0 is the root: level 0, particles [0,N), no parent, skip = the
+ *     node count;
+ *   - every node holds a non-empty particle range whose keys share the
+ *     node's prefix, and its corner is aligned to its level; a node is a
+ *     leaf iff it holds at most leaf_max particles or is at the finest
+ *     level (21);
+ *   - an internal node's children (node+1, then along skip) are 1..8 nodes
+ *     one level down, in distinct octants of its cube, with parent links to
+ *     it, whose particle ranges tile its range in order; a leaf's skip is
+ *     the next node;
+ *   - a node's mass is the sum of its particles' (children's) masses and
+ *     its centre of mass is theirs, inside its cube; FP32 copies, softening
+ *     ranges and walk records agree with the FP64 values.
+ * Returns OG_OK, OG_ERANGE (the build reported out-of-range positions),
+ * OG_ECORRUPT (og_last_error() names the first violation), OG_EINVAL (NULL
+ * tree) or OG_EDEVICE. */
+int og_tree_validate(const og_tree *tree);
 
 /* Free the tree and its device memory (not a caller workspace).  Waits for
  * the tree's stream first. */

@@ -13,11 +13,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libog.so")
-SOURCES = ["k_build.hip", "k_walk.hip", "k_pm.hip", "og_api.cpp", "og_server.cpp", "og_pm.cpp"]
+SOURCES = ["k_build.hip", "k_walk.hip", "k_pm.hip", "og_api.cpp", "og_server.cpp", "og_pm.cpp", "og_validate.cpp"]
 ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-unused-value"]
+_ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# roctx: named host ranges around API calls and build stages (OG_TRACE=1)
+ROCTX = ["-L" + os.path.join(_ROCM, "lib"), "-Wl,-rpath," + os.path.join(_ROCM, "lib"),
+         "-lrocprofiler-sdk-roctx"]
 
 
 def _hipcc():
@@ -41,7 +45,7 @@ def build(verbose: bool = False) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ROCTX
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr)

@@ -848,28 +848,44 @@ void launch_build(BuildArrays &A, hipStream_t s) {
   const bool odd = ((8 + box_passes) & 1) != 0;
   uint64_t *k0 = odd ? A.keys_b : A.keys_a, *k1 = odd ? A.keys_a : A.keys_b;
   uint32_t *v0 = odd ? A.vals_b : A.vals_a, *v1 = odd ? A.vals_a : A.vals_b;
-  k_keys<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, k0, v0, &A.scalars[0]);
-  radix_sort(k0, v0, k1, v1, n, 0, 8, box_passes, A.boxes, A.B, A.hist, A.digit_tot, s);
+  {
+    const TraceRange r("build: keys");
+    k_keys<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, k0, v0, &A.scalars[0]);
+  }
+  {
+    const TraceRange r("build: radix sort");
+    radix_sort(k0, v0, k1, v1, n, 0, 8, box_passes, A.boxes, A.B, A.hist, A.digit_tot, s);
+  }
   const uint64_t *skeys = A.keys_a;
-  k_gather<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.vals_a, A.perm, A.inv, A.part64, A.seps, &A.scalars[0]);
-  k_lcp_depth<<<nb, kThreads, kThreads + 2 * A.leaf_max + 1, s>>>(A.boxes, A.B, n, A.leaf_max, skeys, A.lcp,
-                                                                  A.depth, A.nstart);
-  scan_u32(A.nstart, A.S, &A.scalars[4], n, A.scan_partial, s);
-  k_box_nodes<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.S, n, A.node_cap, A.scalars, A.parent);
-  k_emit<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.S, A.node_cap, A.topo,
-                                 A.first, A.skip);
+  {
+    const TraceRange r("build: gather");
+    k_gather<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.vals_a, A.perm, A.inv, A.part64, A.seps, &A.scalars[0]);
+  }
   const uint32_t gnodes = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kThreads), 8192));
-  k_links<<<gnodes, kThreads, 0, s>>>(A.topo, A.skip, A.scalars, A.node_cap, A.parent, A.nchild, A.lvl_cnt);
-  k_leaves_and_buckets<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.part64, A.part32, A.mom64,
-                                                   A.mom32, A.scalars, A.node_cap, A.lvl_cnt, A.lvl_fill,
-                                                   A.lvl_nodes, A.seps, A.semax, A.semin);
-  // internal nodes at level L number at most n / (leaf_max + 1) <= n / 2; most
-  // levels hold few, so a small grid (grid-stride) keeps the launches short
-  const uint32_t glev = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(n / 2 + 1, kThreads), 512));
-  for (int L = kLevels - 1; L >= 0; --L)
-    k_moments_level<<<glev, kThreads, 0, s>>>(A.boxes, A.B, L, A.topo, A.first, A.skip, A.lvl_cnt,
-                                              A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32, A.semax,
-                                              A.semin);
+  {
+    const TraceRange r("build: topology");
+    k_lcp_depth<<<nb, kThreads, kThreads + 2 * A.leaf_max + 1, s>>>(A.boxes, A.B, n, A.leaf_max, skeys, A.lcp,
+                                                                    A.depth, A.nstart);
+    scan_u32(A.nstart, A.S, &A.scalars[4], n, A.scan_partial, s);
+    k_box_nodes<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.S, n, A.node_cap, A.scalars, A.parent);
+    k_emit<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.S, A.node_cap, A.topo,
+                                   A.first, A.skip);
+    k_links<<<gnodes, kThreads, 0, s>>>(A.topo, A.skip, A.scalars, A.node_cap, A.parent, A.nchild, A.lvl_cnt);
+  }
+  {
+    const TraceRange r("build: moments");
+    k_leaves_and_buckets<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.part64, A.part32, A.mom64,
+                                                     A.mom32, A.scalars, A.node_cap, A.lvl_cnt, A.lvl_fill,
+                                                     A.lvl_nodes, A.seps, A.semax, A.semin);
+    // internal nodes at level L number at most n / (leaf_max + 1) <= n / 2; most
+    // levels hold few, so a small grid (grid-stride) keeps the launches short
+    const uint32_t glev = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(n / 2 + 1, kThreads), 512));
+    for (int L = kLevels - 1; L >= 0; --L)
+      k_moments_level<<<glev, kThreads, 0, s>>>(A.boxes, A.B, L, A.topo, A.first, A.skip, A.lvl_cnt,
+                                                A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32, A.semax,
+                                                A.semin);
+  }
+  const TraceRange r("build: walk records");
   k_wnodes<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.mom32, A.first, A.scalars, A.node_cap,
                                        A.wnode, A.cen64);
 }

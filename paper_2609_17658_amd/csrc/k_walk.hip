@@ -1418,6 +1418,7 @@ static bool env_flag(const char *name) {
 static bool wide_nodes_forced() { return env_flag("OG_WIDE_NODES"); }
 
 void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
+  const TraceRange trace_range(precision == 0 ? "walk: fp64" : "walk: mixed");
   WalkArgs W = W0;
   W.no_interior = env_flag("OG_NO_INTERIOR") ? 1 : 0;
   const uint32_t cus = (uint32_t)device_cu_count();

@@ -14,6 +14,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/og.h"
 #include "og_forest.h"
 
@@ -49,6 +51,20 @@ bool is_device_ptr(const void *p) {
     return false;
   }
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+bool trace_on() {
+  static const bool on = [] {
+    const char *e = std::getenv("OG_TRACE");
+    return e && std::atoi(e) == 1;
+  }();
+  return on;
+}
+TraceRange::TraceRange(const char *name) : on(trace_on()) {
+  if (on) roctxRangePushA(name);
+}
+TraceRange::~TraceRange() {
+  if (on) roctxRangePop();
 }
 
 bool fault_fires(FaultKind k) {
@@ -556,6 +572,7 @@ size_t og_tree_workspace_bound(int64_t N, const og_params *p) {
 
 int og_tree_build(const double *pos, const double *mass, int64_t N, double box, const og_params *params,
                   og_tree **out) {
+  const TraceRange trace_range("og_tree_build");
   if (!out) return fail(OG_EINVAL, "out is NULL");
   int rc = check_params(params, N, box, true);
   if (rc) return rc;
@@ -580,6 +597,7 @@ int og_tree_build(const double *pos, const double *mass, int64_t N, double box, 
 
 int og_tree_force_ex(const og_tree *tree, const og_targets *targets, const og_force_opts *opts, double *acc,
                      double *pot) {
+  const TraceRange trace_range("og_tree_force");
   if (!tree) return fail(OG_EINVAL, "tree is NULL");
   og_tree *t = const_cast<og_tree *>(tree);
   Forest &F = t->F;
@@ -626,6 +644,7 @@ int og_tree_force(const og_tree *tree, const og_targets *targets, double *acc, d
 }
 
 int og_tree_force_noalloc(const og_tree *tree, const og_targets *targets, double *acc, double *pot) {
+  const TraceRange trace_range("og_tree_force_noalloc");
   if (!tree) return fail(OG_EINVAL, "tree is NULL");
   og_tree *t = const_cast<og_tree *>(tree);
   Forest &F = t->F;
@@ -651,6 +670,7 @@ int og_tree_force_noalloc(const og_tree *tree, const og_targets *targets, double
 
 int og_tree_force_active(const og_tree *tree, const int8_t *bin, int32_t level, const og_force_opts *opts,
                          double *acc, double *pot, int64_t *n_active) {
+  const TraceRange trace_range("og_tree_force_active");
   if (!tree) return fail(OG_EINVAL, "tree is NULL");
   og_tree *t = const_cast<og_tree *>(tree);
   Forest &F = t->F;
@@ -757,6 +777,7 @@ int og_tree_free(og_tree *tree) {
 
 // ---------------------------------------------------------------- batch --
 int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out) {
+  const TraceRange trace_range("og_batch_build");
   if (!out || !boxes) return fail(OG_EINVAL, "NULL argument");
   if (B < 1 || B > 65536) return fail(OG_EINVAL, "B = %d outside 1..65536", B);
   std::vector<BoxDev> hb(B);
@@ -798,11 +819,13 @@ int og_batch_build(const og_box *boxes, int32_t B, void *stream, og_batch **out)
 }
 
 int og_batch_force(og_batch *b) {
+  const TraceRange trace_range("og_batch_force");
   if (!b) return fail(OG_EINVAL, "batch is NULL");
   return b->F.walk_all(b->F.precision, b->F.stream, nullptr, nullptr, 0, nullptr);
 }
 
 int og_batch_graph_replay(og_batch *b) {
+  const TraceRange trace_range("og_batch_graph_replay");
   if (!b) return fail(OG_EINVAL, "batch is NULL");
   Forest &F = b->F;
   hipStream_t cs = F.stream;
@@ -877,6 +900,7 @@ const char *og_strerror(int code) {
     case OG_EBUSY: return "busy";
     case OG_EUNSUPPORTED: return "unsupported";
     case OG_ENOTFOUND: return "not found";
+    case OG_ECORRUPT: return "tree invariant violated";
     default: return "unknown error";
   }
 }

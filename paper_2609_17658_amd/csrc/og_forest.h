@@ -27,7 +27,8 @@ bool is_device_ptr(const void *p);
 // library (tree workspace, server arena, a served request's admission,
 // target and active-set scratch, mesh) fail with OG_ENOMEM; OG_FAULT_LAUNCH=k
 // makes the k-th enqueue of a build or a walk fail with OG_EDEVICE.  The
-// count restarts whenever the variable's value changes.
+// count restarts whenever the variable's value changes.  (og_tree_validate
+// has its own knob, OG_FAULT_CORRUPT, which edits its host copy only.)
 enum FaultKind { kFaultAlloc = 0, kFaultLaunch = 1 };
 bool fault_fires(FaultKind k);
 int check_params(const og_params *p, int64_t N, double box, bool need_stream_fields);

@@ -18,6 +18,20 @@ constexpr int kCountBits = 27;              // node particle count field width
 constexpr uint32_t kCountMask = (1u << kCountBits) - 1u;
 constexpr uint64_t kLeafBit = 1ull << 63;   // in Topo::corner
 
+// Host-side stage ranges for profilers (roctx), the analogue of the paper's
+// code timers: with OG_TRACE=1 in the environment every API call and build
+// stage pushes a named range around the work it enqueues (host enqueue
+// intervals; the kernels they enqueue appear beside them in a marker trace,
+// e.g. rocprofv3 --marker-trace --kernel-trace).  Off by default.
+bool trace_on();
+struct TraceRange {
+  bool on;
+  explicit TraceRange(const char *name);
+  ~TraceRange();
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
+
 // Status bits written by kernels (read by the host at sync points).
 constexpr uint32_t kStatusRange = 1u;       // a position outside the box
 constexpr uint32_t kStatusNodes = 2u;       // node bound exceeded (never expected)

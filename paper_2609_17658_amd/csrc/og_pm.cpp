@@ -69,6 +69,7 @@ int og_pm_create(int32_t n_grid, double box, double G, double r_s, void *stream,
 
 int og_pm_force(og_pm *pm, const double *pos, const double *mass, int64_t N, double *acc, double *pot,
                 int32_t accumulate) {
+  const og::TraceRange trace_range("og_pm_force");
   if (!pm) return fail(OG_EINVAL, "pm is NULL");
   if (N < 1 || N > 0x7fffffffll) return fail(OG_EINVAL, "N = %lld outside [1, 2^31-1]", (long long)N);
   if (!is_device_ptr(pos) || !is_device_ptr(mass) || !is_device_ptr(acc) || (pot && !is_device_ptr(pot)))
@@ -94,6 +95,7 @@ int og_pm_force(og_pm *pm, const double *pos, const double *mass, int64_t N, dou
 }
 
 int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, int32_t accumulate) {
+  const og::TraceRange trace_range("og_pm_force_tree");
   if (!pm || !tree) return fail(OG_EINVAL, "pm or tree is NULL");
   const Forest &F = tree->F;
   const BoxDev &b = F.hboxes[0];

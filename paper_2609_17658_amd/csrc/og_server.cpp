@@ -243,6 +243,7 @@ int og_server_create(size_t hbm_budget_bytes, int32_t max_slots, og_server **out
 }
 
 int og_server_submit(og_server *s, const og_box *req, uint64_t *ticket) {
+  const og::TraceRange trace_range("og_server_submit");
   if (!s || !req || !ticket) return fail(OG_EINVAL, "NULL argument");
   int rc = check_params(&req->params, req->N, req->box, false);
   if (rc) return rc;

@@ -15,8 +15,8 @@ from dataclasses import asdict, is_dataclass
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libog.so")
 
-OG_OK, OG_EINVAL, OG_ERANGE, OG_ENOMEM, OG_EDEVICE, OG_EBUSY, OG_EUNSUPPORTED, OG_ENOTFOUND = \
-    0, -1, -2, -3, -4, -5, -6, -7
+OG_OK, OG_EINVAL, OG_ERANGE, OG_ENOMEM, OG_EDEVICE, OG_EBUSY, OG_EUNSUPPORTED, OG_ENOTFOUND, OG_ECORRUPT = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 OG_PREC_FP64, OG_PREC_MIXED = 0, 1
 PRECISIONS = {"fp64": OG_PREC_FP64, "mixed": OG_PREC_MIXED, OG_PREC_FP64: OG_PREC_FP64,
               OG_PREC_MIXED: OG_PREC_MIXED}
@@ -75,6 +75,7 @@ _SIGNATURES = {
     "og_tree_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_size_t)]),
     "og_tree_export": (ctypes.c_int, [_P] * 9),
+    "og_tree_validate": (ctypes.c_int, [_P]),
     "og_tree_free": (ctypes.c_int, [_P]),
     "og_batch_build": (ctypes.c_int, [ctypes.POINTER(og_box), ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "og_batch_force": (ctypes.c_int, [_P]),
@@ -270,6 +271,12 @@ def og_tree_export(tree, N: int):
     return out
 
 
+def og_tree_validate(tree):
+    """Host-side check of the tree's invariants; raises OgError (code
+    OG_ECORRUPT, message naming the first violation) when one fails."""
+    return _check(load().og_tree_validate(tree))
+
+
 def og_tree_free(tree):
     if tree:
         _check(load().og_tree_free(tree))
@@ -391,6 +398,9 @@ class Tree:
 
     def export(self):
         return og_tree_export(self.handle, self.N)
+
+    def validate(self):
+        return og_tree_validate(self.handle)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -124,3 +124,9 @@ def test_build_rejects_host_softening_lengths():
     p = og.make_params(r_s=0.01, eps_particle=eps.ctypes.data)
     h = ctypes.c_void_p()
     assert lib.og_tree_build(None, None, 100, 1.0, ctypes.byref(p), ctypes.byref(h)) == og.OG_EINVAL
+
+
+def test_validate_rejects_null_and_names_its_error():
+    lib = og.load()
+    assert lib.og_tree_validate(None) == og.OG_EINVAL
+    assert lib.og_strerror(og.OG_ECORRUPT) == b"tree invariant violated"
