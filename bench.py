@@ -935,12 +935,18 @@ def leg_active(og, torch, synth, args):
 
 
 def pm_bytes(n_particles, n_grid):
-    """Algorithmic HBM bytes of one mesh force: deposit 32 B/particle read +
-    8 atomics x 8 B; clear 8, density 8 + 16, three 3-D FFTs of three passes
-    each reading and writing 16 B, Green's function 16 + 32, per cell;
-    interpolation 32 B/particle read, 8 gathers x 32 B, 32 B written."""
+    """Algorithmic HBM bytes of one og_pm_force_tree call, each array the
+    pipeline needs read or written once: per particle, the deposit reads
+    32 B, the interpolation reads 32 B and writes 32 B (acc + pot); per mesh
+    cell, the deposit writes the 8-byte fixed-point sum, the forward z pass
+    reads it and writes 16 B, the y pass reads and writes 16 B, the x pass
+    (with the Green's function and both inverse x passes) reads 16 B and
+    writes 32 B, the inverse y and z passes of both fields read and write
+    4 x 32 B, and the interpolation reads both fields (32 B).  The block
+    halos (217 of 729 tile nodes, 6.8 B per cell written and read) are not
+    counted."""
     cells = n_grid ** 3
-    return n_particles * (32 + 64 + 32 + 256 + 32) + cells * (8 + 24 + 9 * 32 + 48)
+    return n_particles * (32 + 32 + 32) + cells * (8 + 24 + 32 + 48 + 128 + 32)
 
 
 def leg_pm(og, torch, synth, args):
@@ -948,6 +954,22 @@ def leg_pm(og, torch, synth, args):
     long-range on a mesh of 2 N^(1/3) points per axis (r_s = 1.25 mesh
     cells), for the headline box and the 256^3 Zel'dovich box."""
     out = {}
+    # the device's streaming rate: a 1 GiB device-to-device copy (read + write)
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ec = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ec[0].record()
+    for _ in range(10):
+        b.copy_(a)
+    ec[1].record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * (1 << 30) / (ec[0].elapsed_time(ec[1]) / 10 * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    out["copy_1GiB_GBps"] = copy_gbps
     for name, make, n_grid, reps in (("mixture2m", lambda: synth.mixture2m(theta=args.theta), 256, 5),
                                      ("zeldovich256", synth.zeldovich256, 512, 3)):
         w = make()
@@ -999,7 +1021,8 @@ def leg_pm(og, torch, synth, args):
                                "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                                "frac": pm_bytes(n, n_grid) / (pm_tree_ms * 1e-3) / PEAK_HBM,
                                "kernel": "og_pm_force_tree (all mesh kernels of one call)",
-                               "algorithmic_bytes": pm_bytes(n, n_grid)}}
+                               "algorithmic_bytes": pm_bytes(n, n_grid),
+                               "frac_of_copy_rate": pm_bytes(n, n_grid) / (pm_tree_ms * 1e-3) / 1e9 / copy_gbps}}
         if not args.no_oracle and name == "mixture2m":
             from oracle import pm as opm
             rng = np.random.default_rng(13)

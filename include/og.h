@@ -377,7 +377,9 @@ int og_server_destroy(og_server *s);
  * [0, L) are wrapped. */
 typedef struct og_pm og_pm;
 
-/* Device bytes an n_grid^3 mesh holds (32 n^3 + 256); 0 if n_grid invalid. */
+/* Device bytes an n_grid^3 mesh holds: 32 n^3 + 256, plus 24 n bytes of
+ * FFT and deconvolution tables and (n/8)^3 + 1 words of block starts, each
+ * rounded up to 256 bytes; 0 if n_grid invalid. */
 size_t og_pm_workspace_bound(int32_t n_grid);
 /* n_grid: power of two in 8..1024; box > 0; r_s > 0 (the split scale of
  * the tree); stream: hipStream_t or NULL.  Allocates the mesh.  Errors:
@@ -392,10 +394,14 @@ int og_pm_create(int32_t n_grid, double box, double G, double r_s, void *stream,
 int og_pm_force(og_pm *pm, const double *pos, const double *mass, int64_t N, double *acc, double *pot,
                 int32_t accumulate);
 /* As og_pm_force for the particles of a built periodic tree whose box side
- * equals the mesh's: the mesh is read back in the tree's curve order
- * (neighbouring threads share cells in cache), and acc/pot (device,
- * [N][3] and [N] or NULL) are written in caller order.  Ordered after the
- * tree's build on its stream.  Errors: OG_EINVAL, OG_EDEVICE. */
+ * equals the mesh's, with the same result to the bit.  The tree's curve
+ * order makes every block of 8^3 mesh cells a contiguous run of its
+ * particles, so each block is deposited and interpolated by one workgroup
+ * through a tile of its 9^3 nodes in LDS (the block's nodes are written
+ * once, without atomics; blocks of more than 2048 particles hand the rest
+ * to per-particle kernels).  acc/pot (device, [N][3] and [N] or NULL) are
+ * written in caller order.  Ordered after the tree's build on its stream.
+ * Errors: OG_EINVAL, OG_EDEVICE. */
 int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, int32_t accumulate);
 /* Waits for the mesh's stream and frees it. */
 int og_pm_free(og_pm *pm);

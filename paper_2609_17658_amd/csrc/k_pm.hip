@@ -7,20 +7,26 @@
 // of the split, the mesh the erf part.
 //
 // Layout: an n^3 mesh of complex FP64 values (double2), index (x*n + y)*n + z.
-//   1. deposit: cloud-in-cell weights onto the nodes j*L/n, summed with
-//      64-bit fixed-point atomics (a power-of-two scale fitted to N * max m),
-//      so the mesh does not depend on the order of the atomic additions;
-//   2. forward 3-D FFT of the density (three passes of length-n transforms
-//      along z, y and x; each workgroup transforms a tile of neighbouring
-//      lines in LDS, so every pass reads and writes whole cache lines);
-//   3. per wave vector: phi_k = -4 pi G exp(-k^2 r_s^2) / k^2 / W(k)^2 rho_k,
-//      W the CIC window, and a_k = -i k phi_k; the two inverse transforms
-//      carry (a_x + i a_y) and (a_z + i phi), each a pair of real fields;
-//   4. inverse FFTs, then CIC interpolation at the particles.
+//   1. deposit: cloud-in-cell weights onto the nodes j*L/n, summed in
+//      64-bit fixed point (a power-of-two scale fitted to N * max m), so
+//      the mesh does not depend on the order of the additions.  Caller
+//      order: atomics onto the mesh.  A tree's curve order: one workgroup
+//      per block of 8^3 cells sums its particles in LDS and stores its
+//      nodes (plus a halo for the blocks above);
+//   2. forward 3-D FFT of the density: length-n transforms along z (the
+//      pass that reads the fixed-point sums), y and x; each workgroup
+//      transforms a tile of neighbouring lines in LDS, so every pass reads
+//      and writes whole cache lines;
+//   3. per wave vector, in the x pass: phi_k = -4 pi G exp(-k^2 r_s^2) /
+//      k^2 / W(k)^2 rho_k, W the CIC window, and a_k = -i k phi_k; two
+//      inverse transforms carry (a_x + i a_y) and (a_z + i phi), each a
+//      pair of real fields, and their x passes run in the same workgroup;
+//   4. the inverse y and z passes, then CIC interpolation at the particles.
 #include <climits>
 #include <cmath>
 #include <cstdlib>
 
+#include "og_internal.h"
 #include "og_pm.h"
 
 namespace og {
@@ -121,13 +127,193 @@ __global__ __launch_bounds__(kPmThreads) void k_deposit(PartRef P, uint32_t N, i
 // or spread out) does.
 constexpr int kDepositTile = 4096;  // nodes (32 KB)
 
+// ------------------------------------------------------ mesh blocks --
+// Tree order (a periodic tree whose root cube is the mesh box, n = 2^k):
+// the mesh cell of a particle is the top k bits of its level-21 tree cell,
+// so the particles of a block of 8^3 cells (a cube of the tree at level
+// k - 3) are one contiguous run of the sorted keys, starting at
+// bstart[h] for the block whose key prefix is h.  A block's particles
+// touch the 9^3 nodes lo .. lo + 8 of each axis: its own 8^3 (which no
+// other block's interior holds) and 217 halo nodes shared with the blocks
+// above it.
+constexpr int kBlk = 8;                                        // cells per block edge
+constexpr int kTile = kBlk + 1;                                // nodes per tile edge
+constexpr int kTile3 = kTile * kTile * kTile;                  // 729
+constexpr int kHalo = kTile3 - kBlk * kBlk * kBlk;             // 217
+constexpr uint32_t kBlockChunk = 2048;  // particles a block's own workgroup takes
+
+// Workgroups are dealt to the 8 XCDs in turn (g % 8), each XCD with its
+// own L2.  Giving XCD j the j-th contiguous share of the work units keeps
+// neighbouring units (which share mesh nodes) in one L2.  A bijection of
+// [0, G) for any G.
+constexpr uint32_t kXcds = 8;
+__device__ inline uint32_t xcd_unit(uint32_t g, uint32_t G) {
+  const uint32_t q = G / kXcds, r = G % kXcds, j = g % kXcds, i = g / kXcds;
+  return j * q + min(j, r) + i;
+}
+
+struct BlockRef {
+  const uint64_t *keys;
+  const uint32_t *bstart;
+  int shift3;   // key bits below the block prefix: 3 (21 - (k - 3))
+  int curve;
+  double tscale;  // 2^21 / L, the tree's cell scale
+};
+
+// A particle beyond the first kBlockChunk of its block (handled by the
+// per-particle kernels).
+__device__ inline bool block_extra(const BlockRef &R, uint32_t i) {
+  return i - R.bstart[(uint32_t)(R.keys[i] >> R.shift3)] >= kBlockChunk;
+}
+
+__global__ __launch_bounds__(kPmThreads) void k_block_starts(BlockRef R, uint32_t N, uint32_t nblocks,
+                                                             uint32_t *bstart) {
+  const uint32_t h = blockIdx.x * kPmThreads + threadIdx.x;
+  if (h > nblocks) return;
+  uint32_t lo = 0, hi = N;  // first particle whose prefix is >= h
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if ((R.keys[mid] >> R.shift3) < (uint64_t)h) lo = mid + 1;
+    else hi = mid;
+  }
+  bstart[h] = lo;
+}
+
+// Lower mesh corner (in cells) of block h: the cell of its first key.
+__device__ inline void block_corner(const BlockRef &R, uint32_t h, int logn, int g0[3]) {
+  uint32_t c[3];
+  key_cell((uint64_t)h << R.shift3, R.curve, c);
+  const int sh = kLevels - logn + 3;
+  for (int k = 0; k < 3; ++k) g0[k] = (int)(c[k] >> sh) * kBlk;
+}
+
+// A particle's CIC node offsets inside its block's tile (0..7) and
+// fractions.  The cell is the tree's (the key was formed from it); the
+// fraction is x n / L minus that cell, as cic() forms it (the two differ
+// only where x n / L rounds up to n, where both put the whole weight on
+// node n = node 0).
+__device__ inline void tile_cic(const double4 &q, const BlockRef &R, int logn, double inv_d, const int g0[3],
+                                int r[3], double f[3]) {
+  const double xs[3] = {q.x, q.y, q.z};
+  const int sh = kLevels - logn;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double v = xs[k] * R.tscale;
+    const uint32_t cell = !(v >= 0.0) ? 0u : (v >= 2097151.0 ? 2097151u : (uint32_t)v);
+    const int ix = (int)(cell >> sh);
+    r[k] = min(max(ix - g0[k], 0), kBlk - 1);
+    f[k] = xs[k] * inv_d - (double)ix;
+  }
+}
+
+__device__ inline int halo_index(int tx, int ty, int tz) {
+  // faces x = 8 (9 x 9), y = 8 (8 x 9), z = 8 (8 x 8)
+  return tx == kBlk ? ty * kTile + tz : (ty == kBlk ? 81 + tx * kTile + tz : 153 + tx * kBlk + ty);
+}
+
+// One workgroup per block: the block's first kBlockChunk particles summed
+// in an LDS tile, then its 8^3 own nodes stored to the mesh (every node of
+// the mesh is some block's own node, so the mesh needs no clearing) and
+// its halo to halo[block] (added by k_density_blocks).
+__global__ __launch_bounds__(kPmThreads) void k_deposit_blocks(const double4 *part, BlockRef R, uint32_t N, int n,
+                                                               int logn, double inv_d,
+                                                               const unsigned long long *mmax,
+                                                               unsigned long long *mesh,
+                                                               unsigned long long *halo) {
+  __shared__ unsigned long long tile[kTile3];
+  const uint32_t h = xcd_unit(blockIdx.x, gridDim.x);
+  const uint32_t s = R.bstart[h], e = min(R.bstart[h + 1], s + kBlockChunk);
+  int g0[3];
+  block_corner(R, h, logn, g0);
+  for (int c = threadIdx.x; c < kTile3; c += kPmThreads) tile[c] = 0ull;
+  __syncthreads();
+  const double scale = fixed_scale(mmax, N);
+  for (uint32_t p = s + threadIdx.x; p < e; p += kPmThreads) {
+    const double4 q = part[p];
+    int r[3];
+    double f[3];
+    tile_cic(q, R, logn, inv_d, g0, r, f);
+    const double m = q.w * scale;
+    const double w[3][2] = {{1.0 - f[0], f[0]}, {1.0 - f[1], f[1]}, {1.0 - f[2], f[2]}};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const unsigned long long qv = (unsigned long long)llrint(m * w[0][a] * w[1][b] * w[2][c]);
+          atomicAdd(&tile[((r[0] + a) * kTile + r[1] + b) * kTile + r[2] + c], qv);
+        }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < kBlk * kBlk * kBlk; c += kPmThreads) {
+    const int lx = c >> 6, ly = (c >> 3) & 7, lz = c & 7;
+    mesh[((uint64_t)(g0[0] + lx) * n + (g0[1] + ly)) * n + (g0[2] + lz)] = tile[(lx * kTile + ly) * kTile + lz];
+  }
+  const uint32_t nb = (uint32_t)n / kBlk;
+  unsigned long long *hb =
+      halo + (((uint64_t)(g0[0] / kBlk) * nb + (uint32_t)(g0[1] / kBlk)) * nb + (uint32_t)(g0[2] / kBlk)) * kHalo;
+  for (int c = threadIdx.x; c < kHalo; c += kPmThreads) {
+    int tx, ty, tz;
+    if (c < 81) {
+      tx = kBlk;
+      ty = c / kTile;
+      tz = c % kTile;
+    } else if (c < 153) {
+      tx = (c - 81) / kTile;
+      ty = kBlk;
+      tz = (c - 81) % kTile;
+    } else {
+      tx = (c - 153) / kBlk;
+      ty = (c - 153) % kBlk;
+      tz = kBlk;
+    }
+    hb[c] = tile[(tx * kTile + ty) * kTile + tz];
+  }
+}
+
+// A node's fixed-point sum: the mesh entry plus, with block halos, the
+// halo entries of the blocks below it that touch it (up to 7, for a block
+// corner).  Unsigned sums: the same value as any other order of adding the
+// same weights.
+__device__ inline unsigned long long node_sum(const unsigned long long *mesh, const unsigned long long *halo,
+                                              uint64_t i, int gx, int gy, int gz, int n) {
+  unsigned long long v = mesh[i];
+  if (halo == nullptr) return v;
+  const int lx = gx & (kBlk - 1), ly = gy & (kBlk - 1), lz = gz & (kBlk - 1);
+  const int nb = n / kBlk, bm = nb - 1;
+  const int bx = gx / kBlk, by = gy / kBlk, bz = gz / kBlk;
+  // the block (bx - dx, by - dy, bz - dz) holds this node as tile node
+  // (lx + 8 dx, ly + 8 dy, lz + 8 dz) when every shifted axis has l = 0
+  auto from = [&](int dx, int dy, int dz) {
+    const uint64_t blk = ((uint64_t)((bx - dx) & bm) * nb + ((by - dy) & bm)) * nb + ((bz - dz) & bm);
+    return halo[blk * kHalo + halo_index(lx + kBlk * dx, ly + kBlk * dy, lz + kBlk * dz)];
+  };
+  if (lz == 0) v += from(0, 0, 1);
+  if (ly == 0) {
+    v += from(0, 1, 0);
+    if (lz == 0) v += from(0, 1, 1);
+  }
+  if (lx == 0) {
+    v += from(1, 0, 0);
+    if (lz == 0) v += from(1, 0, 1);
+    if (ly == 0) {
+      v += from(1, 1, 0);
+      if (lz == 0) v += from(1, 1, 1);
+    }
+  }
+  return v;
+}
+
 __global__ __launch_bounds__(kPmThreads) void k_deposit_tiled(PartRef P, uint32_t N, int n, double inv_d,
                                                               const unsigned long long *mmax,
-                                                              unsigned long long *acc_mesh) {
+                                                              unsigned long long *acc_mesh, BlockRef R) {
   __shared__ unsigned long long tile[kDepositTile];
   __shared__ int red[6][kPmThreads / 64];
-  const uint32_t i = blockIdx.x * kPmThreads + threadIdx.x;
-  const bool ok = i < N;
+  const uint32_t i = xcd_unit(blockIdx.x, gridDim.x) * kPmThreads + threadIdx.x;
+  // with block starts: only the particles the block workgroups left
+  const bool ok = i < N && (R.bstart == nullptr || block_extra(R, i));
+  if (R.bstart != nullptr && __syncthreads_or(ok) == 0) return;
   const double scale = fixed_scale(mmax, N);
   int ix = 0, iy = 0, iz = 0;
   double fx = 0.0, fy = 0.0, fz = 0.0, m = 0.0;
@@ -205,44 +391,24 @@ __global__ __launch_bounds__(kPmThreads) void k_deposit_tiled(PartRef P, uint32_
   }
 }
 
-// Fixed point -> density (mass / cell volume), as the real part.
-__global__ __launch_bounds__(kPmThreads) void k_density(const unsigned long long *acc_mesh, uint64_t cells,
-                                                        uint32_t N, const unsigned long long *mmax,
-                                                        double inv_vol, double2 *rho) {
-  const double f = inv_vol / fixed_scale(mmax, N);
-  for (uint64_t i = blockIdx.x * (uint64_t)kPmThreads + threadIdx.x; i < cells;
-       i += (uint64_t)gridDim.x * kPmThreads)
-    rho[i] = make_double2((double)acc_mesh[i] * f, 0.0);
-}
-
+// ----------------------------------------------------------------- FFT --
 // Length-n transforms along one axis, radix 2, decimation in time (input in
 // bit-reversed order).  kSign = -1: forward e^{-2 pi i jk/n}; +1: inverse
-// without the 1/n.  Lines: axis 2 (z, contiguous) takes `tl` consecutive
-// lines; axes 1 and 0 take `tl` lines with consecutive z, so element j of
-// the tile is `tl` contiguous values.
-template <int kSign>
-__global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *data, int n, int logn, int axis, int tl) {
-  extern __shared__ double2 sm[];
-  double2 *buf = sm;
-  double2 *tw = sm + (size_t)tl * n;
-  const int tid = threadIdx.x;
-  for (int k = tid; k < n / 2; k += kFftThreads) {
-    double s, c;
-    sincospi(2.0 * k / n, &s, &c);
-    tw[k] = make_double2(c, kSign * s);
+// without the 1/n.  A workgroup transforms a tile of `tl` lines.  Axis 2
+// (z, contiguous): `tl` consecutive lines; axes 1 and 0: `tl` lines with
+// consecutive z, so element j of the tile is `tl` contiguous values, and
+// the neighbouring tiles (the rest of those cache lines) go to the same
+// XCD (xcd_unit), so that a line fetched for one tile serves the next.
+struct LineTile {
+  int n, logn, axis, tl;
+  uint32_t g, a, z0;
+  __device__ LineTile(int n_, int logn_, int axis_, int tl_, uint32_t g_) : n(n_), logn(logn_), axis(axis_), tl(tl_), g(g_) {
+    const uint32_t per = (uint32_t)(n / tl);
+    a = g / per;
+    z0 = (g % per) * tl;
   }
-  const uint32_t g = blockIdx.x;
-  const uint32_t per = (uint32_t)(n / tl);
-  const uint32_t a = g / per, z0 = (g % per) * tl;
-  const uint64_t nn = (uint64_t)n;
-  auto addr = [&](int t, int j) -> uint64_t {
-    if (axis == 2) return ((uint64_t)g * tl + t) * nn + j;
-    if (axis == 1) return ((uint64_t)a * nn + j) * nn + z0 + t;
-    return ((uint64_t)j * nn + a) * nn + z0 + t;
-  };
-  const int total = tl * n;
-  for (int idx = tid; idx < total; idx += kFftThreads) {
-    int t, j;
+  // tile element idx -> line t, position j along the line
+  __device__ void split(int idx, int &t, int &j) const {
     if (axis == 2) {
       t = idx >> logn;
       j = idx & (n - 1);
@@ -250,18 +416,93 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *data, int n, 
       t = idx % tl;
       j = idx / tl;
     }
-    const int jr = (int)(__brev((uint32_t)j) >> (32 - logn));
-    buf[t * n + jr] = data[addr(t, j)];
   }
-  __syncthreads();
+  __device__ uint64_t addr(int t, int j) const {
+    const uint64_t nn = (uint64_t)n;
+    if (axis == 2) return ((uint64_t)g * tl + t) * nn + j;
+    if (axis == 1) return ((uint64_t)a * nn + j) * nn + z0 + t;
+    return ((uint64_t)j * nn + a) * nn + z0 + t;
+  }
+  // mesh coordinates of element (t, j)
+  __device__ void coords(int t, int j, int &x, int &y, int &z) const {
+    if (axis == 2) {
+      const uint32_t line = g * tl + t;
+      x = (int)(line >> logn);
+      y = (int)(line & (n - 1));
+      z = j;
+    } else if (axis == 1) {
+      x = (int)a;
+      y = j;
+      z = (int)z0 + t;
+    } else {
+      x = j;
+      y = (int)a;
+      z = (int)z0 + t;
+    }
+  }
+};
+
+__device__ inline int brev(int j, int logn) { return (int)(__brev((uint32_t)j) >> (32 - logn)); }
+
+// LDS position of tile element i: one 16-byte pad after every 16 elements,
+// so that the bit-reversed scatter of the loads and the short-stride
+// butterflies of the first stages fall into different banks.
+__host__ __device__ inline int lp(int i) { return i + (i >> 4); }
+// LDS elements of a padded tile of m elements.
+__host__ __device__ inline int lp_size(int m) { return lp(m - 1) + 1; }
+
+// Tables of one mesh, computed once per force call (k_pm_tables) and
+// copied into LDS by each workgroup: forward twiddles e^{-2 pi i k / n} and
+// inverse twiddles e^{+2 pi i k / n}, k < n/2, and per axis index j (signed
+// wave number m) the factor exp(-(2 pi m / L)^2 r_s^2) / sinc(pi m / n)^4:
+// the Gaussian filter exp(-k^2 r_s^2) and the CIC deconvolution 1 / W(k)^2
+// are both products over the three axes.
+struct PmTables {
+  double2 *twf, *twi;
+  double *wax;
+};
+
+__device__ inline double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+__global__ __launch_bounds__(kPmThreads) void k_pm_tables(PmTables Tb, int n, double L, double r_s) {
+  const int k = blockIdx.x * kPmThreads + threadIdx.x;
+  if (k < n / 2) {
+    double sn, cs;
+    sincospi(2.0 * k / n, &sn, &cs);
+    Tb.twf[k] = make_double2(cs, -sn);
+    Tb.twi[k] = make_double2(cs, sn);
+  }
+  if (k < n) {
+    const int m = k < n / 2 ? k : k - n;
+    const double sj = sinc(M_PI * m / n), s2 = sj * sj;
+    const double km = 2.0 * M_PI / L * m;
+    Tb.wax[k] = exp(-(km * r_s) * (km * r_s)) / (s2 * s2);
+  }
+}
+
+template <typename T>
+__device__ inline void copy_to_lds(T *dst, const T *src, int count) {
+  for (int k = threadIdx.x; k < count; k += kFftThreads) dst[k] = src[k];
+}
+
+// The radix-2 stages of `total / n` lines held in LDS (bit-reversed input,
+// natural-order output).  Callers synchronise before and after.
+// kConj: `tw` holds the opposite sign's twiddles (e^{-sign ...}), used
+// conjugated.
+template <int kSign, bool kConj = false>
+__device__ inline void fft_stages(double2 *buf, const double2 *tw, int n, int logn, int total) {
+  // complex products as fused multiply-adds (deterministic, and one
+  // rounding fewer per product)
+#pragma clang fp contract(fast)
+  const int tid = threadIdx.x;
   int s = 1;
   if (logn & 1) {
     // one radix-2 stage (len 2, twiddle 1) when log2 n is odd
     for (int b = tid; b < total / 2; b += kFftThreads) {
       const int i0 = 2 * b;
-      const double2 u = buf[i0], v = buf[i0 + 1];
-      buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-      buf[i0 + 1] = make_double2(u.x - v.x, u.y - v.y);
+      const double2 u = buf[lp(i0)], v = buf[lp(i0 + 1)];
+      buf[lp(i0)] = make_double2(u.x + v.x, u.y + v.y);
+      buf[lp(i0 + 1)] = make_double2(u.x - v.x, u.y - v.y);
     }
     __syncthreads();
     s = 2;
@@ -274,86 +515,245 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *data, int n, 
       const int t = b >> (logn - 2), r = b & (n / 4 - 1);
       const int pos = r & (h - 1), grp = r >> (s - 1);
       const int i0 = t * n + grp * 4 * h + pos;
-      const double2 w1 = tw[pos * step1], w2 = tw[pos * step2];
+      double2 w1 = tw[pos * step1], w2 = tw[pos * step2];
+      if (kConj) {
+        w1.y = -w1.y;
+        w2.y = -w2.y;
+      }
       // the second stage's twiddle for the odd pair is w2 exp(sign i pi/2)
       const double2 w3 = make_double2(-kSign * w2.y, kSign * w2.x);
-      const double2 a = buf[i0], b0 = buf[i0 + h], c = buf[i0 + 2 * h], d0 = buf[i0 + 3 * h];
+      const double2 a = buf[lp(i0)], b0 = buf[lp(i0 + h)], c = buf[lp(i0 + 2 * h)], d0 = buf[lp(i0 + 3 * h)];
       const double2 vb = make_double2(b0.x * w1.x - b0.y * w1.y, b0.x * w1.y + b0.y * w1.x);
       const double2 vd = make_double2(d0.x * w1.x - d0.y * w1.y, d0.x * w1.y + d0.y * w1.x);
       const double2 a1 = make_double2(a.x + vb.x, a.y + vb.y), b1 = make_double2(a.x - vb.x, a.y - vb.y);
       const double2 c1 = make_double2(c.x + vd.x, c.y + vd.y), d1 = make_double2(c.x - vd.x, c.y - vd.y);
       const double2 vc = make_double2(c1.x * w2.x - c1.y * w2.y, c1.x * w2.y + c1.y * w2.x);
       const double2 ve = make_double2(d1.x * w3.x - d1.y * w3.y, d1.x * w3.y + d1.y * w3.x);
-      buf[i0] = make_double2(a1.x + vc.x, a1.y + vc.y);
-      buf[i0 + 2 * h] = make_double2(a1.x - vc.x, a1.y - vc.y);
-      buf[i0 + h] = make_double2(b1.x + ve.x, b1.y + ve.y);
-      buf[i0 + 3 * h] = make_double2(b1.x - ve.x, b1.y - ve.y);
+      buf[lp(i0)] = make_double2(a1.x + vc.x, a1.y + vc.y);
+      buf[lp(i0 + 2 * h)] = make_double2(a1.x - vc.x, a1.y - vc.y);
+      buf[lp(i0 + h)] = make_double2(b1.x + ve.x, b1.y + ve.y);
+      buf[lp(i0 + 3 * h)] = make_double2(b1.x - ve.x, b1.y - ve.y);
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < total; idx += kFftThreads) {
+}
+
+template <int kSign>
+__global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *data, const double2 *twg, int n, int logn, int axis,
+                                                          int tl) {
+  extern __shared__ double2 sm[];
+  double2 *buf = sm;
+  double2 *tw = sm + lp_size(tl * n);
+  copy_to_lds(tw, twg, n / 2);
+  const LineTile T(n, logn, axis, tl, xcd_unit(blockIdx.x, gridDim.x));
+  const int total = tl * n;
+  for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
     int t, j;
-    if (axis == 2) {
-      t = idx >> logn;
-      j = idx & (n - 1);
-    } else {
-      t = idx % tl;
-      j = idx / tl;
-    }
-    data[addr(t, j)] = buf[t * n + j];
+    T.split(idx, t, j);
+    buf[lp(t * n + brev(j, logn))] = data[T.addr(t, j)];
+  }
+  __syncthreads();
+  fft_stages<kSign>(buf, tw, n, logn, total);
+  for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
+    int t, j;
+    T.split(idx, t, j);
+    data[T.addr(t, j)] = buf[lp(t * n + j)];
   }
 }
 
-__device__ inline double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
-
-// Green's function, CIC deconvolution and gradient, per wave vector:
-// B holds rho_k on entry and (a_z + i phi)_k on exit, A gets (a_x + i a_y)_k.
-// The deconvolution 1 / W^2 = prod over axes of sinc(pi m / n)^-4 is
-// tabulated once per workgroup (n <= 1024 entries); n is a power of two,
-// so the cell index splits by shifts.
-__global__ __launch_bounds__(kPmThreads) void k_green(double2 *B, double2 *A, int n, double L, double G,
-                                                      double r_s) {
-  __shared__ double dec[1024];
-  for (int j = threadIdx.x; j < n; j += kPmThreads) {
-    const int m = j < n / 2 ? j : j - n;
-    const double sj = sinc(M_PI * m / n), s2 = sj * sj;
-    dec[j] = 1.0 / (s2 * s2);
+// The forward z pass of the density: each node's fixed-point sum (with the
+// block halos, when given) becomes mass / cell volume, the real part of the
+// input, as it is read.
+__global__ __launch_bounds__(kFftThreads) void k_fft_z_density(const unsigned long long *mesh,
+                                                               const unsigned long long *halo, uint32_t N,
+                                                               const unsigned long long *mmax, double inv_vol,
+                                                               const double2 *twg, double2 *rho, int n, int logn,
+                                                               int tl) {
+  extern __shared__ double2 sm[];
+  double2 *buf = sm;
+  double2 *tw = sm + lp_size(tl * n);
+  copy_to_lds(tw, twg, n / 2);
+  const double f = inv_vol / fixed_scale(mmax, N);
+  const LineTile T(n, logn, 2, tl, xcd_unit(blockIdx.x, gridDim.x));
+  const int total = tl * n;
+  for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
+    int t, j, x, y, z;
+    T.split(idx, t, j);
+    T.coords(t, j, x, y, z);
+    const unsigned long long v = node_sum(mesh, halo, T.addr(t, j), x, y, z, n);
+    buf[lp(t * n + brev(j, logn))] = make_double2((double)v * f, 0.0);
   }
   __syncthreads();
-  const int logn = __builtin_ctz((unsigned)n);
-  const uint64_t cells = (uint64_t)n * n * n, mask = (uint64_t)(n - 1);
+  fft_stages<-1>(buf, tw, n, logn, total);
+  for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
+    int t, j;
+    T.split(idx, t, j);
+    rho[T.addr(t, j)] = buf[lp(t * n + j)];
+  }
+}
+
+// Green's function, Gaussian filter, CIC deconvolution and gradient at wave
+// vector (ix, iy, iz): phi_k = -4 pi G exp(-k^2 r_s^2) / k^2 / W(k)^2 rho_k
+// and a_k = -i k phi_k; returns (a_x + i a_y)_k in *pa and (a_z + i phi)_k
+// in *pb.  wax: the per-axis factors of the filter and the deconvolution.
+__device__ inline void green(double2 rho, int ix, int iy, int iz, int n, double kf, double G, const double *wax,
+                             double2 *pa, double2 *pb) {
+  const int mx = ix < n / 2 ? ix : ix - n, my = iy < n / 2 ? iy : iy - n, mz = iz < n / 2 ? iz : iz - n;
+  const double kx = kf * mx, ky = kf * my, kz = kf * mz;
+  const double k2 = kx * kx + ky * ky + kz * kz;
+  if (k2 == 0.0) {
+    *pa = make_double2(0.0, 0.0);
+    *pb = make_double2(0.0, 0.0);
+    return;
+  }
+  const double g = -4.0 * M_PI * G / k2 * (wax[ix] * wax[iy] * wax[iz]);
+  const double pr = g * rho.x, pi = g * rho.y;  // phi_k
+  // derivative wavenumbers, the Nyquist one dropped
+  const double dx = mx == -n / 2 ? 0.0 : kx, dy = my == -n / 2 ? 0.0 : ky, dz = mz == -n / 2 ? 0.0 : kz;
+  // a_k = -i k phi_k = k (phi_i, -phi_r)
+  const double axr = dx * pi, axi = -dx * pr;
+  const double ayr = dy * pi, ayi = -dy * pr;
+  const double azr = dz * pi, azi = -dz * pr;
+  *pa = make_double2(axr - ayi, axi + ayr);
+  *pb = make_double2(azr - pi, azi + pr);
+}
+
+// The forward x pass, Green's function and the inverse x passes of both
+// output fields in one workgroup: B holds the y-z transformed density on
+// entry; on exit A holds (a_x + i a_y) and B (a_z + i phi), transformed
+// back along x.  The x lines stay in LDS between the steps; the spectrum,
+// in natural order after the forward stages, goes back in bit-reversed
+// order for the inverse stages through registers (each thread holds at
+// most kXgPer tile elements: tl n <= kXgPer kFftThreads, as fft_lines
+// picks for this kernel).
+constexpr int kXgPer = 8;
+__global__ __launch_bounds__(kFftThreads) void k_fft_x_green(double2 *B, double2 *A, PmTables Tb, int n, int logn,
+                                                             int tl, double L, double G) {
+  extern __shared__ double2 sm[];
+  double2 *bb = sm;
+  double2 *ba = sm + lp_size(tl * n);
+  double2 *tw = ba + lp_size(tl * n);
+  double *wax = reinterpret_cast<double *>(tw + n / 2);
+  copy_to_lds(tw, Tb.twf, n / 2);
+  copy_to_lds(wax, Tb.wax, n);
+  const LineTile T(n, logn, 0, tl, xcd_unit(blockIdx.x, gridDim.x));
+  const int total = tl * n;
+  for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
+    int t, j;
+    T.split(idx, t, j);
+    bb[lp(t * n + brev(j, logn))] = B[T.addr(t, j)];
+  }
+  __syncthreads();
+  fft_stages<-1>(bb, tw, n, logn, total);
   const double kf = 2.0 * M_PI / L;
-  for (uint64_t i = blockIdx.x * (uint64_t)kPmThreads + threadIdx.x; i < cells;
-       i += (uint64_t)gridDim.x * kPmThreads) {
-    const int iz = (int)(i & mask), iy = (int)((i >> logn) & mask), ix = (int)(i >> (2 * logn));
-    const int mx = ix < n / 2 ? ix : ix - n, my = iy < n / 2 ? iy : iy - n, mz = iz < n / 2 ? iz : iz - n;
-    const double kx = kf * mx, ky = kf * my, kz = kf * mz;
-    const double k2 = kx * kx + ky * ky + kz * kz;
-    if (k2 == 0.0) {
-      A[i] = make_double2(0.0, 0.0);
-      B[i] = make_double2(0.0, 0.0);
-      continue;
+  {
+    double2 oa[kXgPer], ob[kXgPer];
+    int dst[kXgPer];
+#pragma unroll
+    for (int k = 0; k < kXgPer; ++k) {
+      const int idx = threadIdx.x + k * kFftThreads;
+      dst[k] = -1;
+      if (idx < total) {
+        int t, j, x, y, z;
+        T.split(idx, t, j);
+        T.coords(t, j, x, y, z);
+        green(bb[lp(t * n + j)], x, y, z, n, kf, G, wax, &oa[k], &ob[k]);
+        dst[k] = lp(t * n + brev(j, logn));
+      }
     }
-    const double g = -4.0 * M_PI * G * exp(-k2 * r_s * r_s) / k2 * (dec[ix] * dec[iy] * dec[iz]);
-    const double2 rho = B[i];
-    const double pr = g * rho.x, pi = g * rho.y;  // phi_k
-    // derivative wavenumbers, the Nyquist one dropped
-    const double dx = mx == -n / 2 ? 0.0 : kx, dy = my == -n / 2 ? 0.0 : ky, dz = mz == -n / 2 ? 0.0 : kz;
-    // a_k = -i k phi_k = k (phi_i, -phi_r)
-    const double axr = dx * pi, axi = -dx * pr;
-    const double ayr = dy * pi, ayi = -dy * pr;
-    const double azr = dz * pi, azi = -dz * pr;
-    A[i] = make_double2(axr - ayi, axi + ayr);
-    B[i] = make_double2(azr - pi, azi + pr);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kXgPer; ++k)
+      if (dst[k] >= 0) {
+        ba[dst[k]] = oa[k];
+        bb[dst[k]] = ob[k];
+      }
+  }
+  __syncthreads();
+  fft_stages<1, true>(ba, tw, n, logn, total);
+  fft_stages<1, true>(bb, tw, n, logn, total);
+  for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
+    int t, j;
+    T.split(idx, t, j);
+    const uint64_t k = T.addr(t, j);
+    A[k] = ba[lp(t * n + j)];
+    B[k] = bb[lp(t * n + j)];
+  }
+}
+
+// Write one particle's interpolated mesh force (slot i, caller order).
+__device__ inline void put_out(uint32_t i, double ax, double ay, double az, double ph, double *acc, double *pot,
+                               int accumulate) {
+  if (accumulate) {
+    acc[3ull * i] += ax;
+    acc[3ull * i + 1] += ay;
+    acc[3ull * i + 2] += az;
+    if (pot) pot[i] += ph;
+  } else {
+    acc[3ull * i] = ax;
+    acc[3ull * i + 1] = ay;
+    acc[3ull * i + 2] = az;
+    if (pot) pot[i] = ph;
+  }
+}
+
+// One workgroup per block: the 9^3 tile nodes of both fields staged in LDS
+// once, then the block's first kBlockChunk particles interpolated from
+// them, with the arithmetic of k_interp.
+__global__ __launch_bounds__(kPmThreads) void k_interp_blocks(const double2 *A, const double2 *B, const double4 *part,
+                                                              BlockRef R, const uint32_t *perm, int n, int logn,
+                                                              double inv_d, double norm, double self, double *acc,
+                                                              double *pot, int accumulate) {
+  __shared__ double2 ta[kTile3], tb[kTile3];
+  const uint32_t h = xcd_unit(blockIdx.x, gridDim.x);
+  const uint32_t s = R.bstart[h], e = min(R.bstart[h + 1], s + kBlockChunk);
+  if (s == e) return;
+  int g0[3];
+  block_corner(R, h, logn, g0);
+  const int mask = n - 1;
+  for (int c = threadIdx.x; c < kTile3; c += kPmThreads) {
+    const int tx = c / (kTile * kTile), ty = (c / kTile) % kTile, tz = c % kTile;
+    const uint64_t k = ((uint64_t)((g0[0] + tx) & mask) * n + ((g0[1] + ty) & mask)) * n + ((g0[2] + tz) & mask);
+    ta[c] = A[k];
+    tb[c] = B[k];
+  }
+  __syncthreads();
+  for (uint32_t p = s + threadIdx.x; p < e; p += kPmThreads) {
+    const double4 q = part[p];
+    int r[3];
+    double f[3];
+    tile_cic(q, R, logn, inv_d, g0, r, f);
+    const double wx[2] = {1.0 - f[0], f[0]}, wy[2] = {1.0 - f[1], f[1]}, wz[2] = {1.0 - f[2], f[2]};
+    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int k = ((r[0] + a) * kTile + r[1] + b) * kTile + r[2] + c;
+          const double w = wx[a] * wy[b] * wz[c];
+          const double2 u = ta[k], v = tb[k];
+          ax += w * u.x;
+          ay += w * u.y;
+          az += w * v.x;
+          ph += w * v.y;
+        }
+    ax *= norm;
+    ay *= norm;
+    az *= norm;
+    ph = ph * norm + self * q.w;
+    put_out(perm[p], ax, ay, az, ph, acc, pot, accumulate);
   }
 }
 
 __global__ __launch_bounds__(kPmThreads) void k_interp(const double2 *A, const double2 *B, PartRef P,
                                                        const uint32_t *perm, uint32_t N, int n, double inv_d,
                                                        double norm, double self, double *acc, double *pot,
-                                                       int accumulate) {
-  const uint32_t t = blockIdx.x * kPmThreads + threadIdx.x;
+                                                       int accumulate, BlockRef R) {
+  const uint32_t t = xcd_unit(blockIdx.x, gridDim.x) * kPmThreads + threadIdx.x;
   if (t >= N) return;
+  if (R.bstart != nullptr && !block_extra(R, t)) return;
   const double4 q = P.get(t);
   const uint32_t i = perm ? perm[t] : t;  // output slot: caller index
   int ix, iy, iz;
@@ -384,17 +784,7 @@ __global__ __launch_bounds__(kPmThreads) void k_interp(const double2 *A, const d
   ay *= norm;
   az *= norm;
   ph = ph * norm + self * q.w;
-  if (accumulate) {
-    acc[3ull * i] += ax;
-    acc[3ull * i + 1] += ay;
-    acc[3ull * i + 2] += az;
-    if (pot) pot[i] += ph;
-  } else {
-    acc[3ull * i] = ax;
-    acc[3ull * i + 1] = ay;
-    acc[3ull * i + 2] = az;
-    if (pot) pot[i] = ph;
-  }
+  put_out(i, ax, ay, az, ph, acc, pot, accumulate);
 }
 
 inline uint32_t blocks_for(uint64_t work, uint32_t threads, uint32_t cap) {
@@ -404,58 +794,126 @@ inline uint32_t blocks_for(uint64_t work, uint32_t threads, uint32_t cap) {
 
 }  // namespace
 
-// Lines per workgroup: up to 16, at most n, and a tile plus twiddles within
-// 64 KB of LDS (16 up to n = 128, then 8, 4 and 2 at n = 256, 512 and
-// 1024).  OG_FFT_LINES=k (a power of two, 1..16), read at each launch,
-// caps it, so that the tests run every width the library can pick on small
-// meshes.
-int fft_lines_per_block(int n) {
-  int tl = 16;
-  while (tl > 1 && (tl > n || (size_t)tl * n * sizeof(double2) + (size_t)(n / 2) * sizeof(double2) > 65536)) tl >>= 1;
+// LDS bytes of a workgroup of `tl` lines: the padded tile and the forward
+// or inverse twiddles; fused (the x pass with the Green's function): two
+// padded tiles, the forward twiddles and the per-axis Green factors.
+size_t fft_lds_bytes(int n, int tl, bool fused) {
+  const size_t tile = (size_t)lp_size(tl * n) * sizeof(double2);
+  return fused ? 2 * tile + (size_t)(n / 2) * sizeof(double2) + (size_t)n * sizeof(double)
+               : tile + (size_t)(n / 2) * sizeof(double2);
+}
+
+// LDS a workgroup may hold on gfx950.
+constexpr size_t kLdsMax = 163840;
+
+// Lines per workgroup: 16 up to n = 64, then 8, 4, 4 and 2 at n = 128,
+// 256, 512 and 1024, for every pass (the fastest widths measured on MI355X:
+// narrower tiles leave more workgroups per CU to overlap their loads with
+// the others' LDS stages, wider ones keep more of each strided row in one
+// cache line); at most n, and halved until the workgroup's LDS fits (the
+// fused x pass at n = 512 takes 82 KB).
+// OG_FFT_LINES=k (a power of two, 1..16), read at each launch, replaces
+// the table's width (still at most n and halved until it fits), so that the
+// tests run every width and tile size the library can pick on small meshes.
+int fft_lines(int n, bool fused) {
+  int tl = n <= 64 ? 16 : (n <= 128 ? 8 : (n <= 512 ? 4 : 2));
   const char *e = getenv("OG_FFT_LINES");
-  const int cap = e ? atoi(e) : 0;
-  if (cap >= 1 && cap <= 16 && (cap & (cap - 1)) == 0 && cap < tl) tl = cap;
+  const int want = e ? atoi(e) : 0;
+  if (want >= 1 && want <= 16 && (want & (want - 1)) == 0) tl = want;
+  if (tl > n) tl = n;
+  while (tl > 1 && (fft_lds_bytes(n, tl, fused) > kLdsMax || (fused && tl * n > kXgPer * kFftThreads))) tl >>= 1;
   return tl;
 }
 
-void launch_fft3(double2 *data, int n, int sign, hipStream_t s) {
-  int logn = 0;
-  while ((1 << logn) < n) ++logn;
-  const int tl = fft_lines_per_block(n);
-  const uint32_t blocks = (uint32_t)((uint64_t)n * n / tl);
-  const size_t lds = ((size_t)tl * n + n / 2) * sizeof(double2);
-  for (int axis = 2; axis >= 0; --axis) {
-    if (sign < 0) k_fft_axis<-1><<<blocks, kFftThreads, lds, s>>>(data, n, logn, axis, tl);
-    else k_fft_axis<1><<<blocks, kFftThreads, lds, s>>>(data, n, logn, axis, tl);
-  }
+namespace {
+// Dynamic LDS beyond the default 64 KB is enabled once per process for the
+// FFT kernels.
+void allow_large_lds() {
+  static const bool done = [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_axis<-1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_axis<1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_z_density),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_x_green),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    return true;
+  }();
+  (void)done;
 }
+
+void launch_fft_pass(double2 *data, const PmTables &Tb, int n, int logn, int sign, int axis, hipStream_t s) {
+  const int tl = fft_lines(n, false);
+  const uint32_t blocks = (uint32_t)((uint64_t)n * n / tl);
+  const size_t lds = fft_lds_bytes(n, tl, false);
+  if (sign < 0) k_fft_axis<-1><<<blocks, kFftThreads, lds, s>>>(data, Tb.twf, n, logn, axis, tl);
+  else k_fft_axis<1><<<blocks, kFftThreads, lds, s>>>(data, Tb.twi, n, logn, axis, tl);
+}
+}  // namespace
 
 void launch_pm(const PmArgs &P, hipStream_t s) {
   const uint64_t cells = (uint64_t)P.n * P.n * P.n;
   const double d = P.L / P.n, inv_d = P.n / P.L;
-  unsigned long long *fixed = reinterpret_cast<unsigned long long *>(P.A);  // aliases A until k_green
-  k_fill_u64<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells);
-  k_fill_u64<<<1, kPmThreads, 0, s>>>(P.mmax, 1);
-  // Caller order: direct atomics (neighbouring threads rarely share a node).
-  // Curve order (a tree's particles): LDS tiles per workgroup.  Interpolation
-  // in curve order shares the eight nodes of neighbouring threads in cache.
+  int logn = 0;
+  while ((1 << logn) < P.n) ++logn;
+  // the fixed-point mesh aliases A until the fused x pass writes A
+  unsigned long long *fixed = reinterpret_cast<unsigned long long *>(P.A);
   const PartRef R{P.pos, P.mass, P.part};
+  // Tree order: block workgroups (see k_deposit_blocks); the halo entries
+  // live in the second half of A, which the fixed-point mesh leaves free.
+  const bool blocks = P.part != nullptr && P.keys != nullptr && P.bstart != nullptr;
+  BlockRef BR{nullptr, nullptr, 0, 0, 0.0};
+  const uint32_t nblocks = (uint32_t)(cells / (kBlk * kBlk * kBlk));
+  allow_large_lds();
+  const PmTables Tb{P.tables, P.tables + P.n / 2, reinterpret_cast<double *>(P.tables + P.n)};
+  k_pm_tables<<<blocks_for((uint64_t)P.n, kPmThreads, 64), kPmThreads, 0, s>>>(Tb, P.n, P.L, P.r_s);
+  k_fill_u64<<<1, kPmThreads, 0, s>>>(P.mmax, 1);
   k_mass_max<<<blocks_for(P.N, kPmThreads, 1024), kPmThreads, 0, s>>>(R, P.N, P.mmax);
-  if (P.part)
+  const unsigned long long *halo = nullptr;
+  if (blocks) {
+    BR = BlockRef{P.keys, P.bstart, 3 * (kLevels - (logn - 3)), P.curve, P.tscale};
+    unsigned long long *hb = fixed + cells;
+    k_block_starts<<<blocks_for(nblocks + 1ull, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(BR, P.N, nblocks,
+                                                                                          P.bstart);
+    k_deposit_blocks<<<nblocks, kPmThreads, 0, s>>>(P.part, BR, P.N, P.n, logn, inv_d, P.mmax, fixed, hb);
+    // what blocks of more than kBlockChunk particles left: atomics onto
+    // the stored mesh (the halo stays apart until the density is read)
     k_deposit_tiled<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(R, P.N, P.n, inv_d, P.mmax,
-                                                                                 fixed);
-  else
+                                                                                 fixed, BR);
+    halo = hb;
+  } else {
+    // Caller order: direct atomics (neighbouring threads rarely share a node).
+    k_fill_u64<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells);
     k_deposit<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(R, P.N, P.n, inv_d, P.mmax, fixed);
-  k_density<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(fixed, cells, P.N, P.mmax,
-                                                                       1.0 / (d * d * d), P.B);
-  launch_fft3(P.B, P.n, -1, s);
-  k_green<<<blocks_for(cells, kPmThreads, 8192), kPmThreads, 0, s>>>(P.B, P.A, P.n, P.L, P.G, P.r_s);
-  launch_fft3(P.A, P.n, +1, s);
-  launch_fft3(P.B, P.n, +1, s);
+  }
+  // forward transform: z (reading the density), y, then x fused with the
+  // Green's function and the inverse x passes; then the inverse y and z
+  // passes of both fields
+  {
+    const int tl = fft_lines(P.n, false);
+    const size_t lds = fft_lds_bytes(P.n, tl, false);
+    k_fft_z_density<<<(uint32_t)((uint64_t)P.n * P.n / tl), kFftThreads, lds, s>>>(fixed, halo, P.N, P.mmax,
+                                                                                 1.0 / (d * d * d), Tb.twf, P.B,
+                                                                                 P.n, logn, tl);
+  }
+  launch_fft_pass(P.B, Tb, P.n, logn, -1, 1, s);
+  {
+    const int tl = fft_lines(P.n, true);
+    k_fft_x_green<<<(uint32_t)((uint64_t)P.n * P.n / tl), kFftThreads, fft_lds_bytes(P.n, tl, true), s>>>(
+        P.B, P.A, Tb, P.n, logn, tl, P.L, P.G);
+  }
+  for (double2 *f : {P.A, P.B}) {
+    launch_fft_pass(f, Tb, P.n, logn, +1, 1, s);
+    launch_fft_pass(f, Tb, P.n, logn, +1, 2, s);
+  }
   const double self = P.G / (std::sqrt(M_PI) * P.r_s);
+  if (blocks)
+    k_interp_blocks<<<nblocks, kPmThreads, 0, s>>>(P.A, P.B, P.part, BR, P.perm, P.n, logn, inv_d,
+                                                   1.0 / (double)cells, self, P.acc, P.pot, P.accumulate);
   k_interp<<<blocks_for(P.N, kPmThreads, 1u << 30), kPmThreads, 0, s>>>(
       P.A, P.B, R, P.part ? P.perm : nullptr, P.N, P.n, inv_d, 1.0 / (double)cells, self, P.acc, P.pot,
-      P.accumulate);
+      P.accumulate, BR);
 }
 
 }  // namespace og

@@ -16,6 +16,8 @@ struct og_pm {
   void *mem = nullptr;
   double2 *A = nullptr, *B = nullptr;
   unsigned long long *mmax = nullptr;
+  double2 *tables = nullptr;
+  uint32_t *bstart = nullptr;
 };
 
 namespace {
@@ -24,7 +26,8 @@ bool pow2_in_range(int32_t n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0
 
 size_t pm_bytes(int32_t n) {
   const size_t cells = (size_t)n * n * n;
-  return 2 * cells * sizeof(double2) + 256;
+  return 2 * cells * sizeof(double2) + 256 + ((pm_table_bytes(n) + 255) & ~(size_t)255) +
+         ((pm_block_words(n) * 4 + 255) & ~(size_t)255);
 }
 
 }  // namespace
@@ -63,6 +66,9 @@ int og_pm_create(int32_t n_grid, double box, double G, double r_s, void *stream,
   p->A = static_cast<double2 *>(p->mem);
   p->B = p->A + cells;
   p->mmax = reinterpret_cast<unsigned long long *>(p->B + cells);
+  p->tables = reinterpret_cast<double2 *>(reinterpret_cast<char *>(p->mmax) + 256);
+  p->bstart = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(p->tables) +
+                                           ((pm_table_bytes(n_grid) + 255) & ~(size_t)255));
   *out = p;
   return OG_OK;
 }
@@ -85,6 +91,7 @@ int og_pm_force(og_pm *pm, const double *pos, const double *mass, int64_t N, dou
   P.A = pm->A;
   P.B = pm->B;
   P.mmax = pm->mmax;
+  P.tables = pm->tables;
   P.acc = acc;
   P.pot = pot;
   P.accumulate = accumulate ? 1 : 0;
@@ -104,6 +111,10 @@ int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, i
   PmArgs P{};
   P.part = F.A.part64;
   P.perm = F.A.perm;
+  P.keys = F.A.keys_a;
+  P.curve = b.curve;
+  P.tscale = b.scale;
+  P.bstart = pm->bstart;
   P.N = F.N;
   P.n = pm->n;
   P.L = pm->L;
@@ -112,6 +123,7 @@ int og_pm_force_tree(og_pm *pm, const og_tree *tree, double *acc, double *pot, i
   P.A = pm->A;
   P.B = pm->B;
   P.mmax = pm->mmax;
+  P.tables = pm->tables;
   P.acc = acc;
   P.pot = pot;
   P.accumulate = accumulate ? 1 : 0;

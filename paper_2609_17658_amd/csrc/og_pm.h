@@ -20,10 +20,25 @@ struct PmArgs {
   double *acc;         // [N][3]
   double *pot;         // [N] or null
   int accumulate;      // 1: add to acc/pot
+  // With part (a periodic tree whose root cube is the mesh box): the tree's
+  // sorted keys and curve, its level-21 cell scale 2^21 / L, and room for
+  // (n/8)^3 + 1 block starts (pm_block_words).
+  const uint64_t *keys;
+  int curve;
+  double tscale;
+  uint32_t *bstart;
+  double2 *tables;     // 3n/2 double2: FFT twiddles and the deconvolution (pm_table_bytes)
 };
 
+// Bytes of the per-size tables: n/2 forward and n/2 inverse twiddles, n
+// deconvolution factors.
+inline size_t pm_table_bytes(int n) { return (size_t)n * 16 + (size_t)n * 8; }
+
+// Words of block starts the tree-order path needs for an n^3 mesh.
+inline size_t pm_block_words(int n) { return (size_t)(n / 8) * (n / 8) * (n / 8) + 1; }
+
 void launch_pm(const PmArgs &P, hipStream_t s);
-void launch_fft3(double2 *data, int n, int sign, hipStream_t s);
-int fft_lines_per_block(int n);
+int fft_lines(int n, bool fused);
+size_t fft_lds_bytes(int n, int tl, bool fused);
 
 }  // namespace og

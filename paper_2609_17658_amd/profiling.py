@@ -7,6 +7,8 @@
       builds the tree `reps` times (every build kernel runs `reps` times);
   python paper_2609_17658_amd/profiling.py pm --n-grid 256 --reps 3
       the particle-mesh force of the same mixture on a 256^3 mesh;
+  python paper_2609_17658_amd/profiling.py pmtree --n-grid 256 --reps 3
+      the same from a built tree (og_pm_force_tree, curve order);
   python paper_2609_17658_amd/profiling.py copy --mib 1024 --reps 3
       device-to-device copy of a buffer of known size, the reference for
       scaling FETCH_SIZE / WRITE_SIZE readings to bytes.
@@ -74,6 +76,29 @@ def _pm(n_grid: int, reps: int, workload: str):
     print("pm %d^3 x%d on %s: done" % (n_grid, reps, workload), flush=True)
 
 
+def _pm_tree(n_grid: int, reps: int, workload: str):
+    import torch
+
+    from paper_2609_17658_amd import og, synth
+
+    w = synth.WORKLOADS[workload]()
+    dev = torch.device("cuda:0")
+    tp = torch.as_tensor(w.pos, device=dev)
+    tm = torch.as_tensor(w.mass, device=dev)
+    prm = w.params.as_dict()
+    stream = torch.cuda.current_stream()
+    t = og.Tree(tp, tm, w.box, prm, stream=stream)
+    mesh = og.PM(n_grid, w.box, prm["G"], prm["r_s"], stream=stream)
+    acc = torch.empty((tp.shape[0], 3), dtype=torch.float64, device=dev)
+    pot = torch.empty(tp.shape[0], dtype=torch.float64, device=dev)
+    for _ in range(reps):
+        mesh.force_tree(t, acc, pot)
+    torch.cuda.synchronize()
+    mesh.close()
+    t.close()
+    print("pm from the tree %d^3 x%d on %s: done" % (n_grid, reps, workload), flush=True)
+
+
 def _copy(mib: int, reps: int):
     import torch
 
@@ -100,6 +125,10 @@ def main(argv=None):
     m.add_argument("--n-grid", type=int, default=256)
     m.add_argument("--reps", type=int, default=3)
     m.add_argument("--workload", default="mixture2m")
+    mt = sub.add_parser("pmtree")
+    mt.add_argument("--n-grid", type=int, default=256)
+    mt.add_argument("--reps", type=int, default=3)
+    mt.add_argument("--workload", default="mixture2m")
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=1024)
     c.add_argument("--reps", type=int, default=3)
@@ -110,6 +139,8 @@ def main(argv=None):
         _build(a.reps, a.workload)
     elif a.cmd == "pm":
         _pm(a.n_grid, a.reps, a.workload)
+    elif a.cmd == "pmtree":
+        _pm_tree(a.n_grid, a.reps, a.workload)
     else:
         _copy(a.mib, a.reps)
     return 0

@@ -63,13 +63,13 @@ def test_pm_matches_oracle(og_mod, n_grid, N, box, G):
     m.close()
 
 
-def test_pm_256_eight_line_tiles_match_oracle(og_mod):
-    """n_grid = 256: the FFT passes take 8 lines per workgroup (the smaller
-    meshes take 16)."""
+def test_pm_256_four_line_tiles_match_oracle(og_mod):
+    """n_grid = 256: the FFT passes take 4 lines per workgroup (the smaller
+    meshes take 16 and 8)."""
     from oracle import pm as opm
     pos, mass = _particles(120000, 256)
     r_s = 1.25 / 256
-    _note("pm n_grid=256 N=120000 (8-line FFT tiles)")
+    _note("pm n_grid=256 N=120000 (4-line FFT tiles)")
     a_o, p_o = opm.long_range(pos, mass, 1.0, 256, 1.0, r_s)
     m = og_mod.PM(256, 1.0, 1.0, r_s, stream=torch.cuda.current_stream())
     acc, pot = m.force(_dev(pos), _dev(mass))
@@ -83,26 +83,33 @@ def test_pm_256_eight_line_tiles_match_oracle(og_mod):
 
 @pytest.mark.parametrize("n_grid", [64, 128])
 def test_pm_every_fft_tile_width(og_mod, n_grid, monkeypatch):
-    """OG_FFT_LINES caps the lines per FFT workgroup, so the 8-, 4-, 2- and
-    1-line tiles (the larger meshes' widths, and one below) run on small
-    meshes: each is bitwise the 16-line result (the same butterflies per
-    line) and within 1e-10 of the oracle."""
+    """OG_FFT_LINES sets the lines per FFT workgroup, so every width the
+    larger meshes take runs on small meshes, and at 128^3 the 16-line
+    tiles of the fused x pass are the larger meshes' tile shape (2048
+    elements, 8 per thread, more than 64 KB of LDS): each result is
+    bitwise the default one (the same butterflies per line) and within
+    1e-10 of the oracle, from caller arrays and from a tree."""
     from oracle import pm as opm
     pos, mass = _particles(30000, n_grid + 1)
     r_s = 1.25 / n_grid
     a_o, p_o = opm.long_range(pos, mass, 1.0, n_grid, 1.0, r_s)
-    m = og_mod.PM(n_grid, 1.0, 1.0, r_s, stream=torch.cuda.current_stream())
+    stream = torch.cuda.current_stream()
+    m = og_mod.PM(n_grid, 1.0, 1.0, r_s, stream=stream)
     ref_a, ref_p = m.force(_dev(pos), _dev(mass))
-    for lines in (8, 4, 2, 1):
+    tree = og_mod.Tree(_dev(pos), _dev(mass), 1.0, synth.scale_free_params(30000).as_dict(), stream=stream)
+    for lines in (16, 8, 4, 2, 1):
         _note("pm n_grid=%d with %d-line FFT tiles" % (n_grid, lines))
         monkeypatch.setenv("OG_FFT_LINES", str(lines))
         acc, pot = m.force(_dev(pos), _dev(mass))
+        at, pt = m.force_tree(tree)
         torch.cuda.synchronize()
         monkeypatch.delenv("OG_FFT_LINES")
         assert torch.equal(acc, ref_a) and torch.equal(pot, ref_p), lines
+        assert torch.equal(at, ref_a) and torch.equal(pt, ref_p), lines
         a, p = acc.cpu().numpy(), pot.cpu().numpy()
         assert np.abs(a - a_o).max() <= 1e-10 * np.abs(a_o).max()
         assert np.abs(p - p_o).max() <= 1e-10 * np.abs(p_o).max()
+    tree.close()
     m.close()
 
 
@@ -178,3 +185,40 @@ def test_pm_from_tree_equals_caller_order(og_mod):
         m2.force_tree(tree)
     for x in (tree, t2, m, m2):
         x.close()
+
+
+@pytest.mark.parametrize("n_grid,curve,clump", [(8, "morton", 0), (32, "hilbert", 0), (64, "morton", 20000),
+                                                (64, "hilbert", 20000), (128, "morton", 40000)])
+def test_pm_from_tree_blocks(og_mod, n_grid, curve, clump):
+    """The tree-order path (block workgroups of 8^3 cells, halos, and the
+    per-particle kernels for blocks of more than 2048 particles) gives the
+    caller-order result to the bit and the oracle's within the bar, with
+    particles at 0 and just below the box side, on one block (n = 8, whose
+    halo wraps onto itself) and on Hilbert trees (block corners from the
+    inverse curve)."""
+    from oracle import pm as opm
+    rng = np.random.default_rng(n_grid + clump)
+    pos, mass = _particles(30000, n_grid)
+    if clump:
+        pos = np.concatenate([pos, (0.61 + 0.004 * rng.standard_normal((clump, 3))) % 1.0])
+        mass = np.concatenate([mass, np.full(clump, 0.5 / clump)])
+    pos[:7, 0] = np.nextafter(1.0, 0.0)
+    pos[7:14, 1] = 0.0
+    pos[14:21, 2] = np.nextafter(1.0, 0.0)
+    n = pos.shape[0]
+    _note("pm from tree n_grid=%d curve=%s N=%d" % (n_grid, curve, n))
+    prm = dict(synth.scale_free_params(n).as_dict(), curve=curve)
+    stream = torch.cuda.current_stream()
+    tree = og_mod.Tree(_dev(pos), _dev(mass), 1.0, prm, stream=stream)
+    r_s = 1.25 / n_grid
+    m = og_mod.PM(n_grid, 1.0, 1.0, r_s, stream=stream)
+    a1, p1 = m.force(_dev(pos), _dev(mass))
+    a2, p2 = m.force_tree(tree)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+    a_o, p_o = opm.long_range(pos, mass, 1.0, n_grid, 1.0, r_s)
+    a, p = a2.cpu().numpy(), p2.cpu().numpy()
+    assert np.abs(a - a_o).max() <= 1e-10 * np.abs(a_o).max()
+    assert np.abs(p - p_o).max() <= 1e-10 * np.abs(p_o).max()
+    tree.close()
+    m.close()
