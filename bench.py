@@ -957,16 +957,16 @@ def leg_pm(og, torch, synth, args):
     # the device's streaming rate: a 1 GiB device-to-device copy (read + write)
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
+    for _ in range(100):  # about 50 ms of copies first: the clocks settle
         b.copy_(a)
     torch.cuda.synchronize()
     ec = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ec[0].record()
-    for _ in range(10):
+    for _ in range(20):
         b.copy_(a)
     ec[1].record()
     torch.cuda.synchronize()
-    copy_gbps = 2 * (1 << 30) / (ec[0].elapsed_time(ec[1]) / 10 * 1e-3) / 1e9
+    copy_gbps = 2 * (1 << 30) / (ec[0].elapsed_time(ec[1]) / 20 * 1e-3) / 1e9
     del a, b
     torch.cuda.empty_cache()
     out["copy_1GiB_GBps"] = copy_gbps
