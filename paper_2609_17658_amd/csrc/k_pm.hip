@@ -681,6 +681,267 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_green(double2 *B, double2
   }
 }
 
+// ------------------------------------------ register-staged FFT (n >= 64) --
+// The same radix-2 decimation-in-time transform, with its first three and
+// last three stages done in registers.  A thread owns a column i < n/8 of a
+// line: the elements i + k n/8, k = 0..7.  Loaded in that order, they are
+// the eight bit-reversed-order inputs of the LDS group 8 brev(i) .. + 7, so
+// the thread runs stages 1-3 on them (twiddles 1, +-i and (+-1 +- i)/sqrt 2)
+// and writes the group contiguously; stages 4 .. log2 n - 3 run in LDS as
+// before; and the last three stages combine exactly the elements i + k n/8
+// again, which the thread reads, transforms and stores in natural order.
+// No bit-reversed scatter, one LDS sweep at n = 256.  LDS holds one pad
+// element per 8 (lq), which spreads the groups' contiguous writes over the
+// banks.
+__host__ __device__ inline int lq(int p) { return p + (p >> 3); }
+__host__ __device__ inline int lq_size(int m) { return lq(m - 1) + 1; }
+
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cmul(double2 a, double2 w) {
+#pragma clang fp contract(fast)
+  return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+// times e^{sign i pi / 2} = sign i
+template <int kSign>
+__device__ inline double2 mul_si(double2 a) { return make_double2(-kSign * a.y, kSign * a.x); }
+
+// Stages 1-3 on one group of eight, in LDS order (u[r] = input brev3(r)).
+template <int kSign>
+__device__ inline void dft8_first(double2 u[8]) {
+#pragma clang fp contract(fast)
+  constexpr double c = 0.70710678118654752440;  // cos pi/4
+#pragma unroll
+  for (int p = 0; p < 8; p += 2) {
+    const double2 a = u[p], b = u[p + 1];
+    u[p] = cadd(a, b);
+    u[p + 1] = csub(a, b);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; q += 4) {
+    double2 a = u[q], b = u[q + 2];
+    u[q] = cadd(a, b);
+    u[q + 2] = csub(a, b);
+    a = u[q + 1];
+    b = mul_si<kSign>(u[q + 3]);
+    u[q + 1] = cadd(a, b);
+    u[q + 3] = csub(a, b);
+  }
+  const double2 x5 = u[5], x7 = u[7];
+  const double2 b[4] = {u[4], make_double2(c * (x5.x - kSign * x5.y), c * (x5.y + kSign * x5.x)), mul_si<kSign>(u[6]),
+                        make_double2(c * (-x7.x - kSign * x7.y), c * (kSign * x7.x - x7.y))};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double2 a = u[r];
+    u[r] = cadd(a, b[r]);
+    u[r + 4] = csub(a, b[r]);
+  }
+}
+
+// The last three stages on the elements i + k n/8 (natural order in e[k]
+// on exit).  tw: e^{sign 2 pi i k / n} (kConj: the opposite sign's table,
+// conjugated).
+template <bool kConj>
+__device__ inline double2 twid(const double2 *tw, int k) {
+  double2 w = tw[k];
+  if (kConj) w.y = -w.y;
+  return w;
+}
+template <bool kConj>
+__device__ inline void dft8_last(double2 e[8], int i, int n, const double2 *tw) {
+  const double2 w = twid<kConj>(tw, 4 * i);
+#pragma unroll
+  for (int p = 0; p < 8; p += 2) {
+    const double2 a = e[p], b = cmul(e[p + 1], w);
+    e[p] = cadd(a, b);
+    e[p + 1] = csub(a, b);
+  }
+  const double2 w0 = twid<kConj>(tw, 2 * i), w1 = twid<kConj>(tw, 2 * i + n / 4);
+#pragma unroll
+  for (int q = 0; q < 8; q += 4) {
+    double2 a = e[q], b = cmul(e[q + 2], w0);
+    e[q] = cadd(a, b);
+    e[q + 2] = csub(a, b);
+    a = e[q + 1];
+    b = cmul(e[q + 3], w1);
+    e[q + 1] = cadd(a, b);
+    e[q + 3] = csub(a, b);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double2 a = e[k], b = cmul(e[k + 4], twid<kConj>(tw, i + k * (n / 8)));
+    e[k] = cadd(a, b);
+    e[k + 4] = csub(a, b);
+  }
+}
+
+// Stages 4 .. log2 n - 3 of `total / n` lines in LDS (lq layout): one
+// radix-2 stage first when their number is odd, then two stages per sweep.
+// Callers synchronise before; every sweep ends with a barrier.
+template <int kSign, bool kConj>
+__device__ inline void fft_middle(double2 *buf, const double2 *tw, int n, int logn, int total) {
+#pragma clang fp contract(fast)
+  const int tid = threadIdx.x;
+  const int s_end = logn - 3;  // last middle stage
+  int s = 4;
+  if ((s_end - s + 1) & 1) {
+    const int h = 1 << (s - 1), step = n >> s;
+    for (int b = tid; b < total / 2; b += kFftThreads) {
+      const int t = b >> (logn - 1), r = b & (n / 2 - 1);
+      const int pos = r & (h - 1), grp = r >> (s - 1);
+      const int i0 = t * n + grp * 2 * h + pos;
+      const double2 a = buf[lq(i0)], v = cmul(buf[lq(i0 + h)], twid<kConj>(tw, pos * step));
+      buf[lq(i0)] = cadd(a, v);
+      buf[lq(i0 + h)] = csub(a, v);
+    }
+    __syncthreads();
+    ++s;
+  }
+  for (; s < s_end; s += 2) {
+    const int h = 1 << (s - 1), step1 = n >> s, step2 = n >> (s + 1);
+    for (int b = tid; b < total / 4; b += kFftThreads) {
+      const int t = b >> (logn - 2), r = b & (n / 4 - 1);
+      const int pos = r & (h - 1), grp = r >> (s - 1);
+      const int i0 = t * n + grp * 4 * h + pos;
+      const double2 w1 = twid<kConj>(tw, pos * step1), w2 = twid<kConj>(tw, pos * step2);
+      const double2 w3 = mul_si<kSign>(w2);
+      const double2 a = buf[lq(i0)], b0 = buf[lq(i0 + h)], c = buf[lq(i0 + 2 * h)], d0 = buf[lq(i0 + 3 * h)];
+      const double2 vb = cmul(b0, w1), vd = cmul(d0, w1);
+      const double2 a1 = cadd(a, vb), b1 = csub(a, vb), c1 = cadd(c, vd), d1 = csub(c, vd);
+      const double2 vc = cmul(c1, w2), ve = cmul(d1, w3);
+      buf[lq(i0)] = cadd(a1, vc);
+      buf[lq(i0 + 2 * h)] = csub(a1, vc);
+      buf[lq(i0 + h)] = cadd(b1, ve);
+      buf[lq(i0 + 3 * h)] = csub(b1, ve);
+    }
+    __syncthreads();
+  }
+}
+
+// Column c of a tile: line t and column i < n/8 (consecutive c run along the
+// contiguous direction of the global rows).
+__device__ inline void tile_col(const LineTile &T, int c, int &t, int &i) {
+  if (T.axis == 2) {
+    t = c >> (T.logn - 3);
+    i = c & (T.n / 8 - 1);
+  } else {
+    t = c & (T.tl - 1);
+    i = c / T.tl;
+  }
+}
+
+__device__ inline int brev3(int r) { return ((r & 1) << 2) | (r & 2) | ((r >> 2) & 1); }
+
+template <int kSign>
+__global__ __launch_bounds__(kFftThreads) void k_fft8_axis(double2 *data, const double2 *twg, int n, int logn,
+                                                           int axis, int tl) {
+  extern __shared__ double2 sm[];
+  double2 *buf = sm;
+  double2 *tw = sm + lq_size(tl * n);
+  copy_to_lds(tw, twg, n / 2);
+  const LineTile T(n, logn, axis, tl, xcd_unit(blockIdx.x, gridDim.x));
+  const int cols = tl * n / 8, n8 = n / 8;
+  for (int c = threadIdx.x; c < cols; c += kFftThreads) {
+    int t, i;
+    tile_col(T, c, t, i);
+    double2 u[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[brev3(k)] = data[T.addr(t, i + k * n8)];
+    dft8_first<kSign>(u);
+    const int base = t * n + 8 * brev(i, logn - 3);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[lq(base + r)] = u[r];
+  }
+  __syncthreads();
+  fft_middle<kSign, false>(buf, tw, n, logn, tl * n);
+  for (int c = threadIdx.x; c < cols; c += kFftThreads) {
+    int t, i;
+    tile_col(T, c, t, i);
+    double2 e[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e[k] = buf[lq(t * n + i + k * n8)];
+    dft8_last<false>(e, i, n, tw);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) data[T.addr(t, i + k * n8)] = e[k];
+  }
+}
+
+// The fused x pass (see k_fft_x_green) with register stages: a thread's
+// column leaves the forward transform in natural order, i + k n/8, which
+// is exactly the column the inverse transforms' first stages need, so the
+// Green's function and those stages run in registers.  At most one column
+// per thread (tl n <= 8 kFftThreads, as fft_lines picks).
+__global__ __launch_bounds__(kFftThreads) void k_fft8_x_green(double2 *B, double2 *A, PmTables Tb, int n, int logn,
+                                                              int tl, double L, double G) {
+  extern __shared__ double2 sm[];
+  double2 *bb = sm;
+  double2 *ba = sm + lq_size(tl * n);
+  double2 *tw = ba + lq_size(tl * n);
+  double *wax = reinterpret_cast<double *>(tw + n / 2);
+  copy_to_lds(tw, Tb.twf, n / 2);
+  copy_to_lds(wax, Tb.wax, n);
+  const LineTile T(n, logn, 0, tl, xcd_unit(blockIdx.x, gridDim.x));
+  const int cols = tl * n / 8, n8 = n / 8;
+  const int c = threadIdx.x;
+  int t = 0, i = 0;
+  if (c < cols) {
+    tile_col(T, c, t, i);
+    double2 u[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[brev3(k)] = B[T.addr(t, i + k * n8)];
+    dft8_first<-1>(u);
+    const int base = t * n + 8 * brev(i, logn - 3);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) bb[lq(base + r)] = u[r];
+  }
+  __syncthreads();
+  fft_middle<-1, false>(bb, tw, n, logn, tl * n);
+  double2 ua[8], ub[8];
+  if (c < cols) {
+    double2 e[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e[k] = bb[lq(t * n + i + k * n8)];
+    dft8_last<false>(e, i, n, tw);
+    const double kf = 2.0 * M_PI / L;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int x, y, z;
+      T.coords(t, i + k * n8, x, y, z);
+      green(e[k], x, y, z, n, kf, G, wax, &ua[brev3(k)], &ub[brev3(k)]);
+    }
+    dft8_first<1>(ua);
+    dft8_first<1>(ub);
+  }
+  __syncthreads();  // every read of the forward tile is done
+  if (c < cols) {
+    const int base = t * n + 8 * brev(i, logn - 3);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      ba[lq(base + r)] = ua[r];
+      bb[lq(base + r)] = ub[r];
+    }
+  }
+  __syncthreads();
+  fft_middle<1, true>(ba, tw, n, logn, tl * n);
+  fft_middle<1, true>(bb, tw, n, logn, tl * n);
+  if (c < cols) {
+    double2 ea[8], eb[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      ea[k] = ba[lq(t * n + i + k * n8)];
+      eb[k] = bb[lq(t * n + i + k * n8)];
+    }
+    dft8_last<true>(ea, i, n, tw);
+    dft8_last<true>(eb, i, n, tw);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t a = T.addr(t, i + k * n8);
+      A[a] = ea[k];
+      B[a] = eb[k];
+    }
+  }
+}
+
 // Write one particle's interpolated mesh force (slot i, caller order).
 __device__ inline void put_out(uint32_t i, double ax, double ay, double az, double ph, double *acc, double *pot,
                                int accumulate) {
@@ -794,11 +1055,14 @@ inline uint32_t blocks_for(uint64_t work, uint32_t threads, uint32_t cap) {
 
 }  // namespace
 
+// Meshes from 64 points per axis take the register-staged passes.
+inline bool fft_regs(int n) { return n >= 64; }
+
 // LDS bytes of a workgroup of `tl` lines: the padded tile and the forward
 // or inverse twiddles; fused (the x pass with the Green's function): two
 // padded tiles, the forward twiddles and the per-axis Green factors.
 size_t fft_lds_bytes(int n, int tl, bool fused) {
-  const size_t tile = (size_t)lp_size(tl * n) * sizeof(double2);
+  const size_t tile = (size_t)(fft_regs(n) ? lq_size(tl * n) : lp_size(tl * n)) * sizeof(double2);
   return fused ? 2 * tile + (size_t)(n / 2) * sizeof(double2) + (size_t)n * sizeof(double)
                : tile + (size_t)(n / 2) * sizeof(double2);
 }
@@ -806,22 +1070,37 @@ size_t fft_lds_bytes(int n, int tl, bool fused) {
 // LDS a workgroup may hold on gfx950.
 constexpr size_t kLdsMax = 163840;
 
-// Lines per workgroup: 16 up to n = 64, then 8, 4, 4 and 2 at n = 128,
-// 256, 512 and 1024, for every pass (the fastest widths measured on MI355X:
-// narrower tiles leave more workgroups per CU to overlap their loads with
-// the others' LDS stages, wider ones keep more of each strided row in one
-// cache line); at most n, and halved until the workgroup's LDS fits (the
-// fused x pass at n = 512 takes 82 KB).
-// OG_FFT_LINES=k (a power of two, 1..16), read at each launch, replaces
-// the table's width (still at most n and halved until it fits), so that the
-// tests run every width and tile size the library can pick on small meshes.
+// Lines per workgroup.  Register-staged passes: 2048 elements per tile (one
+// column of eight per thread; at most 16 lines); smaller meshes: 16 lines.
+// At most n, and halved until the workgroup's LDS fits (and, for the fused
+// x pass, its tile in eight elements per thread).  OG_FFT_LINES=k (a power
+// of two, 1..16), read at each launch, replaces the width (still at most n
+// and halved until it fits), so that the tests run every width and tile
+// size the library can pick on small meshes.
 int fft_lines(int n, bool fused) {
-  int tl = n <= 64 ? 16 : (n <= 128 ? 8 : (n <= 512 ? 4 : 2));
+  int tl = fft_regs(n) ? (2048 / n > 16 ? 16 : 2048 / n) : 16;
   const char *e = getenv("OG_FFT_LINES");
   const int want = e ? atoi(e) : 0;
   if (want >= 1 && want <= 16 && (want & (want - 1)) == 0) tl = want;
   if (tl > n) tl = n;
   while (tl > 1 && (fft_lds_bytes(n, tl, fused) > kLdsMax || (fused && tl * n > kXgPer * kFftThreads))) tl >>= 1;
+  return tl;
+}
+
+// The forward z pass that reads the fixed-point sums (k_fft_z_density, all
+// in LDS, lp layout; its loads gather the block halos, and it runs fastest
+// with the narrower tiles that leave more workgroups per CU): 16, 8, 4, 4
+// and 2 lines at n <= 64, 128, 256, 512 and 1024, or OG_FFT_LINES.
+size_t fft_z_lds_bytes(int n, int tl) {
+  return (size_t)lp_size(tl * n) * sizeof(double2) + (size_t)(n / 2) * sizeof(double2);
+}
+int fft_z_lines(int n) {
+  int tl = n <= 64 ? 16 : (n <= 128 ? 8 : (n <= 512 ? 4 : 2));
+  const char *e = getenv("OG_FFT_LINES");
+  const int want = e ? atoi(e) : 0;
+  if (want >= 1 && want <= 16 && (want & (want - 1)) == 0) tl = want;
+  if (tl > n) tl = n;
+  while (tl > 1 && fft_z_lds_bytes(n, tl) > kLdsMax) tl >>= 1;
   return tl;
 }
 
@@ -838,6 +1117,12 @@ void allow_large_lds() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_x_green),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft8_axis<-1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft8_axis<1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft8_x_green),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
     return true;
   }();
   (void)done;
@@ -847,8 +1132,14 @@ void launch_fft_pass(double2 *data, const PmTables &Tb, int n, int logn, int sig
   const int tl = fft_lines(n, false);
   const uint32_t blocks = (uint32_t)((uint64_t)n * n / tl);
   const size_t lds = fft_lds_bytes(n, tl, false);
-  if (sign < 0) k_fft_axis<-1><<<blocks, kFftThreads, lds, s>>>(data, Tb.twf, n, logn, axis, tl);
-  else k_fft_axis<1><<<blocks, kFftThreads, lds, s>>>(data, Tb.twi, n, logn, axis, tl);
+  if (fft_regs(n)) {
+    if (sign < 0) k_fft8_axis<-1><<<blocks, kFftThreads, lds, s>>>(data, Tb.twf, n, logn, axis, tl);
+    else k_fft8_axis<1><<<blocks, kFftThreads, lds, s>>>(data, Tb.twi, n, logn, axis, tl);
+  } else if (sign < 0) {
+    k_fft_axis<-1><<<blocks, kFftThreads, lds, s>>>(data, Tb.twf, n, logn, axis, tl);
+  } else {
+    k_fft_axis<1><<<blocks, kFftThreads, lds, s>>>(data, Tb.twi, n, logn, axis, tl);
+  }
 }
 }  // namespace
 
@@ -891,17 +1182,17 @@ void launch_pm(const PmArgs &P, hipStream_t s) {
   // Green's function and the inverse x passes; then the inverse y and z
   // passes of both fields
   {
-    const int tl = fft_lines(P.n, false);
-    const size_t lds = fft_lds_bytes(P.n, tl, false);
-    k_fft_z_density<<<(uint32_t)((uint64_t)P.n * P.n / tl), kFftThreads, lds, s>>>(fixed, halo, P.N, P.mmax,
-                                                                                 1.0 / (d * d * d), Tb.twf, P.B,
-                                                                                 P.n, logn, tl);
+    const int tl = fft_z_lines(P.n);
+    k_fft_z_density<<<(uint32_t)((uint64_t)P.n * P.n / tl), kFftThreads, fft_z_lds_bytes(P.n, tl), s>>>(
+        fixed, halo, P.N, P.mmax, 1.0 / (d * d * d), Tb.twf, P.B, P.n, logn, tl);
   }
   launch_fft_pass(P.B, Tb, P.n, logn, -1, 1, s);
   {
     const int tl = fft_lines(P.n, true);
-    k_fft_x_green<<<(uint32_t)((uint64_t)P.n * P.n / tl), kFftThreads, fft_lds_bytes(P.n, tl, true), s>>>(
-        P.B, P.A, Tb, P.n, logn, tl, P.L, P.G);
+    const uint32_t blocks = (uint32_t)((uint64_t)P.n * P.n / tl);
+    const size_t lds = fft_lds_bytes(P.n, tl, true);
+    if (fft_regs(P.n)) k_fft8_x_green<<<blocks, kFftThreads, lds, s>>>(P.B, P.A, Tb, P.n, logn, tl, P.L, P.G);
+    else k_fft_x_green<<<blocks, kFftThreads, lds, s>>>(P.B, P.A, Tb, P.n, logn, tl, P.L, P.G);
   }
   for (double2 *f : {P.A, P.B}) {
     launch_fft_pass(f, Tb, P.n, logn, +1, 1, s);
