@@ -869,28 +869,29 @@ __global__ __launch_bounds__(kFftThreads) void k_fft8_axis(double2 *data, const 
 // The fused x pass (see k_fft_x_green) with register stages: a thread's
 // column leaves the forward transform in natural order, i + k n/8, which
 // is exactly the column the inverse transforms' first stages need, so the
-// Green's function and those stages run in registers.  At most one column
-// per thread (tl n <= 8 kFftThreads, as fft_lines picks).
+// Green's function and those stages run in registers.  One LDS tile serves
+// the forward transform and then each output field in turn (the other
+// field waits in registers).  At most one column per thread (tl n <= 8
+// kFftThreads, as fft_lines picks).
 __global__ __launch_bounds__(kFftThreads) void k_fft8_x_green(double2 *B, double2 *A, PmTables Tb, int n, int logn,
                                                               int tl, double L, double G) {
   extern __shared__ double2 sm[];
   double2 *bb = sm;
-  double2 *ba = sm + lq_size(tl * n);
-  double2 *tw = ba + lq_size(tl * n);
+  double2 *tw = sm + lq_size(tl * n);
   double *wax = reinterpret_cast<double *>(tw + n / 2);
   copy_to_lds(tw, Tb.twf, n / 2);
   copy_to_lds(wax, Tb.wax, n);
   const LineTile T(n, logn, 0, tl, xcd_unit(blockIdx.x, gridDim.x));
   const int cols = tl * n / 8, n8 = n / 8;
   const int c = threadIdx.x;
-  int t = 0, i = 0;
+  int t = 0, i = 0, base = 0;
   if (c < cols) {
     tile_col(T, c, t, i);
+    base = t * n + 8 * brev(i, logn - 3);
     double2 u[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) u[brev3(k)] = B[T.addr(t, i + k * n8)];
     dft8_first<-1>(u);
-    const int base = t * n + 8 * brev(i, logn - 3);
 #pragma unroll
     for (int r = 0; r < 8; ++r) bb[lq(base + r)] = u[r];
   }
@@ -912,32 +913,24 @@ __global__ __launch_bounds__(kFftThreads) void k_fft8_x_green(double2 *B, double
     dft8_first<1>(ua);
     dft8_first<1>(ub);
   }
-  __syncthreads();  // every read of the forward tile is done
-  if (c < cols) {
-    const int base = t * n + 8 * brev(i, logn - 3);
+  // each output field in turn through the tile
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      ba[lq(base + r)] = ua[r];
-      bb[lq(base + r)] = ub[r];
+  for (int f = 0; f < 2; ++f) {
+    __syncthreads();  // every read of the tile is done
+    if (c < cols) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) bb[lq(base + r)] = f == 0 ? ua[r] : ub[r];
     }
-  }
-  __syncthreads();
-  fft_middle<1, true>(ba, tw, n, logn, tl * n);
-  fft_middle<1, true>(bb, tw, n, logn, tl * n);
-  if (c < cols) {
-    double2 ea[8], eb[8];
+    __syncthreads();
+    fft_middle<1, true>(bb, tw, n, logn, tl * n);
+    if (c < cols) {
+      double2 e[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      ea[k] = ba[lq(t * n + i + k * n8)];
-      eb[k] = bb[lq(t * n + i + k * n8)];
-    }
-    dft8_last<true>(ea, i, n, tw);
-    dft8_last<true>(eb, i, n, tw);
+      for (int k = 0; k < 8; ++k) e[k] = bb[lq(t * n + i + k * n8)];
+      dft8_last<true>(e, i, n, tw);
+      double2 *out = f == 0 ? A : B;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const uint64_t a = T.addr(t, i + k * n8);
-      A[a] = ea[k];
-      B[a] = eb[k];
+      for (int k = 0; k < 8; ++k) out[T.addr(t, i + k * n8)] = e[k];
     }
   }
 }
@@ -1059,11 +1052,14 @@ inline uint32_t blocks_for(uint64_t work, uint32_t threads, uint32_t cap) {
 inline bool fft_regs(int n) { return n >= 64; }
 
 // LDS bytes of a workgroup of `tl` lines: the padded tile and the forward
-// or inverse twiddles; fused (the x pass with the Green's function): two
-// padded tiles, the forward twiddles and the per-axis Green factors.
+// or inverse twiddles; fused (the x pass with the Green's function): its
+// padded tile (two for the small meshes' kernel), the forward twiddles and
+// the per-axis Green factors.
 size_t fft_lds_bytes(int n, int tl, bool fused) {
   const size_t tile = (size_t)(fft_regs(n) ? lq_size(tl * n) : lp_size(tl * n)) * sizeof(double2);
-  return fused ? 2 * tile + (size_t)(n / 2) * sizeof(double2) + (size_t)n * sizeof(double)
+  // the register-staged fused pass keeps one tile
+  const size_t tiles = fused && !fft_regs(n) ? 2 * tile : tile;
+  return fused ? tiles + (size_t)(n / 2) * sizeof(double2) + (size_t)n * sizeof(double)
                : tile + (size_t)(n / 2) * sizeof(double2);
 }
 
