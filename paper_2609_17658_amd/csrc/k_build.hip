@@ -23,7 +23,16 @@ constexpr int kWaves = kThreads / 64;
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63; }
 
+// Barrier that orders LDS only: the global stores still in flight are not
+// waited for (use where the workgroup exchanges data through LDS alone).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Block-wide exclusive scan of one value per thread (256 threads).
+template <bool kLdsOnly = false>
 __device__ inline uint32_t block_exscan(uint32_t v, uint32_t *tmp4, uint32_t *total) {
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   uint32_t x = v;
@@ -33,7 +42,8 @@ __device__ inline uint32_t block_exscan(uint32_t v, uint32_t *tmp4, uint32_t *to
     if (lane >= (uint32_t)off) x += t;
   }
   if (lane == 63) tmp4[w] = x;
-  __syncthreads();
+  if (kLdsOnly) lds_barrier();
+  else __syncthreads();
   uint32_t base = 0, tot = 0;
 #pragma unroll
   for (int i = 0; i < kWaves; ++i) {
@@ -41,7 +51,8 @@ __device__ inline uint32_t block_exscan(uint32_t v, uint32_t *tmp4, uint32_t *to
     if (i < (int)w) base += t;
     tot += t;
   }
-  __syncthreads();
+  if (kLdsOnly) lds_barrier();
+  else __syncthreads();
   *total = tot;
   return base + x - v;
 }
@@ -385,11 +396,6 @@ __global__ __launch_bounds__(kThreads) void k_gather(const BoxDev *boxes, int B,
 // ------------------------------------------------------------ topology --
 // lcp(p): levels shared by sorted keys p-1 and p inside one box; -1 at a
 // box's first particle and past its last one.
-__device__ inline int lcp_at(const uint64_t *skeys, uint32_t q, uint32_t b0, uint32_t b1) {
-  if (q <= b0 || q >= b1) return -1;
-  return shared_levels(skeys[q - 1], skeys[q]);
-}
-
 // depth(p): the level of the leaf holding p = the smallest level whose node
 // around p holds <= leaf_max particles (21 at most).  The node at level L
 // around p holds 1 + #{neighbours q within leaf_max places with
@@ -516,37 +522,23 @@ __global__ __launch_bounds__(kThreads) void k_emit(const BoxDev *boxes, int B, u
   }
 }
 
-// Parent links and child counts; counts the internal nodes of each level.
+// Parent links: every child of an internal node points at it.
 __global__ __launch_bounds__(kThreads) void k_links(const Topo *topo, const uint32_t *skip,
                                                     const uint32_t *scalars, uint32_t node_cap,
-                                                    uint32_t *parent, uint32_t *nchild,
-                                                    uint32_t *lvl_cnt) {
-  __shared__ uint32_t h[kLevels + 1];
-  if (threadIdx.x <= kLevels) h[threadIdx.x] = 0;
-  __syncthreads();
+                                                    uint32_t *parent) {
   const uint32_t tot = min(scalars[3], node_cap);
   for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
     const Topo t = topo[r];
-    uint32_t nc = 0;
-    if (!(t.corner & kLeafBit)) {
-      const uint32_t end = min(t.a, tot);
-      for (uint32_t c = r + 1; c < end;) {
-        parent[c] = r;
-        ++nc;
-        const uint32_t nx = skip[c];
-        if (nx <= c) break;  // never taken for a well-formed tree
-        c = nx;
-      }
-      atomicAdd(&h[t.b >> kCountBits], 1u);
+    if (t.corner & kLeafBit) continue;
+    const uint32_t end = min(t.a, tot);
+    for (uint32_t c = r + 1; c < end;) {
+      parent[c] = r;
+      const uint32_t nx = skip[c];
+      if (nx <= c) break;  // never taken for a well-formed tree
+      c = nx;
     }
-    nchild[r] = nc;
   }
-  __syncthreads();
-  if (threadIdx.x <= kLevels && h[threadIdx.x]) atomicAdd(&lvl_cnt[threadIdx.x], h[threadIdx.x]);
 }
-
-// Particles staged in LDS per round of the leaf-moment kernel (32 KB).
-constexpr int kLeafStage = 1024;
 
 // Cube centre of a node in FP64: lo + (corner + 2^(20-level)) L 2^-21.
 __device__ inline void node_centre(const BoxDev &bx, uint64_t corner, int level, double c[3]) {
@@ -557,135 +549,450 @@ __device__ inline void node_centre(const BoxDev &bx, uint64_t corner, int level,
   c[2] = bx.lo[2] + ((double)(uint32_t)((corner >> 42) & 0x1fffffull) + half) * h;
 }
 
-// Bottom-up moments, level by level (paper, "Tree construction": a
-// bottom-up pass computes each node's mass and centre of mass).  Leaves sum
-// their particles relative to the cube centre (and write each particle's
-// FP32 offset from that centre); internal nodes are bucketed by level and
-// each level, deepest first, sums its children in child order.  Every
-// node is summed once in a fixed order, so the result is deterministic, and
-// levels are separated by kernel boundaries only.
-// With per-particle softening lengths (seps non-null) every node also gets
-// the largest and smallest length of its particles (semax, semin).
-__global__ __launch_bounds__(kThreads) void k_leaves_and_buckets(
-    const BoxDev *boxes, int B, const Topo *topo, const double4 *part64, float4 *part32, Mom64 *mom64,
-    Mom32 *mom32, const uint32_t *scalars, uint32_t node_cap, const uint32_t *lvl_cnt, uint32_t *lvl_fill,
-    uint32_t *lvl_nodes, const double *seps, double *semax, double *semin) {
-  __shared__ uint32_t base[kLevels + 1], lcount[kLevels + 1], lres[kLevels + 1];
+// Walk record (see WNode) and FP64 cube centre and side of node r.
+__device__ inline void walk_records(const BoxDev &bx, const Topo &t, const Mom32 &m, uint32_t r, WNode *wn,
+                                    double4 *cen64) {
+  const int lev = (int)(t.b >> kCountBits);
+  const int hc = 1 << (kLevels - lev);
+  const bool leaf = (t.corner & kLeafBit) != 0;
+  const float side = ldexpf(bx.Lf, -lev);
+  WNode w;
+  w.c[0] = 0x4B000000 | (2 * (int)(t.corner & 0x1fffffull) + hc);
+  w.c[1] = 0x4B000000 | (2 * (int)((t.corner >> 21) & 0x1fffffull) + hc);
+  w.c[2] = 0x4B000000 | (2 * (int)((t.corner >> 42) & 0x1fffffull) + hc);
+  w.side2 = side * side;
+  w.o[0] = m.ox;
+  w.o[1] = m.oy;
+  w.o[2] = m.oz;
+  w.m = m.m;
+  w.reach = bx.rcutf + 0.5f * side;
+  w.near = 0.6f * side;
+  const uint32_t count = t.b & kCountMask;
+  const bool wrap = bx.periodic && bx.rcutf + side >= 0.5f * bx.Lf;
+  w.a = leaf ? leaf_tag_bits(t.a, min(count, 8u), wrap) : t.a;
+  w.cf = count | (leaf && count > 8u ? kWBig : 0u) | (leaf ? kWLeaf : 0u) | (wrap ? kWWrap : 0u);
+  wn[r] = w;
+  // the FP64 walks' cube centre and side, in the expressions they used to
+  // evaluate at every visit (so the values are the same to the bit)
+  const double h = bx.L * 0x1p-21, half = ldexp(1.0, 20 - lev);
+  cen64[r] = make_double4(bx.lo[0] + ((double)(uint32_t)(t.corner & 0x1fffffull) + half) * h,
+                          bx.lo[1] + ((double)(uint32_t)((t.corner >> 21) & 0x1fffffull) + half) * h,
+                          bx.lo[2] + ((double)(uint32_t)((t.corner >> 42) & 0x1fffffull) + half) * h,
+                          ldexp(bx.L, -lev));
+}
+
+// Mass and centre of mass of node r from its mass M and first moments s
+// about the cube centre c; FP64 and FP32 forms, then the walk records.
+__device__ inline Mom64 store_node(const BoxDev &bx, const Topo &t, uint32_t r, const double c[3], double M,
+                                   double s0, double s1, double s2, Mom64 *mom64, Mom32 *mom32, WNode *wn,
+                                   double4 *cen64) {
+  const Mom64 m{c[0] + s0 / M, c[1] + s1 / M, c[2] + s2 / M, M};
+  mom64[r] = m;
+  const Mom32 m32{(float)(m.cx - c[0]), (float)(m.cy - c[1]), (float)(m.cz - c[2]), (float)M};
+  mom32[r] = m32;
+  walk_records(bx, t, m32, r, wn, cen64);
+  return m;
+}
+
+// One particle q of a leaf with cube centre c: its mass and first moments
+// added, its FP32 offset from the centre written.
+__device__ inline void leaf_add(const double4 q, const double c[3], double &M, double &s0, double &s1, double &s2,
+                                float4 &out) {
+  const double dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
+  M += q.w;
+  s0 += q.w * dx;
+  s1 += q.w * dy;
+  s2 += q.w * dz;
+  out = make_float4((float)dx, (float)dy, (float)dz, (float)q.w);
+}
+
+// Sums of an internal node over its children's moments, in child order.
+struct ChildSums {
+  double c[3];
+  double M = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, hi = 0.0, lo = INFINITY;
+  __device__ void add(const Mom64 &m) {
+    M += m.m;
+    q0 += m.m * (m.cx - c[0]);
+    q1 += m.m * (m.cy - c[1]);
+    q2 += m.m * (m.cz - c[2]);
+  }
+  __device__ void add_lengths(double h, double l) {
+    hi = h > hi ? h : hi;
+    lo = l < lo ? l : lo;
+  }
+};
+
+// Node after the last node of r's subtree (pre-order).
+__device__ inline uint32_t subtree_end(const Topo &t, uint32_t r, uint32_t tot) {
+  return (t.corner & kLeafBit) ? r + 1 : max(r + 1, min(t.a, tot));
+}
+
+__device__ inline const BoxDev &node_box(const BoxDev *boxes, int B, const uint32_t *first, uint32_t r) {
+  return boxes[B == 1 ? 0 : box_of(boxes, B, first[r])];
+}
+
+// Bottom-up moments (paper, "Tree construction": a bottom-up pass computes
+// each node's mass and centre of mass).  Leaves sum their particles about
+// the cube centre (and write each particle's FP32 offset from it); an
+// internal node sums its children in child order.  Every node is summed
+// once, in that fixed order, so the result is deterministic.  Every node
+// also gets its walk records (WNode, FP64 centre), and with per-particle
+// softening lengths (seps non-null) the largest and smallest length of its
+// particles (semax, semin).
+// The order of work, in three launches:
+//  - k_moments_leaves sums every leaf and classifies every node: a node
+//    whose subtree holds more than kSegNodes nodes is a top node; one with
+//    at most kSegNodes whose parent is a top node (or which has no parent)
+//    roots a segment, a contiguous pre-order range of nodes.  Top nodes
+//    are listed, each with eight empty child slots.
+//  - k_moments_segments: a workgroup takes the segments whose roots lie in
+//    its chunk of kSegChunk node indices and sums their internal nodes
+//    level by level, deepest first, with the moments in LDS; each child of
+//    a top node in the chunk takes its octant slot in its parent's entry.
+//  - k_moments_top: one workgroup sums the top nodes level by level.
+constexpr uint32_t kSegChunk = kThreads;               // one chunk node per thread
+constexpr uint32_t kSegRange = kSegChunk + kSegNodes;  // nodes a chunk's segments can span
+constexpr uint32_t kSegPer = kSegRange / kThreads;     // range positions per thread
+static_assert(kSegRange % kThreads == 0 && kSegRange < 0xffffu, "segment range in whole rounds, 16-bit");
+constexpr int kLeafStage = 1024;                       // leaf particles staged per round (32 KB)
+constexpr uint32_t kNone = 0xffffffffu;
+constexpr uint32_t kTopRef = 0x80000000u;              // in a child slot: a top node's index in the top list
+constexpr uint32_t kClsRoot = 1u;                      // node class: roots a segment
+constexpr uint32_t kClsTop = 0x80000000u;              // node class: top node (| its index in the top list)
+
+// Octant of a node's cube in its parent (the cell parity at its own level).
+__device__ inline uint32_t octant(const Topo &t) {
+  const int sh = kLevels - (int)(t.b >> kCountBits);
+  return (uint32_t)((t.corner >> sh) & 1u) | (uint32_t)((t.corner >> (21 + sh)) & 1u) << 1 |
+         (uint32_t)((t.corner >> (42 + sh)) & 1u) << 2;
+}
+
+__global__ __launch_bounds__(kThreads) void k_moments_leaves(const BoxDev *boxes, int B, const Topo *topo,
+                                                             const uint32_t *parent, const double4 *part64,
+                                                             float4 *part32, Mom64 *mom64, Mom32 *mom32,
+                                                             WNode *wn, double4 *cen64, uint32_t *scalars,
+                                                             uint32_t node_cap, TopArrays T, const double *seps,
+                                                             double *semax, double *semin) {
   // the round's leaf particles, loaded coalesced (a leaf's thread would
   // otherwise read its particles with a stride of a leaf between lanes)
   __shared__ double4 stage[kLeafStage];
-  __shared__ uint32_t prange[2];
-  if (threadIdx.x <= kLevels) {
-    uint32_t o = 0;
-    for (int l = 0; l < (int)threadIdx.x; ++l) o += lvl_cnt[l];
-    base[threadIdx.x] = o;
-  }
+  __shared__ uint32_t prange[2], s_ntop, s_tlev, s_tbase;
   const uint32_t tot = min(scalars[3], node_cap);
-  const uint32_t stride = gridDim.x * kThreads;
-  // round-based so that each block reserves bucket slots once per round
-  for (uint32_t r0 = blockIdx.x * kThreads; r0 < tot; r0 += stride) {
+  for (uint32_t r0 = blockIdx.x * kThreads; r0 < tot; r0 += gridDim.x * kThreads) {
     const uint32_t r = r0 + threadIdx.x;
-    if (threadIdx.x <= kLevels) lcount[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
       prange[0] = 0xffffffffu;
       prange[1] = 0u;
+      s_ntop = 0;
+      s_tlev = 0;
     }
-    __syncthreads();
+    lds_barrier();
     Topo t{};
-    const bool is_leaf = r < tot && ((t = topo[r]).corner & kLeafBit) != 0;
-    if (is_leaf) {
-      atomicMin(&prange[0], t.a);
-      atomicMax(&prange[1], t.a + (t.b & kCountMask));
+    uint32_t top_slot = kNone;
+    const bool in = r < tot;
+    if (in) {
+      t = topo[r];
+      const uint32_t p = parent[r];
+      const bool has_p = p < tot;
+      const bool ptop = has_p && subtree_end(topo[p], p, tot) - p > kSegNodes;
+      if (subtree_end(t, r, tot) - r > kSegNodes) {
+        top_slot = atomicAdd(&s_ntop, 1u);
+        atomicMax(&s_tlev, t.b >> kCountBits);
+      } else {
+        T.id[r] = !has_p || ptop ? kClsRoot : 0u;
+      }
+      if (t.corner & kLeafBit) {
+        atomicMin(&prange[0], t.a);
+        atomicMax(&prange[1], t.a + (t.b & kCountMask));
+      }
     }
-    __syncthreads();
+    lds_barrier();
+    if (threadIdx.x == 0) {  // one reservation per workgroup and round in the top lists
+      if (s_ntop) {
+        s_tbase = atomicAdd(&T.cnt[0], s_ntop);
+        atomicMax(&T.cnt[2], s_tlev);
+      }
+    }
     const uint32_t pa = prange[0], pn = prange[1] > pa ? prange[1] - pa : 0u;
     const bool staged = pn <= (uint32_t)kLeafStage;
     if (staged)
       for (uint32_t i = threadIdx.x; i < pn; i += kThreads) stage[i] = part64[pa + i];
-    __syncthreads();
-    int lvl = -1;
-    uint32_t slot = 0;
-    if (r < tot) {
-      if (is_leaf) {
-        const uint32_t f = t.a, cnt = t.b & kCountMask;
-        const BoxDev &bx = boxes[box_of(boxes, B, f)];
-        double c[3];
-        node_centre(bx, t.corner, (int)(t.b >> kCountBits), c);
-        double M = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (uint32_t j = f; j < f + cnt; ++j) {
-          const double4 q = staged ? stage[j - pa] : part64[j];
-          const double dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
-          M += q.w;
-          s0 += q.w * dx;
-          s1 += q.w * dy;
-          s2 += q.w * dz;
-          part32[j] = make_float4((float)dx, (float)dy, (float)dz, (float)q.w);
-        }
-        const double com[3] = {c[0] + s0 / M, c[1] + s1 / M, c[2] + s2 / M};
-        mom64[r] = Mom64{com[0], com[1], com[2], M};
-        mom32[r] = Mom32{(float)(com[0] - c[0]), (float)(com[1] - c[1]), (float)(com[2] - c[2]), (float)M};
-        if (seps) {
-          double hi = seps[f], lo = hi;
-          for (uint32_t j = f + 1; j < f + cnt; ++j) {
-            hi = seps[j] > hi ? seps[j] : hi;
-            lo = seps[j] < lo ? seps[j] : lo;
-          }
-          semax[r] = hi;
-          semin[r] = lo;
-        }
+    lds_barrier();
+    if (top_slot != kNone) {
+      const uint32_t k = s_tbase + top_slot;
+      if (k < T.cap) {
+        T.list[k] = make_uint4(r, t.b >> kCountBits, (uint32_t)t.corner, (uint32_t)(t.corner >> 32));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) T.slot[8 * k + q] = ~0ull;
+        T.id[r] = kClsTop | k;
       } else {
-        lvl = (int)(t.b >> kCountBits);
-        slot = atomicAdd(&lcount[lvl], 1u);
+        T.id[r] = 0u;
+        atomicOr(&scalars[0], kStatusNodes);
       }
     }
-    __syncthreads();
-    if (threadIdx.x <= kLevels && lcount[threadIdx.x])
-      lres[threadIdx.x] = atomicAdd(&lvl_fill[threadIdx.x], lcount[threadIdx.x]);
-    __syncthreads();
-    if (lvl >= 0) lvl_nodes[base[lvl] + lres[lvl] + slot] = r;
-    __syncthreads();
+    if (in && (t.corner & kLeafBit)) {
+      const uint32_t f = t.a, cnt = t.b & kCountMask;
+      const BoxDev &bx = boxes[B == 1 ? 0 : box_of(boxes, B, f)];
+      double c[3];
+      node_centre(bx, t.corner, (int)(t.b >> kCountBits), c);
+      double M = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      // (two loops: a select between an LDS and a global pointer is not
+      // formed, which this compiler mishandles)
+      if (staged) {
+        for (uint32_t j = f; j < f + cnt; ++j) leaf_add(stage[j - pa], c, M, s0, s1, s2, part32[j]);
+      } else {
+        for (uint32_t j = f; j < f + cnt; ++j) leaf_add(part64[j], c, M, s0, s1, s2, part32[j]);
+      }
+      store_node(bx, t, r, c, M, s0, s1, s2, mom64, mom32, wn, cen64);
+      if (seps) {
+        double hi = seps[f], lo = hi;
+        for (uint32_t j = f + 1; j < f + cnt; ++j) {
+          hi = seps[j] > hi ? seps[j] : hi;
+          lo = seps[j] < lo ? seps[j] : lo;
+        }
+        semax[r] = hi;
+        semin[r] = lo;
+      }
+    }
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_moments_level(const BoxDev *boxes, int B, int level,
-                                                            const Topo *topo, const uint32_t *first,
-                                                            const uint32_t *skip, const uint32_t *lvl_cnt,
-                                                            const uint32_t *lvl_nodes, const uint32_t *scalars,
-                                                            uint32_t node_cap, Mom64 *mom64, Mom32 *mom32,
-                                                            double *semax, double *semin) {
-  uint32_t o = 0;
-  for (int l = 0; l < level; ++l) o += lvl_cnt[l];
-  const uint32_t cnt = lvl_cnt[level];
+__global__ __launch_bounds__(kThreads) void k_moments_segments(const BoxDev *boxes, int B, const Topo *topo,
+                                                               const uint32_t *first, const uint32_t *parent,
+                                                               const uint32_t *cls, Mom64 *mom64, Mom32 *mom32,
+                                                               WNode *wn, double4 *cen64, const uint32_t *scalars,
+                                                               uint32_t node_cap, TopArrays T, double *semax,
+                                                               double *semin) {
+  __shared__ Mom64 smom[kSegRange];
+  __shared__ uint16_t send[kSegRange];  // per position: the position after its subtree
+  __shared__ int32_t mark[kSegRange];   // +1 at segment roots, -1 at their ends; then prefix sums
+  __shared__ uint32_t tmp4[kWaves], s_end, s_lo, s_hi;
   const uint32_t tot = min(scalars[3], node_cap);
-  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < cnt; i += gridDim.x * kThreads) {
-    const uint32_t par = lvl_nodes[o + i];
-    const Topo tp = topo[par];
-    const BoxDev &bx = boxes[box_of(boxes, B, first[par])];
-    double cp[3];
-    node_centre(bx, tp.corner, level, cp);
-    double Mp = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
-    double hi = 0.0, lo = INFINITY;
-    const uint32_t pend = min(tp.a, tot);
-    for (uint32_t ch = par + 1; ch < pend;) {
-      const Mom64 m = mom64[ch];
-      Mp += m.m;
-      q0 += m.m * (m.cx - cp[0]);
-      q1 += m.m * (m.cy - cp[1]);
-      q2 += m.m * (m.cz - cp[2]);
-      if (semax) {
-        hi = semax[ch] > hi ? semax[ch] : hi;
-        lo = semin[ch] < lo ? semin[ch] : lo;
-      }
-      const uint32_t nx = skip[ch];
-      if (nx <= ch) break;  // never taken for a well-formed tree
-      ch = nx;
+  for (uint32_t base = blockIdx.x * kSegChunk; base < tot; base += gridDim.x * kSegChunk) {
+    lds_barrier();  // the previous chunk is done with the shared arrays
+    for (uint32_t i = threadIdx.x; i < kSegRange; i += kThreads) mark[i] = 0;
+    if (threadIdx.x == 0) {
+      s_end = base;
+      s_lo = kLevels + 1;
+      s_hi = 0;
     }
-    const double cm[3] = {cp[0] + q0 / Mp, cp[1] + q1 / Mp, cp[2] + q2 / Mp};
-    mom64[par] = Mom64{cm[0], cm[1], cm[2], Mp};
-    mom32[par] = Mom32{(float)(cm[0] - cp[0]), (float)(cm[1] - cp[1]), (float)(cm[2] - cp[2]), (float)Mp};
-    if (semax) {
-      semax[par] = hi;
-      semin[par] = lo;
+    lds_barrier();
+    // range position i = threadIdx.x + k kThreads is node base + i
+    Topo t[kSegPer];
+    bool mine[kSegPer];
+    const uint32_t x = base + threadIdx.x;
+    uint32_t xcls = 0;
+    if (x < tot) {
+      t[0] = topo[x];
+      xcls = cls[x];
+      if (xcls == kClsRoot) {
+        const uint32_t e = subtree_end(t[0], x, tot);  // e - base < kSegRange (at most kSegNodes nodes)
+        atomicAdd(&mark[threadIdx.x], 1);
+        atomicSub(&mark[e - base], 1);
+        atomicMax(&s_end, e);
+        atomicMin(&s_lo, t[0].b >> kCountBits);
+      }
+    }
+    lds_barrier();
+    // a segment root or top node with a parent: the parent is a top node;
+    // the child takes its slot there as (node << 32 | ref), ref its top-list
+    // index with kTopRef or, for a segment root, the node
+    if (x < tot && xcls != 0u) {
+      const uint32_t p = parent[x];
+      if (p < tot) {
+        const uint32_t pc = cls[p];
+        if ((pc & kClsTop) && (pc & ~kClsTop) < T.cap) {
+          const uint32_t ref = (xcls & kClsTop) ? kTopRef | (xcls & ~kClsTop) : x;
+          T.slot[8 * (pc & ~kClsTop) + octant(t[0])] = (uint64_t)x << 32 | ref;
+        }
+      }
+    }
+    const uint32_t rlen = s_end - base;  // this chunk's segments lie in [base, s_end)
+    if (rlen == 0) continue;
+    {  // inclusive prefix sums of the marks: 1 inside a segment, 0 elsewhere
+      int32_t v[kSegPer];
+      uint32_t run = 0, total;
+#pragma unroll
+      for (uint32_t k = 0; k < kSegPer; ++k) {
+        v[k] = mark[threadIdx.x * kSegPer + k];
+        run += (uint32_t)v[k];
+      }
+      int32_t acc = (int32_t)block_exscan<true>(run, tmp4, &total);
+#pragma unroll
+      for (uint32_t k = 0; k < kSegPer; ++k) {
+        acc += v[k];
+        mark[threadIdx.x * kSegPer + k] = acc;
+      }
+    }
+    lds_barrier();
+    // the leaves' moments and every node's subtree end into LDS
+#pragma unroll
+    for (uint32_t k = 0; k < kSegPer; ++k) {
+      const uint32_t i = threadIdx.x + k * kThreads;
+      mine[k] = i < rlen && mark[i] > 0;
+      if (!mine[k]) continue;
+      if (k > 0) t[k] = topo[base + i];
+      send[i] = (uint16_t)(min(subtree_end(t[k], base + i, tot), base + rlen) - base);
+      if (t[k].corner & kLeafBit) smom[i] = mom64[base + i];
+      else atomicMax(&s_hi, t[k].b >> kCountBits);
+    }
+    lds_barrier();  // slots, leaf moments and s_hi complete
+    // internal nodes, deepest level first
+    for (int L = (int)s_hi; L >= (int)s_lo; --L) {
+      if (semax) __syncthreads();  // children's lengths written (global memory)
+      else if (L != (int)s_hi) lds_barrier();
+      // positions of this level as a bit mask; one copy of the body (the
+      // position's topology picked by selects, not by indexing)
+      uint32_t todo = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < kSegPer; ++k)
+        if (mine[k] && !(t[k].corner & kLeafBit) && (int)(t[k].b >> kCountBits) == L) todo |= 1u << k;
+      while (todo) {
+        const uint32_t k = __builtin_ctz(todo);
+        todo &= todo - 1;
+        Topo tk = t[0];
+#pragma unroll
+        for (uint32_t q = 1; q < kSegPer; ++q)
+          if (k == q) tk = t[q];
+        const uint32_t i = threadIdx.x + k * kThreads, r = base + i;
+        const BoxDev &bx = node_box(boxes, B, first, r);
+        ChildSums cs;
+        node_centre(bx, tk.corner, L, cs.c);
+        // children in child order: the first follows r, each next one
+        // follows the previous one's subtree
+        const uint32_t pend = send[i];
+        for (uint32_t c = i + 1; c < pend;) {
+          cs.add(smom[c]);
+          if (semax) cs.add_lengths(semax[base + c], semin[base + c]);
+          const uint32_t nx = send[c];
+          if (nx <= c) break;  // never taken for a well-formed tree
+          c = nx;
+        }
+        smom[i] = store_node(bx, tk, r, cs.c, cs.M, cs.q0, cs.q1, cs.q2, mom64, mom32, wn, cen64);
+        if (semax) {
+          semax[r] = cs.hi;
+          semin[r] = cs.lo;
+        }
+      }
+    }
+  }
+}
+
+// The top nodes (subtrees of more than kSegNodes nodes), summed by one
+// workgroup after the segments, level by level, deepest first.  A top
+// node's slots hold its children (top nodes and segment roots) by octant
+// as (node << 32 | ref); sorted, they give child order.  With at most
+// kTopThreads top nodes every thread holds one, its slots and its segment
+// -root children's moments in registers, and the top nodes' moments stay
+// in LDS, so the levels cost no memory round trip; larger sets read slots
+// and moments from global memory at every level.  FP32 moments and walk
+// records follow.
+constexpr int kTopThreads = 1024;
+
+// A node's slots in child order (empty slots, all ones, sort last).
+__device__ inline void sort_slots(uint64_t sl[8]) {
+#pragma unroll
+  for (int q = 1; q < 8; ++q)
+#pragma unroll
+    for (int j = q; j > 0; --j)
+      if (sl[j] < sl[j - 1]) {
+        const uint64_t u = sl[j];
+        sl[j] = sl[j - 1];
+        sl[j - 1] = u;
+      }
+}
+
+__device__ inline Mom64 top_mom(const ChildSums &cs) {
+  return Mom64{cs.c[0] + cs.q0 / cs.M, cs.c[1] + cs.q1 / cs.M, cs.c[2] + cs.q2 / cs.M, cs.M};
+}
+
+__device__ inline void top_records(const BoxDev &bx, const Topo &t, uint32_t r, const double c[3],
+                                   const Mom64 &m, Mom32 *mom32, WNode *wn, double4 *cen64) {
+  const Mom32 m32{(float)(m.cx - c[0]), (float)(m.cy - c[1]), (float)(m.cz - c[2]), (float)m.m};
+  mom32[r] = m32;
+  walk_records(bx, t, m32, r, wn, cen64);
+}
+
+__global__ __launch_bounds__(kTopThreads) void k_moments_top(const BoxDev *boxes, int B, const Topo *topo,
+                                                             const uint32_t *first, Mom64 *mom64, Mom32 *mom32,
+                                                             WNode *wn, double4 *cen64, TopArrays T,
+                                                             double *semax, double *semin) {
+  __shared__ Mom64 smt[kTopThreads];
+  const uint32_t ntop = min(T.cnt[0], T.cap);
+  if (ntop == 0) return;
+  const int hi = (int)min(T.cnt[2], (uint32_t)kLevels);
+  if (ntop <= (uint32_t)kTopThreads && semax == nullptr) {
+    // one top node per thread, everything it needs in registers
+    const uint32_t i = threadIdx.x;
+    const bool own = i < ntop;
+    int lev = -1;
+    uint32_t r = 0;
+    uint64_t sl[8];
+    Mom64 m[8];
+    ChildSums cs;
+    Topo t{};
+    if (own) {
+      const uint4 e = T.list[i];
+      r = e.x;
+      lev = (int)min(e.y, (uint32_t)kLevels);
+      t = topo[r];
+      node_centre(node_box(boxes, B, first, r), (uint64_t)e.z | (uint64_t)e.w << 32, lev, cs.c);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sl[q] = T.slot[8 * i + q];
+      sort_slots(sl);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (sl[q] != ~0ull && !((uint32_t)sl[q] & kTopRef)) m[q] = mom64[(uint32_t)(sl[q] >> 32)];
+    }
+    for (int L = hi; L >= 0; --L) {
+      lds_barrier();  // deeper levels summed
+      if (lev != L) continue;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (sl[q] == ~0ull) continue;
+        if ((uint32_t)sl[q] & kTopRef) m[q] = smt[(uint32_t)sl[q] & ~kTopRef];
+        cs.add(m[q]);
+      }
+      const Mom64 mr = top_mom(cs);
+      smt[i] = mr;
+      mom64[r] = mr;
+      top_records(node_box(boxes, B, first, r), t, r, cs.c, mr, mom32, wn, cen64);
+    }
+    return;
+  }
+  for (int L = hi; L >= 0; --L) {
+    __syncthreads();  // deeper levels summed (global memory)
+    for (uint32_t i = threadIdx.x; i < ntop; i += kTopThreads) {
+      const uint4 e = T.list[i];
+      if ((int)e.y != L) continue;
+      const uint32_t r = e.x;
+      uint64_t sl[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sl[q] = T.slot[8 * i + q];
+      sort_slots(sl);
+      Mom64 m[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (sl[q] != ~0ull) m[q] = mom64[(uint32_t)(sl[q] >> 32)];
+      const BoxDev &bx = node_box(boxes, B, first, r);
+      ChildSums cs;
+      node_centre(bx, (uint64_t)e.z | (uint64_t)e.w << 32, L, cs.c);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (sl[q] != ~0ull) cs.add(m[q]);
+      const Mom64 mr = top_mom(cs);
+      mom64[r] = mr;
+      if (semax) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (sl[q] != ~0ull) {
+            const uint32_t node = (uint32_t)(sl[q] >> 32);
+            cs.add_lengths(semax[node], semin[node]);
+          }
+        semax[r] = cs.hi;
+        semin[r] = cs.lo;
+      }
+      top_records(bx, topo[r], r, cs.c, mr, mom32, wn, cen64);
     }
   }
 }
@@ -707,46 +1014,6 @@ __global__ __launch_bounds__(kThreads) void k_targets_map(const BoxDev *boxes, c
   tval[t] = t;
 }
 
-// Walk records for the mixed-precision walk (see WNode).
-__global__ __launch_bounds__(kThreads) void k_wnodes(const BoxDev *boxes, int B, const Topo *topo,
-                                                     const Mom32 *mom32, const uint32_t *first,
-                                                     const uint32_t *scalars, uint32_t node_cap, WNode *wn,
-                                                     double4 *cen64) {
-  const uint32_t tot = min(scalars[3], node_cap);
-  for (uint32_t r = blockIdx.x * kThreads + threadIdx.x; r < tot; r += gridDim.x * kThreads) {
-    const Topo t = topo[r];
-    const Mom32 m = mom32[r];
-    const BoxDev &bx = boxes[box_of(boxes, B, first[r])];
-    const int lev = (int)(t.b >> kCountBits);
-    const int hc = 1 << (kLevels - lev);
-    const bool leaf = (t.corner & kLeafBit) != 0;
-    const float side = ldexpf(bx.Lf, -lev);
-    WNode w;
-    w.c[0] = 0x4B000000 | (2 * (int)(t.corner & 0x1fffffull) + hc);
-    w.c[1] = 0x4B000000 | (2 * (int)((t.corner >> 21) & 0x1fffffull) + hc);
-    w.c[2] = 0x4B000000 | (2 * (int)((t.corner >> 42) & 0x1fffffull) + hc);
-    w.side2 = side * side;
-    w.o[0] = m.ox;
-    w.o[1] = m.oy;
-    w.o[2] = m.oz;
-    w.m = m.m;
-    w.reach = bx.rcutf + 0.5f * side;
-    w.near = 0.6f * side;
-    const uint32_t count = t.b & kCountMask;
-    const bool wrap = bx.periodic && bx.rcutf + side >= 0.5f * bx.Lf;
-    w.a = leaf ? leaf_tag_bits(t.a, min(count, 8u), wrap) : t.a;
-    w.cf = count | (leaf && count > 8u ? kWBig : 0u) | (leaf ? kWLeaf : 0u) | (wrap ? kWWrap : 0u);
-    wn[r] = w;
-    // the FP64 walks' cube centre and side, in the expressions they used to
-    // evaluate at every visit (so the values are the same to the bit)
-    const double h = bx.L * 0x1p-21, half = ldexp(1.0, 20 - lev);
-    cen64[r] = make_double4(bx.lo[0] + ((double)(uint32_t)(t.corner & 0x1fffffull) + half) * h,
-                            bx.lo[1] + ((double)(uint32_t)((t.corner >> 21) & 0x1fffffull) + half) * h,
-                            bx.lo[2] + ((double)(uint32_t)((t.corner >> 42) & 0x1fffffull) + half) * h,
-                            ldexp(bx.L, -lev));
-  }
-}
-
 __global__ __launch_bounds__(kThreads) void k_max_level(const Topo *topo, const uint32_t *scalars,
                                                         uint32_t node_cap, uint32_t *out) {
   __shared__ uint32_t m;
@@ -765,17 +1032,14 @@ __global__ void k_reset(uint32_t *w) { *w = 0; }
 __global__ void k_reset_n(uint32_t *w, int n) {
   if ((int)threadIdx.x < n) w[threadIdx.x] = 0;
 }
-// Status word cleared, particle count for the device-side scans, level
-// counters of the moment buckets cleared.
-__global__ void k_init_scalars(uint32_t *sc, uint32_t n, uint32_t *lvl_cnt, uint32_t *lvl_fill) {
+// Status word cleared, particle count for the device-side scans, counters
+// of the top-node lists cleared.
+__global__ void k_init_scalars(uint32_t *sc, uint32_t n, uint32_t *top_cnt) {
   if (threadIdx.x == 0) {
     sc[0] = 0u;
     sc[4] = n;
   }
-  if (threadIdx.x <= kLevels) {
-    lvl_cnt[threadIdx.x] = 0;
-    lvl_fill[threadIdx.x] = 0;
-  }
+  if (threadIdx.x < 4) top_cnt[threadIdx.x] = 0;
 }
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -837,7 +1101,7 @@ bool radix_sort(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *
 void launch_build(BuildArrays &A, hipStream_t s) {
   const uint32_t n = A.n;
   const uint32_t nb = cdiv(n, kThreads);
-  k_init_scalars<<<1, 64, 0, s>>>(A.scalars, n, A.lvl_cnt, A.lvl_fill);
+  k_init_scalars<<<1, 64, 0, s>>>(A.scalars, n, A.top_cnt);
   if (A.any_open) {
     k_frame_init<<<cdiv(6 * (uint64_t)A.B, kThreads), kThreads, 0, s>>>(A.B, A.minmax);
     k_frame_reduce<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, A.minmax, &A.scalars[0]);
@@ -870,25 +1134,27 @@ void launch_build(BuildArrays &A, hipStream_t s) {
     k_box_nodes<<<cdiv(A.B, 64), 64, 0, s>>>(A.boxes, A.B, A.S, n, A.node_cap, A.scalars, A.parent);
     k_emit<<<nb, kThreads, 0, s>>>(A.boxes, A.B, n, skeys, A.lcp, A.depth, A.S, A.node_cap, A.topo,
                                    A.first, A.skip);
-    k_links<<<gnodes, kThreads, 0, s>>>(A.topo, A.skip, A.scalars, A.node_cap, A.parent, A.nchild, A.lvl_cnt);
+    k_links<<<gnodes, kThreads, 0, s>>>(A.topo, A.skip, A.scalars, A.node_cap, A.parent);
   }
   {
     const TraceRange r("build: moments");
-    k_leaves_and_buckets<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.part64, A.part32, A.mom64,
-                                                     A.mom32, A.scalars, A.node_cap, A.lvl_cnt, A.lvl_fill,
-                                                     A.lvl_nodes, A.seps, A.semax, A.semin);
-    // internal nodes at level L number at most n / (leaf_max + 1) <= n / 2; most
-    // levels hold few, so a small grid (grid-stride) keeps the launches short
-    const uint32_t glev = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(n / 2 + 1, kThreads), 512));
-    for (int L = kLevels - 1; L >= 0; --L)
-      k_moments_level<<<glev, kThreads, 0, s>>>(A.boxes, A.B, L, A.topo, A.first, A.skip, A.lvl_cnt,
-                                                A.lvl_nodes, A.scalars, A.node_cap, A.mom64, A.mom32, A.semax,
-                                                A.semin);
+    const size_t c = A.top_cap;
+    const TopArrays T{A.top_cnt, reinterpret_cast<uint4 *>(A.top_buf), reinterpret_cast<uint64_t *>(A.top_buf + 4 * c),
+                      A.top_id, A.top_cap};
+    // grid-stride over nodes (the node count is known on the device only)
+    const uint32_t gleaf = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kThreads), 4096));
+    k_moments_leaves<<<gleaf, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.parent, A.part64, A.part32, A.mom64,
+                                                A.mom32, A.wnode, A.cen64, A.scalars, A.node_cap, T, A.seps,
+                                                A.semax, A.semin);
+    const uint32_t gseg = std::max<uint32_t>(1, std::min<uint32_t>(cdiv(A.node_cap, kSegChunk), 4096));
+    k_moments_segments<<<gseg, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.first, A.parent, A.top_id, A.mom64,
+                                                 A.mom32, A.wnode, A.cen64, A.scalars, A.node_cap, T, A.semax,
+                                                 A.semin);
+    k_moments_top<<<1, kTopThreads, 0, s>>>(A.boxes, A.B, A.topo, A.first, A.mom64, A.mom32, A.wnode, A.cen64, T,
+                                            A.semax, A.semin);
   }
-  const TraceRange r("build: walk records");
-  k_wnodes<<<gnodes, kThreads, 0, s>>>(A.boxes, A.B, A.topo, A.mom32, A.first, A.scalars, A.node_cap,
-                                       A.wnode, A.cen64);
 }
+
 
 // Active targets (see ActiveArrays).  Flags and the compaction run over the
 // sorted order, so the active list keeps the curve order of the tree.

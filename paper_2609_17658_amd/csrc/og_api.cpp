@@ -122,10 +122,10 @@ void carve(Carver &c, BuildArrays &A, uint32_t n, uint32_t node_cap, int B, bool
   A.first = c.take<uint32_t>(node_cap);
   A.skip = c.take<uint32_t>(node_cap);
   A.parent = c.take<uint32_t>(node_cap);
-  A.nchild = c.take<uint32_t>(node_cap);
-  A.lvl_cnt = c.take<uint32_t>(32);
-  A.lvl_fill = c.take<uint32_t>(32);
-  A.lvl_nodes = c.take<uint32_t>(node_cap);
+  A.top_cap = top_node_bound(node_cap);
+  A.top_cnt = c.take<uint32_t>(32);
+  A.top_buf = c.take<uint32_t>(kTopWords * A.top_cap);
+  A.top_id = c.take<uint32_t>(node_cap);
   A.scalars = c.take<uint32_t>(32);
   if (soft) {
     A.seps = c.take<double>(n);

@@ -42,8 +42,11 @@ struct BuildArrays {
   Mom32 *mom32;
   WNode *wnode;
   double4 *cen64;  // per node: FP64 cube centre (x, y, z) and side (w), for the FP64 walks
-  uint32_t *first, *skip, *parent, *nchild;
-  uint32_t *lvl_cnt, *lvl_fill, *lvl_nodes;   // internal nodes bucketed by level
+  uint32_t *first, *skip, *parent;
+  uint32_t *top_cnt;          // [0] top nodes [2] deepest top level
+  uint32_t *top_buf;          // TopArrays' lists, kTopWords per top node (top_cap)
+  uint32_t *top_id;           // per node: index of a top node in the top list
+  uint32_t top_cap;           // bound on the top nodes (top_node_bound)
   uint32_t *scalars;          // [0] status [3] n_nodes [4] n [8..15] walk queues
                               // [5] deepest level (stats)
   int any_open;               // some box has periodic = 0
@@ -51,6 +54,23 @@ struct BuildArrays {
   double *seps;               // sorted per-particle softening lengths (null: none given)
   double *semax, *semin;      // per node: largest and smallest of its particles' lengths
 };
+
+// The moment kernels sum subtrees of up to kSegNodes nodes per workgroup;
+// the nodes with larger subtrees ("top" nodes) are summed by one workgroup.
+// Top nodes of one level have disjoint subtrees of more than kSegNodes
+// nodes each, so there are fewer than node_cap / kSegNodes + 1 per level.
+constexpr uint32_t kSegNodes = 768;
+inline uint32_t top_node_bound(uint32_t node_cap) { return 2 * (((kLevels + 1) * (node_cap / kSegNodes + 1) + 1) / 2); }
+
+// The top-node list the moment kernels pass to the top-node kernel.
+struct TopArrays {
+  uint32_t *cnt;    // [0] top nodes [2] deepest level of a top node
+  uint4 *list;      // top nodes (cap): node, level, cube corner (low, high word)
+  uint64_t *slot;   // per top node: eight child slots by octant (8 cap)
+  uint32_t *id;     // per node (node_cap): its class (a top node: with its index in `list`)
+  uint32_t cap;
+};
+constexpr size_t kTopWords = 20;  // words of top_buf per top node
 
 void launch_build(BuildArrays &A, hipStream_t s);
 void launch_max_level(const BuildArrays &A, uint32_t *out, hipStream_t s);
