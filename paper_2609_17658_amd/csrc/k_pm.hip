@@ -480,9 +480,9 @@ __global__ __launch_bounds__(kPmThreads) void k_pm_tables(PmTables Tb, int n, do
   }
 }
 
-template <typename T>
+template <int kT = kFftThreads, typename T>
 __device__ inline void copy_to_lds(T *dst, const T *src, int count) {
-  for (int k = threadIdx.x; k < count; k += kFftThreads) dst[k] = src[k];
+  for (int k = threadIdx.x; k < count; k += kT) dst[k] = src[k];
 }
 
 // The radix-2 stages of `total / n` lines held in LDS (bit-reversed input,
@@ -778,7 +778,7 @@ __device__ inline void dft8_last(double2 e[8], int i, int n, const double2 *tw) 
 // Stages 4 .. log2 n - 3 of `total / n` lines in LDS (lq layout): one
 // radix-2 stage first when their number is odd, then two stages per sweep.
 // Callers synchronise before; every sweep ends with a barrier.
-template <int kSign, bool kConj>
+template <int kSign, bool kConj, int kT = kFftThreads>
 __device__ inline void fft_middle(double2 *buf, const double2 *tw, int n, int logn, int total) {
 #pragma clang fp contract(fast)
   const int tid = threadIdx.x;
@@ -786,7 +786,7 @@ __device__ inline void fft_middle(double2 *buf, const double2 *tw, int n, int lo
   int s = 4;
   if ((s_end - s + 1) & 1) {
     const int h = 1 << (s - 1), step = n >> s;
-    for (int b = tid; b < total / 2; b += kFftThreads) {
+    for (int b = tid; b < total / 2; b += kT) {
       const int t = b >> (logn - 1), r = b & (n / 2 - 1);
       const int pos = r & (h - 1), grp = r >> (s - 1);
       const int i0 = t * n + grp * 2 * h + pos;
@@ -799,7 +799,7 @@ __device__ inline void fft_middle(double2 *buf, const double2 *tw, int n, int lo
   }
   for (; s < s_end; s += 2) {
     const int h = 1 << (s - 1), step1 = n >> s, step2 = n >> (s + 1);
-    for (int b = tid; b < total / 4; b += kFftThreads) {
+    for (int b = tid; b < total / 4; b += kT) {
       const int t = b >> (logn - 2), r = b & (n / 4 - 1);
       const int pos = r & (h - 1), grp = r >> (s - 1);
       const int i0 = t * n + grp * 4 * h + pos;
@@ -872,15 +872,18 @@ __global__ __launch_bounds__(kFftThreads) void k_fft8_axis(double2 *data, const 
 // Green's function and those stages run in registers.  One LDS tile serves
 // the forward transform and then each output field in turn (the other
 // field waits in registers).  At most one column per thread (tl n <= 8
-// kFftThreads, as fft_lines picks).
-__global__ __launch_bounds__(kFftThreads) void k_fft8_x_green(double2 *B, double2 *A, PmTables Tb, int n, int logn,
-                                                              int tl, double L, double G) {
+// kT, as fft_lines picks; kT = 512 on the large meshes gives tiles of
+// eight lines there, whose rows along the contiguous axis are whole 128-byte
+// lines).
+template <int kT>
+__global__ __launch_bounds__(kT) void k_fft8_x_green(double2 *B, double2 *A, PmTables Tb, int n, int logn, int tl,
+                                                     double L, double G) {
   extern __shared__ double2 sm[];
   double2 *bb = sm;
   double2 *tw = sm + lq_size(tl * n);
   double *wax = reinterpret_cast<double *>(tw + n / 2);
-  copy_to_lds(tw, Tb.twf, n / 2);
-  copy_to_lds(wax, Tb.wax, n);
+  copy_to_lds<kT>(tw, Tb.twf, n / 2);
+  copy_to_lds<kT>(wax, Tb.wax, n);
   const LineTile T(n, logn, 0, tl, xcd_unit(blockIdx.x, gridDim.x));
   const int cols = tl * n / 8, n8 = n / 8;
   const int c = threadIdx.x;
@@ -896,7 +899,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft8_x_green(double2 *B, double
     for (int r = 0; r < 8; ++r) bb[lq(base + r)] = u[r];
   }
   __syncthreads();
-  fft_middle<-1, false>(bb, tw, n, logn, tl * n);
+  fft_middle<-1, false, kT>(bb, tw, n, logn, tl * n);
   double2 ua[8], ub[8];
   if (c < cols) {
     double2 e[8];
@@ -922,7 +925,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft8_x_green(double2 *B, double
       for (int r = 0; r < 8; ++r) bb[lq(base + r)] = f == 0 ? ua[r] : ub[r];
     }
     __syncthreads();
-    fft_middle<1, true>(bb, tw, n, logn, tl * n);
+    fft_middle<1, true, kT>(bb, tw, n, logn, tl * n);
     if (c < cols) {
       double2 e[8];
 #pragma unroll
@@ -1066,6 +1069,11 @@ size_t fft_lds_bytes(int n, int tl, bool fused) {
 // LDS a workgroup may hold on gfx950.
 constexpr size_t kLdsMax = 163840;
 
+// Threads the fused x pass may use: 512 on meshes of 512 and more (tiles
+// of eight lines at 512), else kFftThreads; a launch takes 512 only when
+// its tile needs them.
+int xg_threads(int n) { return fft_regs(n) && n >= 512 ? 512 : kFftThreads; }
+
 // Lines per workgroup.  Register-staged passes: 2048 elements per tile (one
 // column of eight per thread; at most 16 lines); smaller meshes: 16 lines.
 // At most n, and halved until the workgroup's LDS fits (and, for the fused
@@ -1074,12 +1082,13 @@ constexpr size_t kLdsMax = 163840;
 // and halved until it fits), so that the tests run every width and tile
 // size the library can pick on small meshes.
 int fft_lines(int n, bool fused) {
-  int tl = fft_regs(n) ? (2048 / n > 16 ? 16 : 2048 / n) : 16;
+  const int per = 8 * (fused ? xg_threads(n) : kFftThreads);  // tile elements the workgroup holds in registers
+  int tl = fft_regs(n) ? (per / n > 16 ? 16 : per / n) : 16;
   const char *e = getenv("OG_FFT_LINES");
   const int want = e ? atoi(e) : 0;
   if (want >= 1 && want <= 16 && (want & (want - 1)) == 0) tl = want;
   if (tl > n) tl = n;
-  while (tl > 1 && (fft_lds_bytes(n, tl, fused) > kLdsMax || (fused && tl * n > kXgPer * kFftThreads))) tl >>= 1;
+  while (tl > 1 && (fft_lds_bytes(n, tl, fused) > kLdsMax || (fused && tl * n > per))) tl >>= 1;
   return tl;
 }
 
@@ -1117,7 +1126,9 @@ void allow_large_lds() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft8_axis<1>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft8_x_green),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft8_x_green<kFftThreads>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft8_x_green<512>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
     return true;
   }();
@@ -1187,7 +1198,10 @@ void launch_pm(const PmArgs &P, hipStream_t s) {
     const int tl = fft_lines(P.n, true);
     const uint32_t blocks = (uint32_t)((uint64_t)P.n * P.n / tl);
     const size_t lds = fft_lds_bytes(P.n, tl, true);
-    if (fft_regs(P.n)) k_fft8_x_green<<<blocks, kFftThreads, lds, s>>>(P.B, P.A, Tb, P.n, logn, tl, P.L, P.G);
+    if (fft_regs(P.n) && tl * P.n > 8 * kFftThreads)  // one column of eight per thread
+      k_fft8_x_green<512><<<blocks, 512, lds, s>>>(P.B, P.A, Tb, P.n, logn, tl, P.L, P.G);
+    else if (fft_regs(P.n))
+      k_fft8_x_green<kFftThreads><<<blocks, kFftThreads, lds, s>>>(P.B, P.A, Tb, P.n, logn, tl, P.L, P.G);
     else k_fft_x_green<<<blocks, kFftThreads, lds, s>>>(P.B, P.A, Tb, P.n, logn, tl, P.L, P.G);
   }
   for (double2 *f : {P.A, P.B}) {

@@ -113,6 +113,36 @@ def test_pm_every_fft_tile_width(og_mod, n_grid, monkeypatch):
     m.close()
 
 
+def test_pm_512_fused_pass_threads(og_mod, monkeypatch):
+    """At 512^3 the fused x pass takes tiles of 8 lines with 512 threads;
+    with 4 lines or fewer it takes 256 threads.  Every width gives the
+    default result bitwise (from caller arrays and from a tree), and the
+    mesh force conserves momentum: with the same assignment and
+    interpolation and an odd gradient kernel the pair forces cancel, so
+    sum m a vanishes up to rounding (checked on the oracle at 32^3, where
+    it is 1e-17 of sum m |a|)."""
+    n_grid = 512
+    pos, mass = _particles(30000, 7)
+    stream = torch.cuda.current_stream()
+    m = og_mod.PM(n_grid, 1.0, 1.0, 1.25 / n_grid, stream=stream)
+    ref_a, ref_p = m.force(_dev(pos), _dev(mass))
+    tree = og_mod.Tree(_dev(pos), _dev(mass), 1.0, synth.scale_free_params(30000).as_dict(), stream=stream)
+    for lines in (8, 4, 1):
+        _note("pm n_grid=512 with %d-line FFT tiles" % lines)
+        monkeypatch.setenv("OG_FFT_LINES", str(lines))
+        acc, pot = m.force(_dev(pos), _dev(mass))
+        at, pt = m.force_tree(tree)
+        torch.cuda.synchronize()
+        monkeypatch.delenv("OG_FFT_LINES")
+        assert torch.equal(acc, ref_a) and torch.equal(pot, ref_p), lines
+        assert torch.equal(at, ref_a) and torch.equal(pt, ref_p), lines
+    a = ref_a.cpu().numpy()
+    mom = np.abs((mass[:, None] * a).sum(0))
+    assert np.all(mom <= 1e-12 * (mass[:, None] * np.abs(a)).sum(0))
+    tree.close()
+    m.close()
+
+
 def test_pm_wraps_positions_and_accumulates(og_mod):
     pos, mass = _particles(4000, 5)
     m = og_mod.PM(32, 1.0, 1.0, 1.25 / 32, stream=torch.cuda.current_stream())
