@@ -595,15 +595,19 @@ __device__ inline Mom64 store_node(const BoxDev &bx, const Topo &t, uint32_t r, 
 }
 
 // One particle q of a leaf with cube centre c: its mass and first moments
-// added, its FP32 offset from the centre written.
-__device__ inline void leaf_add(const double4 q, const double c[3], double &M, double &s0, double &s1, double &s2,
-                                float4 &out) {
+// added.
+__device__ inline void leaf_add(const double4 q, const double c[3], double &M, double &s0, double &s1, double &s2) {
   const double dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
   M += q.w;
   s0 += q.w * dx;
   s1 += q.w * dy;
   s2 += q.w * dz;
-  out = make_float4((float)dx, (float)dy, (float)dz, (float)q.w);
+}
+
+// A leaf particle's FP32 offset from the leaf's centre of mass m (the mixed
+// walk adds it to the target's offset from that centre).
+__device__ inline float4 leaf_offset(const double4 q, const Mom64 &m) {
+  return make_float4((float)(q.x - m.cx), (float)(q.y - m.cy), (float)(q.z - m.cz), (float)q.w);
 }
 
 // Sums of an internal node over its children's moments, in child order.
@@ -739,11 +743,16 @@ __global__ __launch_bounds__(kThreads) void k_moments_leaves(const BoxDev *boxes
       // (two loops: a select between an LDS and a global pointer is not
       // formed, which this compiler mishandles)
       if (staged) {
-        for (uint32_t j = f; j < f + cnt; ++j) leaf_add(stage[j - pa], c, M, s0, s1, s2, part32[j]);
+        for (uint32_t j = f; j < f + cnt; ++j) leaf_add(stage[j - pa], c, M, s0, s1, s2);
       } else {
-        for (uint32_t j = f; j < f + cnt; ++j) leaf_add(part64[j], c, M, s0, s1, s2, part32[j]);
+        for (uint32_t j = f; j < f + cnt; ++j) leaf_add(part64[j], c, M, s0, s1, s2);
       }
-      store_node(bx, t, r, c, M, s0, s1, s2, mom64, mom32, wn, cen64);
+      const Mom64 m = store_node(bx, t, r, c, M, s0, s1, s2, mom64, mom32, wn, cen64);
+      if (staged) {
+        for (uint32_t j = f; j < f + cnt; ++j) part32[j] = leaf_offset(stage[j - pa], m);
+      } else {
+        for (uint32_t j = f; j < f + cnt; ++j) part32[j] = leaf_offset(part64[j], m);
+      }
       if (seps) {
         double hi = seps[f], lo = hi;
         for (uint32_t j = f + 1; j < f + cnt; ++j) {

@@ -759,7 +759,7 @@ __device__ inline int wave_max_i32(int v) {
 __device__ inline int wave_min_i32(int v) { return -wave_max_i32(-v); }
 
 // List entries (float4).  A monopole: (offset, mass), mass >= 0, already
-// known to pass the cutoff.  A leaf: (offset of the leaf centre, tag), the
+// known to pass the cutoff.  A leaf: (offset of the leaf's centre of mass, tag), the
 // tag's bits as laid out by leaf_tag_bits.
 __device__ inline float leaf_tag(uint32_t first, uint32_t n, bool wrap) {
   return __uint_as_float(leaf_tag_bits(first, n, wrap));
@@ -975,7 +975,8 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
           const bool wrapd = kPer && (cf & kWWrap) != 0;
           if (pend) {
             if (next <= n) {
-              list[cnt][lane] = make_float4(dcx, dcy, dcz, leaf_tag((w.a & kTagFirst) + pend, min(8u, lc - pend), wrapd));
+              list[cnt][lane] = make_float4(dcx + w.o[0], dcy + w.o[1], dcz + w.o[2],
+                                            leaf_tag((w.a & kTagFirst) + pend, min(8u, lc - pend), wrapd));
               ++cnt;
             }
             pend += 8;
@@ -1005,8 +1006,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
           }
           const bool contrib = live && !open && (!kCut || r2 < k.rc2);
           const bool open_here = live && open;
-          list[cnt][lane] = open_here ? make_float4(dcx, dcy, dcz, leaf_tag(w.a & kTagFirst, min(8u, lc), wrapd))
-                                      : make_float4(dx, dy, dz, w.m);
+          list[cnt][lane] = make_float4(dx, dy, dz, open_here ? leaf_tag(w.a & kTagFirst, min(8u, lc), wrapd) : w.m);
           if (kSoft) lsoft[cnt][lane] = emono;
           cnt += (contrib || (open_here && (cf & kWLeaf) != 0)) ? 1u : 0u;
           if (act && !open_here) next = ns;
@@ -1039,10 +1039,11 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
         }
         const bool contrib = live && !open && (!kCut || r2 < k.rc2);
         const bool open_here = live && open;
-        // one entry: the accepted monopole or, at a leaf, the opened leaf.
-        // Every lane writes its next slot; only a real entry advances it.
-        const float4 entry = open_here ? make_float4(dcx, dcy, dcz, __uint_as_float(w.a))
-                                       : make_float4(dx, dy, dz, w.m);
+        // one entry: the offset of n's centre of mass and either its mass
+        // (an accepted monopole) or, at an opened leaf, the leaf's tag (its
+        // particles' offsets are stored from that centre of mass).  Every
+        // lane writes its next slot; only a real entry advances it.
+        const float4 entry = make_float4(dx, dy, dz, open_here ? __uint_as_float(w.a) : w.m);
         list[cnt][lane] = entry;
         if (kSoft) lsoft[cnt][lane] = emono;
         cnt += (uint32_t)(contrib || (open_here && (cf & kWLeaf) != 0));
@@ -1375,9 +1376,9 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
                 q.c[1] = fc[1];
                 q.c[2] = fc[2];
                 q.tag = j | (wrapd ? kGWrap : 0u);
-                q.o[0] = pq.x;
-                q.o[1] = pq.y;
-                q.o[2] = pq.z;
+                q.o[0] = w.o[0] + pq.x;  // leaf offsets are stored from the leaf's centre of mass
+                q.o[1] = w.o[1] + pq.y;
+                q.o[2] = w.o[2] + pq.z;
                 q.m = pq.w;
                 list[cnt + lane] = q;
               }
