@@ -560,7 +560,8 @@ __device__ inline void walk_records(const BoxDev &bx, const Topo &t, const Mom32
   w.c[0] = 0x4B000000 | (2 * (int)(t.corner & 0x1fffffull) + hc);
   w.c[1] = 0x4B000000 | (2 * (int)((t.corner >> 21) & 0x1fffffull) + hc);
   w.c[2] = 0x4B000000 | (2 * (int)((t.corner >> 42) & 0x1fffffull) + hc);
-  w.side2 = side * side;
+  // the geometric criterion side^2 > theta^2 r^2 as one comparison with r^2
+  w.side2 = bx.relative ? side * side : (bx.theta2f > 0.0f ? side * side / bx.theta2f : INFINITY);
   w.o[0] = m.ox;
   w.o[1] = m.oy;
   w.o[2] = m.oz;

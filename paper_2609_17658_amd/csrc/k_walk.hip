@@ -995,7 +995,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
           const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
           const bool act = next <= n;
           const bool live = act && !(kCut && mdc > w.reach);
-          const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
+          const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > r2);
           bool open = far_open || (mdc < w.near);
           float emono = 0.0f;
           if (kSoft && k.soft) {
@@ -1028,7 +1028,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
         }
         const float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
         const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
-        const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
+        const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > r2);
         bool open = far_open || (mdc < w.near);
         float emono = 0.0f;  // the monopole's softening length (k.soft)
         if (kSoft && k.soft) {
@@ -1341,7 +1341,7 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
         }
         const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
         const bool live = valid && !(kCut && mdc > w.reach);
-        const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > k.theta2 * r2);
+        const bool far_open = relative ? (w.m * w.side2 > aol * (r2 * r2)) : (w.side2 > r2);
         const bool open = live && (far_open || mdc < w.near);
         const uint32_t nskip = ns > n ? ns : n + 1;  // a skip always moves forward
         uint32_t nn;

@@ -85,7 +85,10 @@ struct __attribute__((aligned(16))) Mom32 {
 //   c[3]:   cube centre c in half-cells of the level-21 grid, stored as
 //           0x4B000000 | c: the bits of the float 2^23 + c, a multiple of
 //           2^22 above c (so c modulo 2^22 is unchanged)
-//   side2:  side^2;  reach: r_cut + side/2;  near: 0.6 side
+//   side2:  side^2 / theta^2, the squared distance inside which the
+//           geometric criterion opens the node (infinite at theta = 0); in a
+//           box with the relative criterion, side^2
+//   reach:  r_cut + side/2;  near: 0.6 side
 //   o[3]:   centre of mass minus cube centre;  m: mass
 //   a:      internal node: skip (the next node after the subtree);
 //           leaf: its interaction-list tag (below), whose low bits hold
