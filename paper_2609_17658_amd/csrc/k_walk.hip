@@ -38,6 +38,11 @@ constexpr float kAsA2 = -0.284496736f;
 constexpr float kAsA3 = 1.421413741f;
 constexpr float kAsA4 = -1.453152027f;
 constexpr float kAsA5 = 1.061405429f;
+// The FP32 walk evaluates with v = x sqrt(log2 e) (exp(-x^2) = 2^(-v^2)):
+// p and 2/sqrt(pi) divided by sqrt(log2 e) = 1.2011224087864498.
+constexpr float kSqrtLog2e = 1.2011224087864498f;
+constexpr float kAsPv = 0.2727374808792225f;
+constexpr float kTwoOverSqrtPiV = 0.9394372786996513f;
 
 // Read-only tree data is read through the constant address space: the
 // compiler may then use scalar (SMEM) loads for wave-uniform addresses.  The
@@ -650,7 +655,7 @@ __global__ __launch_bounds__(64 * kWalk64Waves) __attribute__((amdgpu_waves_per_
 constexpr int kWalk32Threads = 64;       // one wavefront per workgroup
 
 struct Consts32 {
-  float G, eps2, inv2rs, rc2, theta2, h22, half_box, box;
+  float G, eps2, inv2rs, rc2, theta2, h22, half_box, box;  // inv2rs: sqrt(log2 e) / (2 r_s)
   float hs2, hinv;  // spline support squared and inverse
   bool cutoff, periodic, spline;
   bool soft;        // per-particle softening lengths: each pair brings its own
@@ -721,11 +726,13 @@ __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, c
   if (k.cutoff) {
     // r2 = 0 (coincident partners) gives r = 0
     const float r = r2 * __builtin_amdgcn_rsqf(r2 + 0x1p-126f);
-    const float u = r * k.inv2rs;
-    const float e = __expf(-u * u);
-    const float t = __builtin_amdgcn_rcpf(1.0f + kAsP * u);
+    // v = u sqrt(log2 e) with u = r / (2 r_s) (k.inv2rs holds the product), so
+    // that exp(-u^2) = 2^(-v^2) is one exp2; the constants in u are rescaled
+    const float v = r * k.inv2rs;
+    const float e = __builtin_amdgcn_exp2f(-(v * v));
+    const float t = __builtin_amdgcn_rcpf(1.0f + kAsPv * v);
     const float ec = t * (kAsA1 + t * (kAsA2 + t * (kAsA3 + t * (kAsA4 + t * kAsA5)))) * e;
-    S = ec + (float)kTwoOverSqrtPi * u * e;
+    S = ec + kTwoOverSqrtPiV * v * e;
     pf = ec;
   }
   const float gm = k.G * m;
@@ -847,7 +854,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
     Consts32 k;
     k.G = bx.Gf;
     k.eps2 = bx.eps2f;
-    k.inv2rs = bx.inv2rsf;
+    k.inv2rs = bx.inv2rsf * kSqrtLog2e;
     k.rc2 = bx.rc2f;
     k.theta2 = bx.theta2f;
     k.h22 = bx.h22f;
@@ -1052,7 +1059,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
         next = open_here ? next : max(next, ns);
         // the lanes still at or before n are exactly those that opened it; a
         // leaf's skip is n + 1; a skip always moves forward
-        n = __ballot(open_here) ? n + 1 : max(ns, n + 1);
+        n = __ballot(next <= n) ? n + 1 : max(ns, n + 1);
       }
     };
     if (kPer && lane_wrap) walk(std::integral_constant<int, 2>{});
@@ -1216,7 +1223,7 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
     Consts32 k;
     k.G = bx.Gf;
     k.eps2 = bx.eps2f;
-    k.inv2rs = bx.inv2rsf;
+    k.inv2rs = bx.inv2rsf * kSqrtLog2e;
     k.rc2 = bx.rc2f;
     k.theta2 = bx.theta2f;
     k.h22 = bx.h22f;
