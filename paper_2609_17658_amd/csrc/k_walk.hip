@@ -724,8 +724,9 @@ __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, c
   }
   float S = 1.0f, pf = 1.0f;
   if (k.cutoff) {
-    // r2 = 0 (coincident partners) gives r = 0
-    const float r = r2 * __builtin_amdgcn_rsqf(r2 + 0x1p-126f);
+    // the hardware square root (about 1 ulp); r2 = 0 (coincident partners)
+    // gives r = 0
+    const float r = __builtin_amdgcn_sqrtf(r2);
     // v = u sqrt(log2 e) with u = r / (2 r_s) (k.inv2rs holds the product), so
     // that exp(-u^2) = 2^(-v^2) is one exp2; the constants in u are rescaled
     const float v = r * k.inv2rs;
