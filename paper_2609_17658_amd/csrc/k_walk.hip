@@ -718,9 +718,8 @@ __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, c
       wv = ri;
     }
   } else {
-    const float rinv = __builtin_amdgcn_rsqf(r2 + (kExt && k.soft ? e * e : k.eps2));
-    g = rinv * rinv * rinv;
-    wv = rinv;
+    wv = __builtin_amdgcn_rsqf(r2 + (kExt && k.soft ? e * e : k.eps2));
+    g = 0.0f;  // Plummer: formed below as wv^3, sharing G m wv with the potential
   }
   float S = 1.0f, pf = 1.0f;
   if (k.cutoff) {
@@ -737,11 +736,20 @@ __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, c
     pf = ec;
   }
   const float gm = k.G * m;
-  const double f = (double)(gm * g * S);
+  float fs, ps;  // G m (1/r^3) S and G m (1/r) erfc, softened
+  if (kExt && k.spline) {
+    fs = gm * g * S;
+    ps = gm * wv * pf;
+  } else {
+    const float gw = gm * wv;
+    ps = gw * pf;
+    fs = gw * (wv * wv) * S;
+  }
+  const double f = (double)fs;
   ax = fma(f, (double)dx, ax);
   ay = fma(f, (double)dy, ay);
   az = fma(f, (double)dz, az);
-  ph -= (double)(gm * wv * pf);
+  ph -= (double)ps;
 }
 
 // 2^23 + a as a float, exactly, for 0 <= a < 2^23.
