@@ -784,21 +784,30 @@ __device__ inline float leaf_tag(uint32_t first, uint32_t n, bool wrap) {
 // Evaluate and empty every lane's list, lane-parallel: each step every lane
 // takes the next partner of its own list (a monopole, or the next particle
 // of a leaf entry, read with a per-lane load), in list order.
+// A lane's list position is kept as the byte offset of its slot in `list`
+// (row * kListRow + lane * 16), which is the LDS address the slot's load or
+// store takes, so that no address is formed per entry.
+constexpr uint32_t kListRow = kWalk32Threads * sizeof(float4);
+__device__ inline float4 &list_at(float4 (*list)[kWalk32Threads], uint32_t off) {
+  return *reinterpret_cast<float4 *>(reinterpret_cast<char *>(list) + off);
+}
+
 template <int kCap, bool kExt, bool kSoft>
 __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], float (*lsoft)[kWalk32Threads],
                              float eif, uint32_t lane, uint32_t p, uint32_t &cnt, const Consts32 &k, double &ax,
                              double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(fast)
-  uint32_t e = 0, j = 0;
+  // cnt: this lane's next free slot (byte offset); e: the entry being read
+  uint32_t e = lane * (uint32_t)sizeof(float4), j = 0;
   while (__ballot(e < cnt)) {
     if (e < cnt) {
-      const float4 q = list[e][lane];
+      const float4 q = list_at(list, e);
       const uint32_t tag = __float_as_uint(q.w);
       float dx = q.x, dy = q.y, dz = q.z, m = q.w;
       float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
       bool use = true;
       float es = 0.0f;                    // the pair's softening length (k.soft)
-      if (kSoft && k.soft && !(tag & kTagLeaf)) es = lsoft[e][lane];
+      if (kSoft && k.soft && !(tag & kTagLeaf)) es = lsoft[e / kListRow][lane];
       if (tag & kTagLeaf) {
         const uint32_t first = tag & kTagFirst, n = ((tag >> 27) & 7u) + 1u;
         const float4 pq = A.part32[first + j];
@@ -820,10 +829,10 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
         ++j;
         if (j == n) {
           j = 0;
-          ++e;
+          e += kListRow;
         }
       } else {
-        ++e;
+        e += kListRow;
       }
       if (use) {
         eval32<kExt>(dx, dy, dz, r2, m, k, ax, ay, az, ph, es);
@@ -831,7 +840,7 @@ __device__ inline void flush(const WalkArgs &A, float4 (*list)[kWalk32Threads], 
       }
     }
   }
-  cnt = 0;
+  cnt = lane * (uint32_t)sizeof(float4);
 }
 
 // kMode: 0 = cutoff and periodicity read from each box; 1 = cutoff, open
@@ -934,7 +943,9 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
       interior = !A.no_interior && (float)(wave_min_i32(df) - 2) * k.h22 > rc;
     }
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
-    uint32_t ni = 0, cnt = 0;
+    // cnt: the byte offset of this lane's next free list slot (see list_at)
+    uint32_t ni = 0, cnt = lane * (uint32_t)sizeof(float4);
+    const uint32_t cfull = cnt + kCap * kListRow;
     const uint32_t nend = bx.node_end;
     // A lane is active at node n while next <= n: an opening lane keeps its
     // value and so stays active in the subtree; a lane that prunes or accepts
@@ -963,7 +974,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
                               : ldw((const WNode *)((const char *)A.wnode + n * (uint32_t)sizeof(WNode)));
         const uint32_t cf = w.cf;
         // room for this visit's entry
-        if (__ballot(cnt >= (uint32_t)kCap)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
+        if (__ballot(cnt >= cfull)) flush<kCap, kExt, kSoft>(A, list, lsoft, eif, lane, p, cnt, k, ax, ay, az, ph, ni);
         float f0, f1, f2;  // node centre minus lane origin, in half-cells (exact)
         if (kPer && kForm == 1) {
           f0 = biased((w.c[0] - gq0) & kMask) - qb0;
@@ -991,9 +1002,9 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
           const bool wrapd = kPer && (cf & kWWrap) != 0;
           if (pend) {
             if (next <= n) {
-              list[cnt][lane] = make_float4(dcx + w.o[0], dcy + w.o[1], dcz + w.o[2],
-                                            leaf_tag((w.a & kTagFirst) + pend, min(8u, lc - pend), wrapd));
-              ++cnt;
+              list_at(list, cnt) = make_float4(dcx + w.o[0], dcy + w.o[1], dcz + w.o[2],
+                                               leaf_tag((w.a & kTagFirst) + pend, min(8u, lc - pend), wrapd));
+              cnt += kListRow;
             }
             pend += 8;
             if (pend >= lc) {
@@ -1022,9 +1033,9 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
           }
           const bool contrib = live && !open && (!kCut || r2 < k.rc2);
           const bool open_here = live && open;
-          list[cnt][lane] = make_float4(dx, dy, dz, open_here ? leaf_tag(w.a & kTagFirst, min(8u, lc), wrapd) : w.m);
-          if (kSoft) lsoft[cnt][lane] = emono;
-          cnt += (contrib || (open_here && (cf & kWLeaf) != 0)) ? 1u : 0u;
+          list_at(list, cnt) = make_float4(dx, dy, dz, open_here ? leaf_tag(w.a & kTagFirst, min(8u, lc), wrapd) : w.m);
+          if (kSoft) lsoft[cnt / kListRow][lane] = emono;
+          cnt += (contrib || (open_here && (cf & kWLeaf) != 0)) ? kListRow : 0u;
           if (act && !open_here) next = ns;
           const bool opened = __ballot(open_here) != 0;
           if ((cf & kWBig) && opened) {
@@ -1060,9 +1071,9 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
         // particles' offsets are stored from that centre of mass).  Every
         // lane writes its next slot; only a real entry advances it.
         const float4 entry = make_float4(dx, dy, dz, open_here ? __uint_as_float(w.a) : w.m);
-        list[cnt][lane] = entry;
-        if (kSoft) lsoft[cnt][lane] = emono;
-        cnt += (uint32_t)(contrib || (open_here && (cf & kWLeaf) != 0));
+        list_at(list, cnt) = entry;
+        if (kSoft) lsoft[cnt / kListRow][lane] = emono;
+        cnt += (contrib || (open_here && (cf & kWLeaf) != 0)) ? kListRow : 0u;
         // a lane past n is past all of n's subtree, so max() leaves it as
         // it is, and moves an active lane that did not open n to skip(n)
         next = open_here ? next : max(next, ns);
