@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "short-range tree-force particles/s, FP32 vs FP64 at stated error; p99 ms"
-FLOP_PER_INTERACTION = 43          # 36 FP32 + 7 FP64 per accepted partner (the pair term as executed)
+FLOP_PER_INTERACTION = 42          # 35 FP32 + 7 FP64 per accepted partner (the pair term as executed)
 PEAK_FP32 = 157.3e12               # MI355X FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12                  # MI355X HBM3E, B/s
 BUILD_BYTES_PER_PARTICLE = None    # computed from the tree (algorithmic bytes)

@@ -565,7 +565,7 @@ __device__ inline void walk_records(const BoxDev &bx, const Topo &t, const Mom32
   w.o[0] = m.ox;
   w.o[1] = m.oy;
   w.o[2] = m.oz;
-  w.m = m.m;
+  w.m = bx.Gf * m.m;  // G M: the FP32 pair term's factor
   w.reach = bx.rcutf + 0.5f * side;
   w.near = 0.6f * side;
   const uint32_t count = t.b & kCountMask;
@@ -606,9 +606,10 @@ __device__ inline void leaf_add(const double4 q, const double c[3], double &M, d
 }
 
 // A leaf particle's FP32 offset from the leaf's centre of mass m (the mixed
-// walk adds it to the target's offset from that centre).
-__device__ inline float4 leaf_offset(const double4 q, const Mom64 &m) {
-  return make_float4((float)(q.x - m.cx), (float)(q.y - m.cy), (float)(q.z - m.cz), (float)q.w);
+// walk adds it to the target's offset from that centre) and its G times
+// mass (the product the FP32 pair term would form, rounded the same way).
+__device__ inline float4 leaf_offset(const double4 q, const Mom64 &m, float Gf) {
+  return make_float4((float)(q.x - m.cx), (float)(q.y - m.cy), (float)(q.z - m.cz), Gf * (float)q.w);
 }
 
 // Sums of an internal node over its children's moments, in child order.
@@ -750,9 +751,9 @@ __global__ __launch_bounds__(kThreads) void k_moments_leaves(const BoxDev *boxes
       }
       const Mom64 m = store_node(bx, t, r, c, M, s0, s1, s2, mom64, mom32, wn, cen64);
       if (staged) {
-        for (uint32_t j = f; j < f + cnt; ++j) part32[j] = leaf_offset(stage[j - pa], m);
+        for (uint32_t j = f; j < f + cnt; ++j) part32[j] = leaf_offset(stage[j - pa], m, bx.Gf);
       } else {
-        for (uint32_t j = f; j < f + cnt; ++j) part32[j] = leaf_offset(part64[j], m);
+        for (uint32_t j = f; j < f + cnt; ++j) part32[j] = leaf_offset(part64[j], m, bx.Gf);
       }
       if (seps) {
         double hi = seps[f], lo = hi;

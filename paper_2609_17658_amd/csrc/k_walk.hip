@@ -698,7 +698,9 @@ __device__ inline void spline32(float u, float hinv, float &g, float &w) {
 // term, accumulated in FP64.
 // e: the pair's softening length when k.soft (kExt variants only).
 template <bool kExt>
-__device__ inline void eval32(float dx, float dy, float dz, float r2, float m, const Consts32 &k, double &ax,
+// gm: the partner's G times mass (walk records and FP32 particle copies hold
+// it so).
+__device__ inline void eval32(float dx, float dy, float dz, float r2, float gm, const Consts32 &k, double &ax,
                               double &ay, double &az, double &ph, float e = 0.0f) {
 #pragma clang fp contract(fast)
   float g, wv;  // softened 1/r^3 and 1/r
@@ -735,7 +737,6 @@ __device__ inline void eval32(float dx, float dy, float dz, float r2, float m, c
     S = ec + kTwoOverSqrtPiV * v * e;
     pf = ec;
   }
-  const float gm = k.G * m;
   float fs, ps;  // G m (1/r^3) S and G m (1/r) erfc, softened
   if (kExt && k.spline) {
     fs = gm * g * S;
@@ -888,11 +889,12 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
     uint32_t p = 0, slot = 0;
     const bool valid = lane_target(A, gr, bx, lane, p, slot);
     const float eif = k.soft && valid ? (float)A.seps[p] : 0.0f;  // the target's softening length
-    // relative criterion: open iff M side^2 > (alpha |a_old| / G) r^4
+    // relative criterion: open iff G M side^2 > alpha |a_old| r^4 (the
+    // record's mass is G M)
     float aol = 0.0f;
     if (relative && valid) {
       const double *v = A.a_old + 3ull * (A.perm[p] - bx.p_off);
-      aol = (float)(bx.alpha * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / bx.G);
+      aol = (float)(bx.alpha * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
     }
     // lane origin: centre of the target's level-21 cell, in half-cells
     int o0 = 0, o1 = 0, o2 = 0;
@@ -1261,7 +1263,7 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
     float aol = 0.0f;
     if (relative && valid) {
       const double *v = A.a_old + 3ull * (A.perm[p] - bx.p_off);
-      aol = (float)(bx.alpha * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / bx.G);
+      aol = (float)(bx.alpha * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));  // against G M
     }
     int o0 = 0, o1 = 0, o2 = 0;
     float xr = 0.0f, yr = 0.0f, zr = 0.0f;

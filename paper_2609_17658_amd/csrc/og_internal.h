@@ -89,7 +89,7 @@ struct __attribute__((aligned(16))) Mom32 {
 //           geometric criterion opens the node (infinite at theta = 0); in a
 //           box with the relative criterion, side^2
 //   reach:  r_cut + side/2;  near: 0.6 side
-//   o[3]:   centre of mass minus cube centre;  m: mass
+//   o[3]:   centre of mass minus cube centre;  m: G times the mass
 //   a:      internal node: skip (the next node after the subtree);
 //           leaf: its interaction-list tag (below), whose low bits hold
 //           the leaf's first particle
