@@ -412,18 +412,20 @@ __device__ inline uint32_t lane_rank(uint64_t mask) {
 // descriptors (x: owner lane | entry << 8, y: particle within the entry,
 // z: the owner's target) and then, in the same place, its terms; a ballot
 // marks the slots whose pair contributes.
-template <bool kExt, bool kTail>
-__device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*lsoft)[64], double4 *slots,
-                               uint32_t lane, uint32_t p, bool soft, const BoxDev &bx, uint32_t &cnt, double &ax,
-                               double &ay, double &az, double &ph, uint32_t &ni) {
+// The row machinery of the evaluation, for any list layout: items(e) is
+// the number of items of this lane's entry e (e < nent), and
+// term(l, e, j, po, t) computes the terms t of item j of lane l's entry e
+// for target po and says whether the pair contributes.
+template <int kCap, class Items, class Term>
+__device__ inline void flush_rows64(double4 *slots, uint32_t lane, uint32_t p, uint32_t nent, Items items, Term term,
+                                    double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
 #pragma clang fp contract(off)
   // this lane's entry sizes (in items) and their total
-  constexpr int kCap = walk64_cap<kExt>();
   uint32_t sz[kCap];
   uint32_t P = 0;
 #pragma unroll
   for (int e = 0; e < kCap; ++e) {
-    sz[e] = (uint32_t)e < cnt ? entry_items64(list[e][lane]) : 0u;
+    sz[e] = (uint32_t)e < nent ? items((uint32_t)e) : 0u;
     P += sz[e];
   }
   uint32_t ce = 0, cj = 0;  // entry and particle of this lane's next item
@@ -458,29 +460,7 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
     bool contributes = false;
     if (lane < f) {
       const uint4 d = *reinterpret_cast<const uint4 *>(slots + lane);
-      const uint32_t l = d.x & 63u, e = d.x >> 8, po = d.z;
-      const double4 q = list[e][l];
-      double dx = q.x, dy = q.y, dz = q.z, m = q.w, es = bx.eps;
-      bool use = true;
-      if (q.w >= 0.0) {
-        if (soft) es = lsoft[e][l];
-      } else {
-        const uint64_t bits = (uint64_t)__double_as_longlong(q.x);
-        const uint32_t i = (uint32_t)bits + d.y;
-        use = i != po;
-        const double4 xo = A.part64[po], sp = A.part64[i];
-        dx = sp.x - xo.x;
-        dy = sp.y - xo.y;
-        dz = sp.z - xo.z;
-        // a branch: leaves of interior groups (below level 1) need no image
-        minimg3(dx, dy, dz, (bits >> 63) != 0, bx.box);
-        m = sp.w;
-        if (soft) {
-          const double ej = A.seps[i], eo = A.seps[po];
-          es = eo > ej ? eo : ej;
-        }
-      }
-      contributes = use && pair64_terms<kExt, kTail>(dx, dy, dz, m, es, bx, t);
+      contributes = term(d.x & 63u, d.x >> 8, d.y, d.z, t);
     }
     const uint64_t used = __ballot(contributes);
     __builtin_amdgcn_wave_barrier();
@@ -505,6 +485,41 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
     }
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+template <bool kExt, bool kTail>
+__device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*lsoft)[64], double4 *slots,
+                               uint32_t lane, uint32_t p, bool soft, const BoxDev &bx, uint32_t &cnt, double &ax,
+                               double &ay, double &az, double &ph, uint32_t &ni) {
+  constexpr int kCap = walk64_cap<kExt>();
+  flush_rows64<kCap>(
+      slots, lane, p, cnt, [&](uint32_t e) { return entry_items64(list[e][lane]); },
+      [&](uint32_t l, uint32_t e, uint32_t j, uint32_t po, double4 &t) {
+#pragma clang fp contract(off)
+        const double4 q = list[e][l];
+        double dx = q.x, dy = q.y, dz = q.z, m = q.w, es = bx.eps;
+        bool use = true;
+        if (q.w >= 0.0) {
+          if (soft) es = lsoft[e][l];
+        } else {
+          const uint64_t bits = (uint64_t)__double_as_longlong(q.x);
+          const uint32_t i = (uint32_t)bits + j;
+          use = i != po;
+          const double4 xo = A.part64[po], sp = A.part64[i];
+          dx = sp.x - xo.x;
+          dy = sp.y - xo.y;
+          dz = sp.z - xo.z;
+          // a branch: leaves of interior groups (below level 1) need no image
+          minimg3(dx, dy, dz, (bits >> 63) != 0, bx.box);
+          m = sp.w;
+          if (soft) {
+            const double ej = A.seps[i], eo = A.seps[po];
+            es = eo > ej ? eo : ej;
+          }
+        }
+        return use && pair64_terms<kExt, kTail>(dx, dy, dz, m, es, bx, t);
+      },
+      ax, ay, az, ph, ni);
   cnt = 0;
 }
 
@@ -1092,6 +1107,249 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
   }
 }
 
+// ------------------------------------------------- screened FP64 walk --
+// The FP64 walk's decisions compare FP64 quantities with per-node
+// thresholds: the largest centre offset max|dc| with r_cut + side/2 (prune)
+// and 0.6 side (near), r^2 with side^2/theta^2 (open) and r_cut^2 (cutoff).
+// This walk forms the same quantities in FP32 the way the mixed walk does
+// (node centres exact in half-cells, each target's offset from its cell
+// centre rounded once, centre-of-mass offsets rounded once) and takes a
+// comparison's outcome from the FP32 value when it lies outside a band
+// around the threshold that the FP32 error cannot cross.  With h half a
+// level-21 cell, the FP32 max|dc| is within 2^-22.4 (max|dc| + h) +
+// 2^-51 (|lo| + L) of the FP64 one, and near a threshold max|dc| >= 1.2 h;
+// r^2 is within 2^-18.5 r^2 of the FP64 value near either r^2 threshold
+// when theta <= 1 (there |offset| <= 1.5 r and h <= r/2).  With the
+// thresholds' own FP32 rounding (at most 5 x 2^-24) the distance tests need
+// under 2^-20.6 and the r^2 tests under 2^-18.3 relative; the bands are
+// 64 ulps (at least 2^-18) and 1024 ulps (at least 2^-14).
+// A lane with a value inside a band, every lane at a node whose offsets may
+// need the minimum image (kWWrap, which includes the two top levels of a
+// periodic box), and every lane of a box outside the bounds above (theta >
+// 1, a root corner beyond 64 root sides from the origin, periodic without a
+// cutoff) takes the FP64 walk's tests in its own expressions (tests64).
+// List entries are references, a node (monopole) or a leaf's particle
+// range, with the FP64 walk's image flag, and the evaluation forms each FP64
+// offset from the FP64 centre of mass or particle and the target as the
+// FP64 walk does.  Decisions, offsets, pair terms and summation order are
+// those of k_walk64, so the results are the same to the bit.
+
+// Entry: x = node (monopole) or first particle (leaf); y = item count |
+// kELeaf | kEWrap (the offsets take the minimum image).
+constexpr uint32_t kELeaf = 0x80000000u, kEWrap = 0x40000000u;
+constexpr uint32_t kScreenRow = kWalk32Threads * sizeof(uint2);
+constexpr uint32_t kBandC = 64, kBandR = 1024;  // bands, in ulps of the FP32 value
+constexpr int kScreenCap = 4;  // list entries per lane
+
+// |bits(v) - bits(t)| < band for non-negative v and positive t, given
+// lo = bits(t) - band: one unsigned comparison
+__device__ inline bool in_band(float v, uint32_t lo, uint32_t band) { return __float_as_uint(v) - lo < 2u * band; }
+
+// The FP64 walk's tests of a node (cube centre and side cs, moments mm) for a
+// target at xi, in its expressions: the cutoff prune, the opening criterion
+// and the cutoff test of the monopole.
+__device__ inline void tests64(const double4 &cs, const Mom64 &mm, const double4 &xi, bool wrap, const BoxDev &bx,
+                               bool &pruned, bool &open, bool &within) {
+#pragma clang fp contract(off)
+  const double side = cs.w, box = bx.box;
+  double dcx = cs.x - xi.x, dcy = cs.y - xi.y, dcz = cs.z - xi.z;
+  minimg3(dcx, dcy, dcz, wrap, box);
+  pruned = false;
+  if (bx.cutoff) {
+    const double reach = bx.rcut + 0.5 * side;
+    pruned = fabs(dcx) > reach || fabs(dcy) > reach || fabs(dcz) > reach;
+  }
+  double dx = mm.cx - xi.x, dy = mm.cy - xi.y, dz = mm.cz - xi.z;
+  minimg3(dx, dy, dz, wrap, box);
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double near = 0.6 * side;
+  open = (side * side > bx.theta2 * r2) || (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
+  within = !bx.cutoff || r2 < bx.rc2;
+}
+
+// kMode as for k_walk32; kTail as for k_walk64; kCap: list entries per lane.
+// Six waves per SIMD (at most 80 vector registers, no scratch); the
+// instance with the library erfc tail takes four (128 registers, a few
+// values in scratch, like the FP64 walk's instance with the tail).
+template <int kMode, bool kTail, int kCap>
+__global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kTail ? 4 : 6, 8))) void k_walk64s(WalkArgs A) {
+#pragma clang fp contract(fast)
+  __shared__ uint2 list[kCap][kWalk32Threads];
+  __shared__ double4 slots[kWalk32Threads];
+  const uint32_t lane = threadIdx.x;
+  device_counts(A);
+  GroupQueue Q = make_queue(A);
+  while (true) {
+    const uint32_t g = pop_group(Q, lane);
+    if (g >= A.n_groups) break;
+    const GroupRef gr = group_of(A, g);
+    const BoxDev bx = ld(A.boxes + gr.box);
+    const bool kCut = kMode == 0 ? bx.cutoff != 0 : kMode != 3;
+    const bool kPer = kMode == 0 ? bx.periodic != 0 : kMode == 2;
+    uint32_t p = 0, slot = 0;
+    const bool valid = lane_target(A, gr, bx, lane, p, slot);
+    double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (valid) xi = A.part64[p];
+    // the FP64 walk's interior groups (no minimum image below level 1)
+    bool interior = false;
+    if (kPer) {
+      const double box = bx.box, m = bx.rcut + 0x1p-40 * box;
+      const bool inside = !valid || (xi.x >= m && xi.x <= box - m && xi.y >= m && xi.y <= box - m &&
+                                     xi.z >= m && xi.z <= box - m);
+      interior = bx.rcut <= 0.24 * box && __ballot(!inside) == 0;
+    }
+    // lane origin (the centre of the target's level-21 cell, in half-cells)
+    // and the target's FP32 offset from it, as in the mixed walk
+    int o0 = 0, o1 = 0, o2 = 0;
+    float xr = 0.0f, yr = 0.0f, zr = 0.0f;
+    if (valid) {
+      uint32_t cc[3];
+      key_cell(A.skeys[p], bx.curve, cc);
+      o0 = 2 * (int)cc[0] + 1;
+      o1 = 2 * (int)cc[1] + 1;
+      o2 = 2 * (int)cc[2] + 1;
+      const double h22 = bx.L * 0x1p-22;
+      xr = (float)(xi.x - (bx.lo[0] + (double)o0 * h22));
+      yr = (float)(xi.y - (bx.lo[1] + (double)o1 * h22));
+      zr = (float)(xi.z - (bx.lo[2] + (double)o2 * h22));
+    }
+    const float h22f = bx.h22f, rc2f = bx.rc2f;
+    const double lim = 64.0 * bx.L;
+    const bool screened = bx.theta2 <= 1.0 && fabs(bx.lo[0]) <= lim && fabs(bx.lo[1]) <= lim &&
+                          fabs(bx.lo[2]) <= lim && (!kPer || kCut);
+    // a target farther than its cell from the cell's centre (not one inside
+    // the root cube) is not screened either
+    const bool lane_exact = !screened || fmaxf(fmaxf(fabsf(xr), fabsf(yr)), fabsf(zr)) > 1.5f * h22f;
+    const int g0 = __builtin_amdgcn_readfirstlane(o0), g1 = __builtin_amdgcn_readfirstlane(o1),
+              g2 = __builtin_amdgcn_readfirstlane(o2);
+    constexpr int kHalf = 1 << 21, kMask = (1 << 22) - 1;
+    const int gq0 = g0 - kHalf, gq1 = g1 - kHalf, gq2 = g2 - kHalf;
+    const int q0 = o0 - gq0, q1 = o1 - gq1, q2 = o2 - gq2;
+    bool lane_wrap = false;
+    if (kPer) {
+      const float rc = sqrtf(rc2f);
+      const int e = valid ? max(abs(o0 - g0), max(abs(o1 - g1), abs(o2 - g2))) : 0;
+      lane_wrap = !((float)wave_max_i32(e) + rc / h22f < (float)((1 << 20) - (1 << 16)));
+    }
+    // the FP64 walk's image flag below level 1
+    const uint32_t gwrap = kPer && !interior ? kEWrap : 0u;
+    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+    // cnt: byte offset of this lane's next free list slot
+    uint32_t ni = 0, cnt = lane * (uint32_t)sizeof(uint2);
+    const uint32_t cfull = cnt + kCap * kScreenRow;
+    const uint32_t nend = bx.node_end;
+    uint32_t next = valid ? bx.root : nend;
+    auto flush = [&]() {
+      const uint32_t nent = (cnt - lane * (uint32_t)sizeof(uint2)) / kScreenRow;
+      flush_rows64<kCap>(
+          slots, lane, p, nent,
+          [&](uint32_t e) {
+            const uint32_t y = list[e][lane].y;
+            return (y & kELeaf) ? (y & kCountMask) : 1u;
+          },
+          [&](uint32_t l, uint32_t e, uint32_t j, uint32_t po, double4 &t) {
+#pragma clang fp contract(off)
+            const uint2 q = list[e][l];
+            const double4 xo = A.part64[po];
+            double dx, dy, dz, m;
+            bool use = true;
+            if (q.y & kELeaf) {
+              const uint32_t i = q.x + j;
+              use = i != po;
+              const double4 sp = A.part64[i];
+              dx = sp.x - xo.x;
+              dy = sp.y - xo.y;
+              dz = sp.z - xo.z;
+              m = sp.w;
+            } else {
+              const Mom64 mm = A.mom64[q.x];
+              dx = mm.cx - xo.x;
+              dy = mm.cy - xo.y;
+              dz = mm.cz - xo.z;
+              m = mm.m;
+            }
+            minimg3(dx, dy, dz, (q.y & kEWrap) != 0, bx.box);
+            return use && pair64_terms<false, kTail>(dx, dy, dz, m, bx.eps, bx, t);
+          },
+          ax, ay, az, ph, ni);
+      cnt = lane * (uint32_t)sizeof(uint2);
+    };
+    // kForm as in the mixed walk: 0 = c - o as it is (open boxes, the FP64
+    // walk's interior groups), 1 = reduced against the first lane, 2 = the
+    // minimum image per lane
+    auto walk = [&](auto form_t) {
+      constexpr int kForm = decltype(form_t)::value;
+      const float qb0 = biased(kForm == 1 ? q0 : o0), qb1 = biased(kForm == 1 ? q1 : o1),
+                  qb2 = biased(kForm == 1 ? q2 : o2);
+      for (uint32_t n = bx.root; n < nend;) {
+        const WNode w = ldw((const WNode *)((const char *)A.wnode + n * (uint32_t)sizeof(WNode)));
+        if (__ballot(cnt >= cfull)) flush();
+        float f0, f1, f2;
+        if (kPer && kForm == 1) {
+          f0 = biased((w.c[0] - gq0) & kMask) - qb0;
+          f1 = biased((w.c[1] - gq1) & kMask) - qb1;
+          f2 = biased((w.c[2] - gq2) & kMask) - qb2;
+        } else if (kPer && kForm == 2) {
+          f0 = (float)wrap_cells((w.c[0] & kMask) - o0);
+          f1 = (float)wrap_cells((w.c[1] & kMask) - o1);
+          f2 = (float)wrap_cells((w.c[2] & kMask) - o2);
+        } else {
+          f0 = __int_as_float(w.c[0]) - qb0;
+          f1 = __int_as_float(w.c[1]) - qb1;
+          f2 = __int_as_float(w.c[2]) - qb2;
+        }
+        const float dcx = f0 * h22f - xr, dcy = f1 * h22f - yr, dcz = f2 * h22f - zr;
+        const float mdc = fmaxf(fmaxf(fabsf(dcx), fabsf(dcy)), fabsf(dcz));
+        const uint32_t cf = w.cf;
+        const bool leaf = (cf & kWLeaf) != 0;
+        const uint32_t ns = leaf ? n + 1 : w.a;
+        const bool act = next <= n;
+        const bool amb_w = lane_exact || (kPer && (cf & kWWrap) != 0);
+        const bool amb_c = amb_w || (kCut && in_band(mdc, __float_as_uint(w.reach) - kBandC, kBandC));
+        // every active lane certainly prunes n: the wave skips its subtree
+        if (kCut && !__ballot(act && (amb_c || !(mdc > w.reach)))) {
+          n = max(ns, n + 1);
+          continue;
+        }
+        const float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
+        const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
+        bool live = act && !(kCut && mdc > w.reach);
+        bool open = w.side2 > r2 || mdc < w.near;
+        bool within = !kCut || r2 < rc2f;
+        const bool amb = amb_c || in_band(mdc, __float_as_uint(w.near) - kBandC, kBandC) ||
+                         in_band(r2, __float_as_uint(w.side2) - kBandR, kBandR) ||
+                         (kCut && in_band(r2, __float_as_uint(rc2f) - kBandR, kBandR));
+        uint32_t ewrap = gwrap;
+        if (__ballot(act && amb)) {
+          const Topo t = ld(A.topo + n);
+          const double4 cs = ld(A.cen64 + n);
+          const Mom64 mm = ld(A.mom64 + n);
+          if (act && amb) {
+            const bool wrap = kPer && !(interior && (int)(t.b >> kCountBits) >= 2);
+            bool pruned;
+            tests64(cs, mm, xi, wrap, bx, pruned, open, within);
+            live = !pruned;
+            ewrap = wrap ? kEWrap : 0u;
+          }
+        }
+        const bool open_here = live && open;
+        const bool take = live && (open ? leaf : within);
+        // every lane writes its next slot; only a real entry advances it
+        *reinterpret_cast<uint2 *>(reinterpret_cast<char *>(list) + cnt) =
+            open_here ? make_uint2(w.a & kTagFirst, (cf & kWCount) | kELeaf | ewrap) : make_uint2(n, 1u | ewrap);
+        cnt += take ? kScreenRow : 0u;
+        next = open_here ? next : max(next, ns);
+        n = __ballot(next <= n) ? n + 1 : max(ns, n + 1);
+      }
+    };
+    if (kPer && !interior && lane_wrap) walk(std::integral_constant<int, 2>{});
+    else if (kPer && !interior) walk(std::integral_constant<int, 1>{});
+    else walk(std::integral_constant<int, 0>{});
+    flush();
+    if (valid) write_out(A, bx, slot, ax, ay, az, ph, ni);
+  }
+}
+
 // ------------------------------------------- group-shared interaction lists --
 // One walk per group of targets (the paper's grouped neighbour search
 // applied to the tree walk): at a visited node every lane applies the
@@ -1474,7 +1732,13 @@ void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
     }
     return;
   }
-  if (precision == 0) {
+  if (precision == 0 && !W.ext && !W.wide_nodes && !wide_nodes_forced() && !env_flag("OG_WALK64_PLAIN")) {
+    // screened FP64 walk: one wave per workgroup, 6 waves per SIMD
+    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(24u * cus, groups));
+    if (W.erfc_tail) k_walk64s<0, true, kScreenCap><<<blocks, kWalk32Threads, 0, s>>>(W);
+    else if (W.box_kind == 2) k_walk64s<2, false, kScreenCap><<<blocks, kWalk32Threads, 0, s>>>(W);
+    else k_walk64s<0, false, kScreenCap><<<blocks, kWalk32Threads, 0, s>>>(W);
+  } else if (precision == 0) {
     // 4 waves per workgroup, 4 waves per SIMD
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(4u * cus, (groups + 3) / 4));
     if (W.ext && W.erfc_tail) k_walk64<true, true><<<blocks, 64 * kWalk64Waves, 0, s>>>(W);
