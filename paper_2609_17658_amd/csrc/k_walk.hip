@@ -416,6 +416,7 @@ __device__ inline uint32_t lane_rank(uint64_t mask) {
 // the number of items of this lane's entry e (e < nent), and
 // term(l, e, j, po, t) computes the terms t of item j of lane l's entry e
 // for target po and says whether the pair contributes.
+constexpr uint32_t kOwnerRows = 48;  // lanes with an item from which a row is evaluated in place
 template <int kCap, class Items, class Term>
 __device__ inline void flush_rows64(double4 *slots, uint32_t lane, uint32_t p, uint32_t nent, Items items, Term term,
                                     double &ax, double &ay, double &az, double &ph, uint32_t &ni) {
@@ -430,7 +431,30 @@ __device__ inline void flush_rows64(double4 *slots, uint32_t lane, uint32_t p, u
   }
   uint32_t ce = 0, cj = 0;  // entry and particle of this lane's next item
   uint32_t k = 0;           // next row (wave-uniform)
+  // Rows that nearly every lane takes part in are evaluated by their owners
+  // in place (no slots): the same terms, added in the same order.
   uint64_t row = __ballot(P > 0);
+  while ((uint32_t)__popcll(row) >= kOwnerRows) {
+    if (P > k) {
+      double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (term(lane, ce, cj, p, t)) {
+        ax += t.x;
+        ay += t.y;
+        az += t.z;
+        ph -= t.w;
+        ++ni;
+      }
+      uint32_t n = sz[0];
+#pragma unroll
+      for (int e = 1; e < kCap; ++e) n = ce == (uint32_t)e ? sz[e] : n;
+      ++cj;
+      const bool next_entry = cj == n;
+      ce += next_entry ? 1u : 0u;
+      cj = next_entry ? 0u : cj;
+    }
+    ++k;
+    row = __ballot(P > k);
+  }
   while (row) {
     // fill the step with whole rows k, k + 1, ... while they fit
     const uint32_t k0 = k;
@@ -442,7 +466,7 @@ __device__ inline void flush_rows64(double4 *slots, uint32_t lane, uint32_t p, u
         const uint32_t at = f + lane_rank(row);
         *reinterpret_cast<uint4 *>(slots + at) = make_uint4(lane | (ce << 8), cj, p, 0u);
         uint32_t n = sz[0];
-#pragma unroll
+  #pragma unroll
         for (int e = 1; e < kCap; ++e) n = ce == (uint32_t)e ? sz[e] : n;
         ++cj;
         const bool next_entry = cj == n;
@@ -493,8 +517,8 @@ __device__ inline void flush64(const WalkArgs &A, double4 (*list)[64], double (*
                                double &ay, double &az, double &ph, uint32_t &ni) {
   constexpr int kCap = walk64_cap<kExt>();
   flush_rows64<kCap>(
-      slots, lane, p, cnt, [&](uint32_t e) { return entry_items64(list[e][lane]); },
-      [&](uint32_t l, uint32_t e, uint32_t j, uint32_t po, double4 &t) {
+      slots, lane, p, cnt, [&](uint32_t e) __attribute__((always_inline)) { return entry_items64(list[e][lane]); },
+      [&](uint32_t l, uint32_t e, uint32_t j, uint32_t po, double4 &t) __attribute__((always_inline)) {
 #pragma clang fp contract(off)
         const double4 q = list[e][l];
         double dx = q.x, dy = q.y, dz = q.z, m = q.w, es = bx.eps;
@@ -1239,15 +1263,15 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
     const uint32_t cfull = cnt + kCap * kScreenRow;
     const uint32_t nend = bx.node_end;
     uint32_t next = valid ? bx.root : nend;
-    auto flush = [&]() {
+    auto flush = [&]() __attribute__((always_inline)) {
       const uint32_t nent = (cnt - lane * (uint32_t)sizeof(uint2)) / kScreenRow;
       flush_rows64<kCap>(
           slots, lane, p, nent,
-          [&](uint32_t e) {
+          [&](uint32_t e) __attribute__((always_inline)) {
             const uint32_t y = list[e][lane].y;
             return (y & kELeaf) ? (y & kCountMask) : 1u;
           },
-          [&](uint32_t l, uint32_t e, uint32_t j, uint32_t po, double4 &t) {
+          [&](uint32_t l, uint32_t e, uint32_t j, uint32_t po, double4 &t) __attribute__((always_inline)) {
 #pragma clang fp contract(off)
             const uint2 q = list[e][l];
             const double4 xo = A.part64[po];
@@ -1582,7 +1606,7 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
         }
       };
       // every lane evaluates every entry for its own target, in list order
-      auto flush = [&]() {
+      auto flush = [&]() __attribute__((always_inline)) {
         __syncthreads();
         for (uint32_t e = 0; e < cnt; ++e) {
           const GEntry q = list[e];
