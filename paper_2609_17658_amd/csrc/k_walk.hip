@@ -1191,12 +1191,15 @@ __device__ inline void tests64(const double4 &cs, const Mom64 &mm, const double4
   within = !bx.cutoff || r2 < bx.rc2;
 }
 
-// kMode as for k_walk32; kTail as for k_walk64; kCap: list entries per lane.
-// Six waves per SIMD (at most 80 vector registers, no scratch); the
-// instance with the library erfc tail takes four (128 registers, a few
-// values in scratch, like the FP64 walk's instance with the tail).
-template <int kMode, bool kTail, int kCap>
-__global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kTail ? 4 : 6, 8))) void k_walk64s(WalkArgs A) {
+// kMode as for k_walk32; kTail as for k_walk64; kCap: list entries per lane;
+// kExt: the softening kernel is read from each box (spline boxes; the node
+// tests do not depend on it).
+// Six waves per SIMD (at most 80 vector registers, no scratch); the spline
+// instance takes five (96, a few bytes of scratch) and the instances with
+// the library erfc tail four (128, a few values in scratch, like the FP64
+// walk's instances with the tail).
+template <int kMode, bool kTail, int kCap, bool kExt = false>
+__global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kTail ? 4 : (kExt ? 5 : 6), 8))) void k_walk64s(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ uint2 list[kCap][kWalk32Threads];
   __shared__ double4 slots[kWalk32Threads];
@@ -1293,7 +1296,7 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
               m = mm.m;
             }
             minimg3(dx, dy, dz, (q.y & kEWrap) != 0, bx.box);
-            return use && pair64_terms<false, kTail>(dx, dy, dz, m, bx.eps, bx, t);
+            return use && pair64_terms<kExt, kTail>(dx, dy, dz, m, bx.eps, bx, t);
           },
           ax, ay, az, ph, ni);
       cnt = lane * (uint32_t)sizeof(uint2);
@@ -1756,10 +1759,13 @@ void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
     }
     return;
   }
-  if (precision == 0 && !W.ext && !W.wide_nodes && !wide_nodes_forced() && !env_flag("OG_WALK64_PLAIN")) {
+  if (precision == 0 && !W.relative && !W.seps && !W.wide_nodes && !wide_nodes_forced() &&
+      !env_flag("OG_WALK64_PLAIN")) {
     // screened FP64 walk: one wave per workgroup, 6 waves per SIMD
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(24u * cus, groups));
-    if (W.erfc_tail) k_walk64s<0, true, kScreenCap><<<blocks, kWalk32Threads, 0, s>>>(W);
+    if (W.ext && W.erfc_tail) k_walk64s<0, true, kScreenCap, true><<<blocks, kWalk32Threads, 0, s>>>(W);
+    else if (W.ext) k_walk64s<0, false, kScreenCap, true><<<blocks, kWalk32Threads, 0, s>>>(W);
+    else if (W.erfc_tail) k_walk64s<0, true, kScreenCap><<<blocks, kWalk32Threads, 0, s>>>(W);
     else if (W.box_kind == 2) k_walk64s<2, false, kScreenCap><<<blocks, kWalk32Threads, 0, s>>>(W);
     else k_walk64s<0, false, kScreenCap><<<blocks, kWalk32Threads, 0, s>>>(W);
   } else if (precision == 0) {

@@ -7,8 +7,9 @@ cases cover the kernel's branches: periodic groups that take no minimum
 image below level 1 and groups that do (per-group reduction and per-lane
 images), open boundaries with a cutoff and without one, boxes the screen
 does not cover (theta > 1, a root cube far from the origin), the library
-erfc tail, big and coincident leaves, trees of a few particles, Hilbert keys,
-target lists and a batch of boxes.  Parity with the oracle is covered by the
+erfc tail, spline softening, big and coincident leaves, trees of a few
+particles, Hilbert keys, target lists and batches of boxes (one with a spline
+box among Plummer boxes).  Parity with the oracle is covered by the
 FP64 parity tests, which run this walk by default."""
 import sys
 
@@ -87,6 +88,9 @@ def _cases():
     pos[600:900] = 0.25
     out.append(("coincident7000_lm32", pos, np.full(n, 1.0 / n), 1.0,
                 dict(synth.scale_free_params(n, leaf_max=32).as_dict())))
+    # spline softening (read from the box; the node tests do not depend on it)
+    out.append(("mixture32k_spline", w.pos, w.mass, 1.0, dict(base, softening=1)))
+    out.append(("clustered8000_tail_spline", out[7][1], out[7][2], 1.0, dict(out[7][4], softening=1)))
     # a few particles: leaves at the top two levels
     for n in (2, 5, 17, 70):
         pos = synth.wrap(rng.random((n, 3)))
@@ -121,16 +125,24 @@ def test_screened_target_list_equals_plain(og_mod, monkeypatch):
         assert np.array_equal(x, y)
 
 
-def test_screened_batch_equals_plain(og_mod, monkeypatch):
+def _batch_items(spline):
     rng = np.random.default_rng(11)
     items = []
     for i, n in enumerate((3000, 9000, 1500)):
         pos = synth.wrap(rng.random((n, 3)))
         prm = synth.scale_free_params(n, theta=0.4 + 0.2 * i).as_dict()
+        if spline and i == 1:
+            prm["softening"] = 1  # one spline box among Plummer boxes
         items.append((_dev(pos), _dev(np.full(n, 1.0 / n)), 1.0, prm))
     pos = rng.random((2500, 3)) * 3.0
     items.append((_dev(pos), _dev(np.full(2500, 1 / 2500)), 1.0,
                   dict(G=1.0, eps=0.01, r_s=0.1, r_cut=0.45, theta=0.5, periodic=0, leaf_max=8)))
+    return items
+
+
+@pytest.mark.parametrize("spline", [False, True], ids=["plummer", "with_spline_box"])
+def test_screened_batch_equals_plain(og_mod, monkeypatch, spline):
+    items = _batch_items(spline)
     _note("screened vs plain FP64 walk: batch of %d boxes" % len(items))
 
     def run():
