@@ -1145,7 +1145,7 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
 // r^2 is within 2^-18.5 r^2 of the FP64 value near either r^2 threshold
 // when theta <= 1 (there |offset| <= 1.5 r and h <= r/2).  With the
 // thresholds' own FP32 rounding (at most 5 x 2^-24) the distance tests need
-// under 2^-20.6 and the r^2 tests under 2^-18.3 relative; the bands are
+// under 2^-20.4 and the r^2 tests under 2^-18.3 relative; the bands are
 // 64 ulps (at least 2^-18) and 1024 ulps (at least 2^-14).
 // A lane with a value inside a band, every lane at a node whose offsets may
 // need the minimum image (kWWrap, which includes the two top levels of a
