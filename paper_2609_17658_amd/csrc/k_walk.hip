@@ -1146,12 +1146,20 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
 // when theta <= 1 (there |offset| <= 1.5 r and h <= r/2).  With the
 // thresholds' own FP32 rounding (at most 5 x 2^-24) the distance tests need
 // under 2^-20.4 and the r^2 tests under 2^-18.3 relative; the bands are
-// 64 ulps (at least 2^-18) and 1024 ulps (at least 2^-14).
+// 64 ulps (at least 2^-18) and 1024 ulps (at least 2^-14).  The relative
+// criterion, G M side^2 > alpha |a_old| r^4, has no theta to bound r by the
+// side; but where the near test is certainly false the centre of mass is at
+// least 0.1 side from the target (it lies within side/2 of the centre on the
+// axis where |dc| >= 0.6 side), so r^2 is within 2^-16.3 r^2 and the
+// comparison within 2^-15.2 of its FP64 value; its band is 4096 ulps (at
+// least 2^-12).  Where the near test is certainly true the node is opened
+// whatever the criterion says.
 // A lane with a value inside a band, every lane at a node whose offsets may
 // need the minimum image (kWWrap, which includes the two top levels of a
 // periodic box), and every lane of a box outside the bounds above (theta >
-// 1, a root corner beyond 64 root sides from the origin, periodic without a
-// cutoff) takes the FP64 walk's tests in its own expressions (tests64).
+// 1 with the geometric criterion, a root corner beyond 64 root sides from
+// the origin, periodic without a cutoff) takes the FP64 walk's tests in its
+// own expressions (tests64).
 // List entries are references, a node (monopole) or a leaf's particle
 // range, with the FP64 walk's image flag, and the evaluation forms each FP64
 // offset from the FP64 centre of mass or particle and the target as the
@@ -1162,18 +1170,25 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
 // kELeaf | kEWrap (the offsets take the minimum image).
 constexpr uint32_t kELeaf = 0x80000000u, kEWrap = 0x40000000u;
 constexpr uint32_t kScreenRow = kWalk32Threads * sizeof(uint2);
-constexpr uint32_t kBandC = 64, kBandR = 1024;  // bands, in ulps of the FP32 value
+constexpr uint32_t kBandC = 64, kBandR = 1024, kBandRel = 4096;  // bands, in ulps of the FP32 value
 constexpr int kScreenCap = 4;  // list entries per lane
 
 // |bits(v) - bits(t)| < band for non-negative v and positive t, given
 // lo = bits(t) - band: one unsigned comparison
 __device__ inline bool in_band(float v, uint32_t lo, uint32_t band) { return __float_as_uint(v) - lo < 2u * band; }
 
+// |a_old| of a target, in the FP64 walk's expression.
+__device__ inline double norm3_64(const double *v) {
+#pragma clang fp contract(off)
+  return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+}
+
 // The FP64 walk's tests of a node (cube centre and side cs, moments mm) for a
 // target at xi, in its expressions: the cutoff prune, the opening criterion
-// and the cutoff test of the monopole.
+// (geometric, or relative with the target's |a_old| aold) and the cutoff
+// test of the monopole.
 __device__ inline void tests64(const double4 &cs, const Mom64 &mm, const double4 &xi, bool wrap, const BoxDev &bx,
-                               bool &pruned, bool &open, bool &within) {
+                               bool relative, double aold, bool &pruned, bool &open, bool &within) {
 #pragma clang fp contract(off)
   const double side = cs.w, box = bx.box;
   double dcx = cs.x - xi.x, dcy = cs.y - xi.y, dcz = cs.z - xi.z;
@@ -1187,13 +1202,14 @@ __device__ inline void tests64(const double4 &cs, const Mom64 &mm, const double4
   minimg3(dx, dy, dz, wrap, box);
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double near = 0.6 * side;
-  open = (side * side > bx.theta2 * r2) || (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
+  const bool far_open = relative ? (bx.G * mm.m * side * side > bx.alpha * aold * r2 * r2) : (side * side > bx.theta2 * r2);
+  open = far_open || (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
   within = !bx.cutoff || r2 < bx.rc2;
 }
 
 // kMode as for k_walk32; kTail as for k_walk64; kCap: list entries per lane;
-// kExt: the softening kernel is read from each box (spline boxes; the node
-// tests do not depend on it).
+// kExt: the softening kernel and the opening criterion are read from each box
+// (spline and relative-criterion boxes).
 // Six waves per SIMD (at most 80 vector registers, no scratch); the spline
 // instance takes five (96, a few bytes of scratch) and the instances with
 // the library erfc tail four (128, a few values in scratch, like the FP64
@@ -1241,8 +1257,17 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
       zr = (float)(xi.z - (bx.lo[2] + (double)o2 * h22));
     }
     const float h22f = bx.h22f, rc2f = bx.rc2f;
+    // the relative criterion: the target's |a_old| (FP64, and alpha |a_old|
+    // in FP32 for the screen; the record's mass is G M, its side2 side^2)
+    const bool relative = kExt && bx.relative;
+    double aold = 0.0;
+    float aol = 0.0f;
+    if (relative && valid) {
+      aold = norm3_64(A.a_old + 3ull * (A.perm[p] - bx.p_off));
+      aol = (float)(bx.alpha * aold);
+    }
     const double lim = 64.0 * bx.L;
-    const bool screened = bx.theta2 <= 1.0 && fabs(bx.lo[0]) <= lim && fabs(bx.lo[1]) <= lim &&
+    const bool screened = (relative || bx.theta2 <= 1.0) && fabs(bx.lo[0]) <= lim && fabs(bx.lo[1]) <= lim &&
                           fabs(bx.lo[2]) <= lim && (!kPer || kCut);
     // a target farther than its cell from the cell's centre (not one inside
     // the root cube) is not screened either
@@ -1341,10 +1366,12 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
         const float dx = dcx + w.o[0], dy = dcy + w.o[1], dz = dcz + w.o[2];
         const float r2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
         bool live = act && !(kCut && mdc > w.reach);
-        bool open = w.side2 > r2 || mdc < w.near;
+        const float gms2 = w.m * w.side2, ar4 = aol * (r2 * r2);  // relative: G M side^2, alpha |a_old| r^4
+        bool open = (relative ? gms2 > ar4 : w.side2 > r2) || mdc < w.near;
         bool within = !kCut || r2 < rc2f;
         const bool amb = amb_c || in_band(mdc, __float_as_uint(w.near) - kBandC, kBandC) ||
-                         in_band(r2, __float_as_uint(w.side2) - kBandR, kBandR) ||
+                         (relative ? in_band(ar4, __float_as_uint(gms2) - kBandRel, kBandRel)
+                                   : in_band(r2, __float_as_uint(w.side2) - kBandR, kBandR)) ||
                          (kCut && in_band(r2, __float_as_uint(rc2f) - kBandR, kBandR));
         uint32_t ewrap = gwrap;
         if (__ballot(act && amb)) {
@@ -1354,7 +1381,7 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
           if (act && amb) {
             const bool wrap = kPer && !(interior && (int)(t.b >> kCountBits) >= 2);
             bool pruned;
-            tests64(cs, mm, xi, wrap, bx, pruned, open, within);
+            tests64(cs, mm, xi, wrap, bx, relative, aold, pruned, open, within);
             live = !pruned;
             ewrap = wrap ? kEWrap : 0u;
           }
@@ -1759,8 +1786,7 @@ void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
     }
     return;
   }
-  if (precision == 0 && !W.relative && !W.seps && !W.wide_nodes && !wide_nodes_forced() &&
-      !env_flag("OG_WALK64_PLAIN")) {
+  if (precision == 0 && !W.seps && !W.wide_nodes && !wide_nodes_forced() && !env_flag("OG_WALK64_PLAIN")) {
     // screened FP64 walk: one wave per workgroup, 6 waves per SIMD
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(24u * cus, groups));
     if (W.ext && W.erfc_tail) k_walk64s<0, true, kScreenCap, true><<<blocks, kWalk32Threads, 0, s>>>(W);

@@ -318,7 +318,6 @@ WalkArgs Forest::walk_args() const {
   for (const auto &b : hboxes) {
     if (kind(b) != W.box_kind) W.box_kind = 0;
     if (b.spline || b.relative) W.ext = 1;
-    if (b.relative) W.relative = 1;
   }
   W.counter = &A.scalars[8];
   W.group_lists = group_lists;

@@ -131,7 +131,6 @@ struct WalkArgs {
   int64_t *nint;
   int pot_override;           // 1: use `pot` (possibly null) instead of the box's
   int ext;                    // some box uses spline softening or the relative criterion
-  int relative;               // some box uses the relative criterion
   const uint32_t *dev_count;  // non-null: n_targets = [0], n_groups = [1], read on the device
   const double *seps, *semax, *semin;  // per-particle softening (null: the boxes' eps)
   int group_lists;            // 1: group-shared interaction lists, 0: per-target walk

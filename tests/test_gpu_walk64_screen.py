@@ -7,7 +7,8 @@ cases cover the kernel's branches: periodic groups that take no minimum
 image below level 1 and groups that do (per-group reduction and per-lane
 images), open boundaries with a cutoff and without one, boxes the screen
 does not cover (theta > 1, a root cube far from the origin), the library
-erfc tail, spline softening, big and coincident leaves, trees of a few
+erfc tail, spline softening, the relative criterion, big and coincident
+leaves, trees of a few
 particles, Hilbert keys, target lists and batches of boxes (one with a spline
 box among Plummer boxes).  Parity with the oracle is covered by the
 FP64 parity tests, which run this walk by default."""
@@ -44,7 +45,12 @@ def _dev(a, dtype=torch.float64):
 def _fp64(og, pos, mass, box, prm, targets=None):
     tree = og.Tree(_dev(pos), _dev(mass), box, prm, stream=torch.cuda.current_stream())
     tg = None if targets is None else _dev(targets, torch.int64)
-    acc, pot, nint = tree.force(targets=tg, precision="fp64", with_counts=True)
+    a_old = None
+    if prm.get("criterion", 0) == 1:
+        # previous accelerations of a spread of magnitudes (both walks get the same)
+        rng = np.random.default_rng(5)
+        a_old = _dev(rng.standard_normal((pos.shape[0], 3)) * np.exp(rng.uniform(-3.0, 3.0, (pos.shape[0], 1))))
+    acc, pot, nint = tree.force(targets=tg, precision="fp64", with_counts=True, a_old=a_old)
     torch.cuda.synchronize()
     out = acc.cpu().numpy(), pot.cpu().numpy(), nint.cpu().numpy()
     assert tree.status() == 0
@@ -91,6 +97,13 @@ def _cases():
     # spline softening (read from the box; the node tests do not depend on it)
     out.append(("mixture32k_spline", w.pos, w.mass, 1.0, dict(base, softening=1)))
     out.append(("clustered8000_tail_spline", out[7][1], out[7][2], 1.0, dict(out[7][4], softening=1)))
+    # the relative criterion (with theta above 1 too: it is not used), alone
+    # and with spline softening, periodic and open
+    rel = dict(criterion=1, alpha=0.002)
+    out.append(("mixture32k_relative", w.pos, w.mass, 1.0, dict(base, **rel)))
+    out.append(("mixture32k_relative_theta1.5", w.pos, w.mass, 1.0, dict(base, theta=1.5, **rel)))
+    out.append(("mixture32k_spline_relative", w.pos, w.mass, 1.0, dict(base, softening=1, **rel)))
+    out.append(("open_cut5000_relative", out[8][1], out[8][2], 1.0, dict(out[8][4], criterion=1, alpha=0.01)))
     # a few particles: leaves at the top two levels
     for n in (2, 5, 17, 70):
         pos = synth.wrap(rng.random((n, 3)))
