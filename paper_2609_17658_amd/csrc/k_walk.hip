@@ -1153,7 +1153,10 @@ __attribute__((amdgpu_waves_per_eu(kCap == 4 ? 8 : 1, 8))) void k_walk32(WalkArg
 // axis where |dc| >= 0.6 side), so r^2 is within 2^-16.3 r^2 and the
 // comparison within 2^-15.2 of its FP64 value; its band is 4096 ulps (at
 // least 2^-12).  Where the near test is certainly true the node is opened
-// whatever the criterion says.
+// whatever the criterion says.  With per-particle lengths a node is also
+// opened when r^2 < (2.8 emax)^2 (its lengths differing and its largest
+// above the target's, comparisons made in FP64): the same r^2 bound with a
+// 1024-ulp band.
 // A lane with a value inside a band, every lane at a node whose offsets may
 // need the minimum image (kWWrap, which includes the two top levels of a
 // periodic box), and every lane of a box outside the bounds above (theta >
@@ -1187,8 +1190,11 @@ __device__ inline double norm3_64(const double *v) {
 // target at xi, in its expressions: the cutoff prune, the opening criterion
 // (geometric, or relative with the target's |a_old| aold) and the cutoff
 // test of the monopole.
+// soft: per-particle lengths, with the node's length range (emin, emax) and
+// the target's length ei (the mixed-softening opening test).
 __device__ inline void tests64(const double4 &cs, const Mom64 &mm, const double4 &xi, bool wrap, const BoxDev &bx,
-                               bool relative, double aold, bool &pruned, bool &open, bool &within) {
+                               bool relative, double aold, bool soft, double emin, double emax, double ei,
+                               bool &pruned, bool &open, bool &within) {
 #pragma clang fp contract(off)
   const double side = cs.w, box = bx.box;
   double dcx = cs.x - xi.x, dcy = cs.y - xi.y, dcz = cs.z - xi.z;
@@ -1204,12 +1210,24 @@ __device__ inline void tests64(const double4 &cs, const Mom64 &mm, const double4
   const double near = 0.6 * side;
   const bool far_open = relative ? (bx.G * mm.m * side * side > bx.alpha * aold * r2 * r2) : (side * side > bx.theta2 * r2);
   open = far_open || (fabs(dcx) < near && fabs(dcy) < near && fabs(dcz) < near);
+  if (soft && emin < emax && emax > ei) {
+    const double hm = 2.8 * emax;
+    if (r2 < hm * hm) open = true;
+  }
   within = !bx.cutoff || r2 < bx.rc2;
 }
 
+// (2.8 emax)^2 in the FP64 walk's expression.
+__device__ inline double hm2_64(double emax) {
+#pragma clang fp contract(off)
+  const double hm = 2.8 * emax;
+  return hm * hm;
+}
+
 // kMode as for k_walk32; kTail as for k_walk64; kCap: list entries per lane;
-// kExt: the softening kernel and the opening criterion are read from each box
-// (spline and relative-criterion boxes).
+// kExt: the softening kernel, the opening criterion and per-particle lengths
+// are read from each box (spline, relative-criterion and per-particle-length
+// boxes).
 // Six waves per SIMD (at most 80 vector registers, no scratch); the spline
 // instance takes five (96, a few bytes of scratch) and the instances with
 // the library erfc tail four (128, a few values in scratch, like the FP64
@@ -1266,6 +1284,9 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
       aold = norm3_64(A.a_old + 3ull * (A.perm[p] - bx.p_off));
       aol = (float)(bx.alpha * aold);
     }
+    // per-particle lengths: the target's (FP64, as the FP64 walk reads it)
+    const bool soft = kExt && A.seps != nullptr && bx.epsp != nullptr;
+    const double ei = soft && valid ? A.seps[p] : bx.eps;
     const double lim = 64.0 * bx.L;
     const bool screened = (relative || bx.theta2 <= 1.0) && fabs(bx.lo[0]) <= lim && fabs(bx.lo[1]) <= lim &&
                           fabs(bx.lo[2]) <= lim && (!kPer || kCut);
@@ -1303,7 +1324,7 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
 #pragma clang fp contract(off)
             const uint2 q = list[e][l];
             const double4 xo = A.part64[po];
-            double dx, dy, dz, m;
+            double dx, dy, dz, m, es = bx.eps;
             bool use = true;
             if (q.y & kELeaf) {
               const uint32_t i = q.x + j;
@@ -1313,15 +1334,24 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
               dy = sp.y - xo.y;
               dz = sp.z - xo.z;
               m = sp.w;
+              if (soft) {
+                const double ej = A.seps[i], eo = A.seps[po];
+                es = eo > ej ? eo : ej;
+              }
             } else {
               const Mom64 mm = A.mom64[q.x];
               dx = mm.cx - xo.x;
               dy = mm.cy - xo.y;
               dz = mm.cz - xo.z;
               m = mm.m;
+              if (soft) {
+                // the monopole's length: the larger of the target's and the node's largest
+                const double eo = A.seps[po], emax = A.semax[q.x];
+                es = eo > emax ? eo : emax;
+              }
             }
             minimg3(dx, dy, dz, (q.y & kEWrap) != 0, bx.box);
-            return use && pair64_terms<kExt, kTail>(dx, dy, dz, m, bx.eps, bx, t);
+            return use && pair64_terms<kExt, kTail>(dx, dy, dz, m, es, bx, t);
           },
           ax, ay, az, ph, ni);
       cnt = lane * (uint32_t)sizeof(uint2);
@@ -1369,7 +1399,21 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
         const float gms2 = w.m * w.side2, ar4 = aol * (r2 * r2);  // relative: G M side^2, alpha |a_old| r^4
         bool open = (relative ? gms2 > ar4 : w.side2 > r2) || mdc < w.near;
         bool within = !kCut || r2 < rc2f;
-        const bool amb = amb_c || in_band(mdc, __float_as_uint(w.near) - kBandC, kBandC) ||
+        // per-particle lengths: the node is also opened when its lengths
+        // differ, its largest exceeds the target's and r < 2.8 emax (the
+        // length comparisons are made in FP64, exactly; r^2 is screened)
+        bool amb_s = false;
+        double emin = 0.0, emax = 0.0;
+        if (kExt && soft) {
+          emax = *cptr(A.semax + n);
+          emin = *cptr(A.semin + n);
+          if (emin < emax && emax > ei) {
+            const float hm2 = (float)hm2_64(emax);
+            open = open || r2 < hm2;
+            amb_s = in_band(r2, __float_as_uint(hm2) - kBandR, kBandR);
+          }
+        }
+        const bool amb = amb_c || amb_s || in_band(mdc, __float_as_uint(w.near) - kBandC, kBandC) ||
                          (relative ? in_band(ar4, __float_as_uint(gms2) - kBandRel, kBandRel)
                                    : in_band(r2, __float_as_uint(w.side2) - kBandR, kBandR)) ||
                          (kCut && in_band(r2, __float_as_uint(rc2f) - kBandR, kBandR));
@@ -1381,7 +1425,7 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
           if (act && amb) {
             const bool wrap = kPer && !(interior && (int)(t.b >> kCountBits) >= 2);
             bool pruned;
-            tests64(cs, mm, xi, wrap, bx, relative, aold, pruned, open, within);
+            tests64(cs, mm, xi, wrap, bx, relative, aold, kExt && soft, emin, emax, ei, pruned, open, within);
             live = !pruned;
             ewrap = wrap ? kEWrap : 0u;
           }
@@ -1786,7 +1830,7 @@ void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
     }
     return;
   }
-  if (precision == 0 && !W.seps && !W.wide_nodes && !wide_nodes_forced() && !env_flag("OG_WALK64_PLAIN")) {
+  if (precision == 0 && !W.wide_nodes && !wide_nodes_forced() && !env_flag("OG_WALK64_PLAIN")) {
     // screened FP64 walk: one wave per workgroup, 6 waves per SIMD
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(24u * cus, groups));
     if (W.ext && W.erfc_tail) k_walk64s<0, true, kScreenCap, true><<<blocks, kWalk32Threads, 0, s>>>(W);

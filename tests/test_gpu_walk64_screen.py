@@ -7,8 +7,8 @@ cases cover the kernel's branches: periodic groups that take no minimum
 image below level 1 and groups that do (per-group reduction and per-lane
 images), open boundaries with a cutoff and without one, boxes the screen
 does not cover (theta > 1, a root cube far from the origin), the library
-erfc tail, spline softening, the relative criterion, big and coincident
-leaves, trees of a few
+erfc tail, spline softening, the relative criterion, per-particle
+softening lengths, big and coincident leaves, trees of a few
 particles, Hilbert keys, target lists and batches of boxes (one with a spline
 box among Plummer boxes).  Parity with the oracle is covered by the
 FP64 parity tests, which run this walk by default."""
@@ -43,6 +43,12 @@ def _dev(a, dtype=torch.float64):
 
 
 def _fp64(og, pos, mass, box, prm, targets=None):
+    prm = dict(prm)
+    eps = prm.pop("eps_lengths", None)
+    te = None
+    if eps is not None:  # per-particle softening lengths (kept alive with the tree)
+        te = _dev(eps)
+        prm["eps_particle"] = te
     tree = og.Tree(_dev(pos), _dev(mass), box, prm, stream=torch.cuda.current_stream())
     tg = None if targets is None else _dev(targets, torch.int64)
     a_old = None
@@ -104,6 +110,16 @@ def _cases():
     out.append(("mixture32k_relative_theta1.5", w.pos, w.mass, 1.0, dict(base, theta=1.5, **rel)))
     out.append(("mixture32k_spline_relative", w.pos, w.mass, 1.0, dict(base, softening=1, **rel)))
     out.append(("open_cut5000_relative", out[8][1], out[8][2], 1.0, dict(out[8][4], criterion=1, alpha=0.01)))
+    # per-particle lengths (30 % at five times the box's), with the Plummer
+    # and spline kernels, with the relative criterion, and in an open box
+    lengths = np.full(w.pos.shape[0], base["eps"])
+    lengths[rng.random(w.pos.shape[0]) < 0.3] *= 5.0
+    out.append(("mixture32k_lengths", w.pos, w.mass, 1.0, dict(base, eps_lengths=lengths)))
+    out.append(("mixture32k_lengths_spline", w.pos, w.mass, 1.0, dict(base, softening=1, eps_lengths=lengths)))
+    out.append(("mixture32k_lengths_relative", w.pos, w.mass, 1.0, dict(base, eps_lengths=lengths, **rel)))
+    nl = out[11][1].shape[0]
+    lengths_open = np.where(rng.random(nl) < 0.3, 0.05, 0.01)
+    out.append(("newton3000_lengths", out[11][1], out[11][2], 1.0, dict(out[11][4], eps_lengths=lengths_open)))
     # a few particles: leaves at the top two levels
     for n in (2, 5, 17, 70):
         pos = synth.wrap(rng.random((n, 3)))
