@@ -7,17 +7,20 @@ cases cover the kernel's branches: periodic groups that take no minimum
 image below level 1 and groups that do (per-group reduction and per-lane
 images), open boundaries with a cutoff and without one, boxes the screen
 does not cover (theta > 1, a root cube far from the origin), the library
-erfc tail, spline softening, the relative criterion, per-particle
-softening lengths, big and coincident leaves, trees of a few
-particles, Hilbert keys, target lists and batches of boxes (one with a spline
-box among Plummer boxes).  Parity with the oracle is covered by the
-FP64 parity tests, which run this walk by default."""
+erfc tail, spline softening, the relative criterion, per-particle softening
+lengths, big and coincident leaves, trees of a few particles, Hilbert keys,
+target lists, batches of boxes (one with a spline box among Plummer boxes),
+and 40 generated inputs with coincident points and coordinates on cell faces
+and at the periodic wrap.  Parity with the oracle is covered by the FP64
+parity tests, which run this walk by default."""
 import sys
 
 import numpy as np
 import pytest
+from hypothesis import HealthCheck, given, settings
 
 from paper_2609_17658_amd import synth
+from prop_inputs import configs
 
 pytestmark = pytest.mark.gpu
 
@@ -188,3 +191,20 @@ def test_screened_batch_equals_plain(og_mod, monkeypatch, spline):
     plain = run()
     for (a1, p1), (a2, p2) in zip(screened, plain):
         assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large,
+                                 HealthCheck.function_scoped_fixture])
+@given(cfg=configs())
+def test_screened_equals_plain_on_generated_inputs(og_mod, monkeypatch, cfg):
+    """Coincident points, dyadic coordinates on cell faces (exact ties with
+    node thresholds), coordinates 0 and just below the periodic side, theta 0
+    to 0.8, leaves of 1 to 16, both curves, open and periodic boxes."""
+    _note("screened vs plain FP64 walk: %s" % cfg.label)
+    monkeypatch.delenv("OG_WALK64_PLAIN", raising=False)
+    screened = _fp64(og_mod, cfg.pos, cfg.mass, cfg.box, cfg.params)
+    monkeypatch.setenv("OG_WALK64_PLAIN", "1")
+    plain = _fp64(og_mod, cfg.pos, cfg.mass, cfg.box, cfg.params)
+    for x, y in zip(screened, plain):
+        assert np.array_equal(x, y)
