@@ -1228,12 +1228,14 @@ __device__ inline double hm2_64(double emax) {
 // kExt: the softening kernel, the opening criterion and per-particle lengths
 // are read from each box (spline, relative-criterion and per-particle-length
 // boxes).
-// Six waves per SIMD (at most 80 vector registers, no scratch); the spline
-// instance takes five (96, a few bytes of scratch) and the instances with
-// the library erfc tail four (128, a few values in scratch, like the FP64
-// walk's instances with the tail).
+// Seven waves per SIMD (at most 72 vector registers, a few bytes of
+// scratch; the target's FP64 position is reloaded by the lanes that take the
+// FP64 tests instead of being kept across the walk); the instance for the
+// variant boxes takes five (96) and the instances with the library erfc tail
+// four (128, a few values in scratch, like the FP64 walk's instances with
+// the tail).
 template <int kMode, bool kTail, int kCap, bool kExt = false>
-__global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kTail ? 4 : (kExt ? 5 : 6), 8))) void k_walk64s(WalkArgs A) {
+__global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kTail ? 4 : (kExt ? 5 : 7), 8))) void k_walk64s(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ uint2 list[kCap][kWalk32Threads];
   __shared__ double4 slots[kWalk32Threads];
@@ -1425,7 +1427,8 @@ __global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(
           if (act && amb) {
             const bool wrap = kPer && !(interior && (int)(t.b >> kCountBits) >= 2);
             bool pruned;
-            tests64(cs, mm, xi, wrap, bx, relative, aold, kExt && soft, emin, emax, ei, pruned, open, within);
+            const double4 xq = A.part64[p];  // reloaded: not kept in registers across the walk
+            tests64(cs, mm, xq, wrap, bx, relative, aold, kExt && soft, emin, emax, ei, pruned, open, within);
             live = !pruned;
             ewrap = wrap ? kEWrap : 0u;
           }
@@ -1831,8 +1834,8 @@ void launch_walk(const WalkArgs &W0, int precision, hipStream_t s) {
     return;
   }
   if (precision == 0 && !W.wide_nodes && !wide_nodes_forced() && !env_flag("OG_WALK64_PLAIN")) {
-    // screened FP64 walk: one wave per workgroup, 6 waves per SIMD
-    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(24u * cus, groups));
+    // screened FP64 walk: one wave per workgroup, 7 waves per SIMD
+    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(28u * cus, groups));
     if (W.ext && W.erfc_tail) k_walk64s<0, true, kScreenCap, true><<<blocks, kWalk32Threads, 0, s>>>(W);
     else if (W.ext) k_walk64s<0, false, kScreenCap, true><<<blocks, kWalk32Threads, 0, s>>>(W);
     else if (W.erfc_tail) k_walk64s<0, true, kScreenCap><<<blocks, kWalk32Threads, 0, s>>>(W);
