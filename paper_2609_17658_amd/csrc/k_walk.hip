@@ -1231,11 +1231,11 @@ __device__ inline double hm2_64(double emax) {
 // Seven waves per SIMD (at most 72 vector registers, a few bytes of
 // scratch; the target's FP64 position is reloaded by the lanes that take the
 // FP64 tests instead of being kept across the walk); the instance for the
-// variant boxes takes five (96) and the instances with the library erfc tail
-// four (128, a few values in scratch, like the FP64 walk's instances with
-// the tail).
+// variant boxes takes six (80, some scratch: faster than five without) and
+// the instances with the library erfc tail four (128, a few values in
+// scratch, like the FP64 walk's instances with the tail).
 template <int kMode, bool kTail, int kCap, bool kExt = false>
-__global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kTail ? 4 : (kExt ? 5 : 7), 8))) void k_walk64s(WalkArgs A) {
+__global__ __launch_bounds__(kWalk32Threads) __attribute__((amdgpu_waves_per_eu(kTail ? 4 : (kExt ? 6 : 7), 8))) void k_walk64s(WalkArgs A) {
 #pragma clang fp contract(fast)
   __shared__ uint2 list[kCap][kWalk32Threads];
   __shared__ double4 slots[kWalk32Threads];
